@@ -1,0 +1,260 @@
+/*
+ * dmlmc.h -- C ABI of the deflated multigrid multilevel Monte Carlo library (gfx950).
+ *
+ * Computes tr(D^-1) for the 2D Wilson-Schwinger operator D by multigrid multilevel
+ * Monte Carlo with exact deflation of the coarsest term (Frommer & Ramirez-Hidalgo,
+ * "Deflated Multigrid Multilevel Monte Carlo", Lattice 2022: eq. 11 with eqs. 4-7).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status:      every call returns dmlmc_status (0 = OK, < 0 = error) and never throws
+ *              or aborts across the ABI.  dmlmc_last_error() gives the message.
+ * Validation:  arguments are checked on the host before any device work; a rejected
+ *              call returns DMLMC_EINVAL and leaves every output untouched.
+ * Streams:     all device work of a context is enqueued on the context's stream; every
+ *              call returns after that stream is synchronised (results are ready).
+ * Ownership:   the caller owns every buffer it passes.  Host inputs are copied before
+ *              the call returns.  Device buffers (B, X, ...) are caller-allocated, must
+ *              not alias each other, and are only read/written during the call.  The
+ *              library owns contexts, hierarchies and deflations together with their
+ *              device memory; each is released only by its destroy/free call.  A
+ *              hierarchy or deflation belongs to the context that created it.
+ * Threads:     a context is not thread-safe; distinct contexts are independent.
+ * Complex:     interleaved (re, im) pairs: complex128 = 2 doubles, complex64 = 2 floats
+ *              (the layout of numpy/torch complex arrays).
+ * Index:       a vector at level l with lattice Lx_l x Lt_l and d_l dofs per site has
+ *              n_l = Lx_l * Lt_l * d_l entries; entry d_l * (x + Lx_l * t) + dof.
+ *              Fine level: d_1 = 2 spin components.  Coarse level: the first half of a
+ *              site's dofs has chirality +, the second half chirality -.
+ * Blocks of RHS: nrhs vectors stored one after another with leading dimension ld >= n_l
+ *              (vector r starts at element r * ld).
+ * Levels:      1-based, l = 1 is the fine lattice, l = L the coarsest.
+ */
+#ifndef DMLMC_H
+#define DMLMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DMLMC_OK = 0,
+  DMLMC_EINVAL = -1,   /* invalid argument (shape, level, size, null pointer)        */
+  DMLMC_ENOMEM = -2,   /* device or host allocation failed                            */
+  DMLMC_EHIP = -3,     /* a HIP runtime call failed; message holds the HIP error      */
+  DMLMC_ENOCONV = -4,  /* solver stopped at maxiter; outputs hold the best iterate    */
+  DMLMC_ENUMERIC = -5, /* NaN or Inf detected in a residual norm                      */
+  DMLMC_ESTATE = -6    /* object used with a context it does not belong to            */
+} dmlmc_status;
+
+typedef enum { DMLMC_FP64 = 0, DMLMC_MIXED = 1 } dmlmc_precision;
+
+typedef struct dmlmc_ctx dmlmc_ctx;
+typedef struct dmlmc_hier dmlmc_hier;
+typedef struct dmlmc_defl dmlmc_defl;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`.  hip_stream: a hipStream_t to enqueue on,
+ * or NULL for a stream the context creates (default priority) and owns. */
+dmlmc_status dmlmc_create(dmlmc_ctx **out, int device, void *hip_stream);
+void dmlmc_destroy(dmlmc_ctx *ctx);
+/* Message of the last failed call on ctx (or of the last failed dmlmc_create when ctx
+ * is NULL); owned by the library, valid until the next call on ctx. */
+const char *dmlmc_last_error(const dmlmc_ctx *ctx);
+/* Library version string. */
+const char *dmlmc_version(void);
+
+/* ---------------------------------------------------------------- hierarchy
+ * The operator (Sec. 1 and 4.3: the 2D Wilson-Schwinger model; Gamma5-hermitian,
+ * Sec. 2 before eq. 7), with Wilson parameter 1 and two spin components:
+ *   (D psi)(x) = (m0+2) psi(x) - 1/2 sum_mu [ (1 - s_mu) U_mu(x) psi(x+mu)
+ *                                       + (1 + s_mu) conj(U_mu(x-mu)) psi(x-mu) ],
+ * s_x = sigma_1, s_t = sigma_2, Gamma5 = sigma_3; periodic in x, antiperiodic in t when
+ * antiperiodic_t != 0.  U_mu(x, t) = exp(i theta[mu][t][x]).
+ *
+ * The multigrid hierarchy (Sec. 3.1, eq. 8 and the Petrov-Galerkin coarse operator
+ * D_{l+1} = P_l^H D_l P_l; spin-preserving aggregation, eq. 14): level l is coarsened
+ * by agg[l-1] = {ax, at} site blocks with ntv[l-1] test vectors per chirality.  The
+ * test vectors are V = MGS(D_l^-1 ... MGS(D_l^-1 V0)) (n_inv steps, solves to relative
+ * residual 1e-12) from Z4 start vectors V0 drawn by the SplitMix64 counter hash with
+ * `seed`; P_l is the QR factor (positive real diagonal) of V on every
+ * (aggregate, chirality) block.  import_tv, when not NULL, gives per coarsening step
+ * l (0-based) host complex128 test vectors [ntv][n_l] (vector k at k * n_l) that
+ * replace the inverse iteration (P_l is then the local QR of the imported vectors). */
+typedef struct {
+  int Lx, Lt;
+  double m0;
+  int antiperiodic_t;
+  const double *theta; /* host, [2][Lt][Lx]; copied */
+} dmlmc_lattice;
+
+typedef struct {
+  int nlevels;          /* L >= 1 (1 = fine level only, no coarsening) */
+  int agg[7][2];        /* {ax, at} per coarsening step */
+  int ntv[7];           /* test vectors per chirality per coarsening step */
+  int n_inv;            /* inverse-iteration steps of the test-vector setup (>= 1) */
+  uint64_t seed;        /* seed of the Z4 start vectors */
+  const void *const *import_tv; /* NULL or nlevels-1 host pointers (see above) */
+} dmlmc_mg_params;
+
+/* Builds the hierarchy.  Errors: EINVAL when a lattice extent is not divisible by its
+ * aggregate, a coarse extent would be < 2, ntv exceeds the rows of an
+ * (aggregate, chirality) block, or nlevels is outside 1..8. */
+dmlmc_status dmlmc_build_hierarchy(dmlmc_ctx *ctx, const dmlmc_lattice *lat,
+                                   const dmlmc_mg_params *mg, dmlmc_hier **out);
+void dmlmc_free_hierarchy(dmlmc_hier *h);
+
+/* Level geometry: lattice extents and dofs per site of level `level`. */
+dmlmc_status dmlmc_level_info(const dmlmc_hier *h, int level, int *Lx, int *Lt, int *dofs);
+
+/* Copies level data to host buffers (any of them may be NULL):
+ *   P_host:  complex128 [n_level][n_{level+1}] dense row-major interpolator P_level
+ *            (level < L; zero outside the aggregate blocks);
+ *   Dc_host: complex128 [sites][5][d][d] block stencil of level `level` >= 2
+ *            (directions self, +x, -x, +t, -t; where an extent is 2 the +mu block holds
+ *            the whole coupling and the -mu block is zero);
+ *   tv_host: complex128 [ntv][n_level] test vectors used for P_level (level < L). */
+dmlmc_status dmlmc_export_level(dmlmc_ctx *ctx, const dmlmc_hier *h, int level, void *P_host,
+                                void *Dc_host, void *tv_host);
+
+/* ---------------------------------------------------------------- deflation
+ * Exact deflation at level `level` (normally L) by the k eigenpairs of
+ * Q = Gamma5 D_level with the smallest |lambda| (ties: lambda ascending), which are the
+ * k smallest singular triplets of D_level (eq. 7: U = Gamma5 X sign(Lambda), V = X,
+ * Sigma = |Lambda|).  The projector is Pi = W W^H with W = Gamma5 X_k (eq. 4) and the
+ * small trace term tr(D^-1 Pi) = sum_i x_i^H Gamma5 x_i / lambda_i (eq. 6) is returned in
+ * tr_defl_out.  The eigensolver is Chebyshev-filtered subspace iteration on Q^2 with
+ * Rayleigh-Ritz on Q, run until every residual ||Q x_i - lambda_i x_i|| <= eig_rtol *
+ * ||Q||_est.  import_X (host complex128 [k][n_level]) and import_lambda (host double
+ * [k]), when not NULL, replace the eigensolve.  Errors: EINVAL for k < 1 or k > n_level
+ * / 4; ENOCONV when the eigensolver stops at its iteration limit (outputs still set). */
+dmlmc_status dmlmc_deflate(dmlmc_ctx *ctx, dmlmc_hier *h, int level, int k, double eig_rtol,
+                           const void *import_X, const double *import_lambda,
+                           dmlmc_defl **out, double *tr_defl_out);
+void dmlmc_free_deflation(dmlmc_defl *d);
+/* Eigensolver statistics: outer subspace iterations, Chebyshev degrees summed over them
+ * (Q^2 applications per subspace vector) and the final max ||Q x_i - lambda_i x_i|| /
+ * ||Q||_bound (all zero for an imported deflation).  Any pointer may be NULL. */
+dmlmc_status dmlmc_deflation_info(const dmlmc_defl *d, int *iters, int64_t *degree_sum,
+                                  double *max_residual);
+/* Copies the deflation to the host: X_host complex128 [k][n_level] eigenvectors of Q,
+ * lambda_host double [k]; either may be NULL. */
+dmlmc_status dmlmc_export_deflation(dmlmc_ctx *ctx, const dmlmc_defl *d, void *X_host,
+                                    double *lambda_host);
+
+/* ---------------------------------------------------------------- solves
+ * Solves D_level X = B for nrhs right-hand sides (Sec. 3.1: multigrid-preconditioned
+ * Krylov solves; the paper solves each sample to a relative residual, Sec. 4.3).
+ * Right-preconditioned FGMRES with per-RHS Krylov spaces, FP64 Arnoldi (Gram-Schmidt
+ * with reorthogonalisation) and a V-cycle (eq. 8, applied recursively) as
+ * preconditioner; stops when ||B_r - D X_r|| <= rtol ||B_r|| for every r, the residual
+ * computed in FP64.  prec = DMLMC_FP64: everything in FP64.  prec = DMLMC_MIXED: the
+ * V-cycle, its smoother and coarse solves and the operator inside the Krylov solver run
+ * in complex FP32; an outer FP64 iterative refinement recomputes the residual in FP64.
+ * When proj != NULL (a deflation of this level) B is replaced by (I - W W^H) B.
+ * B, X: device complex128, [nrhs][ld]; X is overwritten (initial guess zero).
+ * maxiter bounds the total Krylov iterations per RHS.  Errors: EINVAL (level, nrhs < 1,
+ * ld < n_level, null pointers), ENOCONV (rtol not met; X holds the last iterate),
+ * ENUMERIC (NaN/Inf residual). */
+typedef struct {
+  int iters;        /* Krylov iterations (max over RHS, summed over refinement steps) */
+  int ir_steps;     /* FP64 refinement steps (1 in FP64 mode) */
+  int converged;    /* 1 if every RHS met rtol */
+  double relres_max;/* max_r ||B_r - D X_r|| / ||B_r|| in FP64 */
+} dmlmc_solve_stats;
+
+dmlmc_status dmlmc_solve_multi_rhs(dmlmc_ctx *ctx, const dmlmc_hier *h, int level,
+                                   const dmlmc_defl *proj, const void *B, void *X, int nrhs,
+                                   int64_t ld, dmlmc_precision prec, double rtol, int maxiter,
+                                   dmlmc_solve_stats *stats);
+
+/* ---------------------------------------------------------------- trace
+ * MGMLMC estimate of tr(D^-1) (eq. 11) with exact deflation of the coarsest term
+ * (eq. 5): samples of difference level l < L are s = x^H D_l^-1 x - y^H D_{l+1}^-1 y with
+ * y = P_l^H x; samples of level L are s = x^H D_L^-1 (x - W W^H x); x is the real Z2
+ * vector of sample i of level l, entry j = 1 - 2 bit_j(SplitMix64 hash of
+ * (noise_seed, l, i, j / 64)).  Samples are drawn in blocks of rhs_block indices; the
+ * estimate is Re(sum_l mean_l) + tr_defl with relative error sqrt(sum_l var_l / N_l) /
+ * |estimate|.  Sample counts start at n0[l] (rounded up to rhs_block) and follow the
+ * multilevel allocation N_l = ceil(eps^-2 T^-2 sqrt(V_l / C_l) sum_j sqrt(V_j C_j))
+ * (C_l: a fixed per-level work proxy) until the error is <= eps, unless fixed_counts.
+ * samples_out[l-1], when not NULL, receives max_samples[l-1] complex128 sample values
+ * (host).  Errors: EINVAL, ENOCONV (a solve failed; result holds the samples so far). */
+typedef struct {
+  double eps;
+  uint64_t noise_seed;
+  int n0[8];
+  int64_t max_samples[8];
+  int rhs_block;
+  dmlmc_precision prec;
+  double rtol;
+  int fixed_counts;
+  int maxiter;
+  double *samples_out[8];
+} dmlmc_mlmc_params;
+
+typedef struct {
+  double trace, trace_imag, rel_err;
+  int64_t N[8];
+  double mean_re[8], mean_im[8], var[8];
+  double cost_s[8];       /* wall seconds spent per level */
+  double tr_defl;
+  double t_trace_s;       /* wall seconds of the whole estimate */
+  int64_t iters[8];       /* Krylov iterations summed over the level's solves */
+} dmlmc_trace_result;
+
+dmlmc_status dmlmc_mlmc_trace(dmlmc_ctx *ctx, const dmlmc_hier *h, const dmlmc_defl *coarsest,
+                              const dmlmc_mlmc_params *p, dmlmc_trace_result *out);
+
+/* ---------------------------------------------------------------- single operators
+ * Applies one operator of level `level` to nrhs device vectors (for parity checks and
+ * kernel timing).  in/out: device, complex128 when prec = DMLMC_FP64 and complex64
+ * when prec = DMLMC_MIXED, [nrhs][ld_in] / [nrhs][ld_out] with ld = n of the vector's
+ * level:
+ *   DMLMC_OP_D         out = D_level in
+ *   DMLMC_OP_RESTRICT  out (level+1) = P_level^H in (level)
+ *   DMLMC_OP_PROLONG   out (level) = P_level in (level+1)
+ *   DMLMC_OP_SMOOTH    out = smoother sweeps(out; b = in), out is the initial guess
+ *   DMLMC_OP_VCYCLE    out = V-cycle(in) (one preconditioner application)
+ *   DMLMC_OP_DEFL_C    out ([nrhs][k]) = W^H in                 (needs dmlmc_set_deflation)
+ *   DMLMC_OP_DEFL_P    out = in - W (W^H in)                    (needs dmlmc_set_deflation)
+ *                      (both take complex128 in/out; DMLMC_FP64 selects FP64 kernels,
+ *                      DMLMC_MIXED the complex-FP32 matrix-core kernels with FP64
+ *                      accumulation of W^H in)
+ *   DMLMC_OP_GAMMA5_D  out = Gamma5 D_level in
+ * `arg` is the number of smoother sweeps for DMLMC_OP_SMOOTH and unused otherwise. */
+enum {
+  DMLMC_OP_D = 0, DMLMC_OP_RESTRICT = 1, DMLMC_OP_PROLONG = 2, DMLMC_OP_SMOOTH = 3,
+  DMLMC_OP_VCYCLE = 4, DMLMC_OP_DEFL_C = 6, DMLMC_OP_DEFL_P = 7, DMLMC_OP_GAMMA5_D = 8
+};
+dmlmc_status dmlmc_apply(dmlmc_ctx *ctx, const dmlmc_hier *h, int op, int level, const void *in,
+                         void *out, int nrhs, dmlmc_precision prec, uint64_t arg);
+
+/* Writes the real Z2 noise vectors of samples sample0 .. sample0 + nrhs - 1 of level
+ * `level` (length n each, [nrhs][n], device, complex128 for DMLMC_FP64 / complex64 for
+ * DMLMC_MIXED): entry j = 1 - 2 * bit (j % 64) of SM(SM(SM(SM(seed) + level) + i) + j / 64)
+ * with SM one SplitMix64 step (Steele, Lea & Flood 2014); Z2 noise as in Sec. 2, eq. 2. */
+dmlmc_status dmlmc_z2_noise(dmlmc_ctx *ctx, int64_t n, uint64_t seed, int level, int64_t sample0,
+                            int nrhs, void *out, dmlmc_precision prec);
+
+/* Attaches (or with d = NULL detaches) a deflation used by DMLMC_OP_DEFL_*. */
+dmlmc_status dmlmc_set_deflation(dmlmc_hier *h, const dmlmc_defl *d);
+
+/* ---------------------------------------------------------------- kernel timing
+ * When enabled, the library brackets every launch of the named kernel classes with HIP
+ * events on the context stream and accumulates their durations.  Classes:
+ * "wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong", "gs_dots", "gs_update",
+ * "defl_gemm".  dmlmc_timing_get returns (launches, total milliseconds, bytes per
+ * launch summed) for a class. */
+dmlmc_status dmlmc_timing_enable(dmlmc_ctx *ctx, int enable);
+dmlmc_status dmlmc_timing_reset(dmlmc_ctx *ctx);
+dmlmc_status dmlmc_timing_get(dmlmc_ctx *ctx, const char *cls, int64_t *launches, double *ms,
+                              double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMLMC_H */

@@ -1,0 +1,269 @@
+// Internal declarations of the dmlmc library (host + device).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "dmlmc.h"
+
+// ------------------------------------------------------------------ complex arithmetic
+template <typename R>
+struct __align__(2 * sizeof(R)) Cx {
+  R x, y;
+};
+using c64 = Cx<float>;
+using c128 = Cx<double>;
+
+template <typename R>
+__host__ __device__ __forceinline__ Cx<R> cmk(R a, R b) {
+  Cx<R> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename R>
+__host__ __device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return cmk(a.x + b.x, a.y + b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return cmk(a.x - b.x, a.y - b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ Cx<R> operator*(Cx<R> a, Cx<R> b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename R>
+__host__ __device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return cmk(s * a.x, s * a.y); }
+template <typename R>
+__host__ __device__ __forceinline__ Cx<R> conj(Cx<R> a) { return cmk(a.x, -a.y); }
+// conj(a) * b
+template <typename R>
+__host__ __device__ __forceinline__ Cx<R> cdot(Cx<R> a, Cx<R> b) {
+  return cmk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+// acc += a * b
+template <typename R>
+__host__ __device__ __forceinline__ void cfma(Cx<R>& acc, Cx<R> a, Cx<R> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+template <typename R>
+__host__ __device__ __forceinline__ void cfmac(Cx<R>& acc, Cx<R> a, Cx<R> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+template <typename R>
+__host__ __device__ __forceinline__ double cabs2(Cx<R> a) {
+  return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+}
+template <typename To, typename From>
+__host__ __device__ __forceinline__ Cx<To> ccast(Cx<From> a) {
+  return cmk((To)a.x, (To)a.y);
+}
+
+// ------------------------------------------------------------------ errors
+struct DmlmcError : std::runtime_error {
+  dmlmc_status status;
+  DmlmcError(dmlmc_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess)                                                                     \
+      throw DmlmcError(_e == hipErrorOutOfMemory ? DMLMC_ENOMEM : DMLMC_EHIP,                 \
+                       std::string(#expr) + ": " + hipGetErrorString(_e) + " at " __FILE__ ":" + \
+                           std::to_string(__LINE__));                                         \
+  } while (0)
+
+#define REQUIRE(cond, msg)                                                  \
+  do {                                                                      \
+    if (!(cond)) throw DmlmcError(DMLMC_EINVAL, std::string("invalid argument: ") + (msg)); \
+  } while (0)
+
+#define LAUNCH_CHECK() HIPCHK(hipGetLastError())
+
+// ------------------------------------------------------------------ device memory
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    HIPCHK(hipMalloc(&p, b));
+    bytes = b;
+  }
+  // grows (never shrinks); contents are not preserved
+  void ensure(size_t b) { if (b > bytes) alloc(b); }
+  void release() { if (p) { (void)hipFree(p); p = nullptr; bytes = 0; } }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------------ timing of kernel classes
+struct TimerClass {
+  int64_t launches = 0;
+  double ms = 0.0;
+  double bytes = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<double> pending_bytes;
+};
+
+struct dmlmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  bool timing = false;
+  std::map<std::string, TimerClass> timers;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+  DevBuf scratch_dots;   // reduction partials
+  DevBuf scratch_small;  // small per-RHS device results
+};
+
+// RAII bracket around one launch of a timed kernel class.
+struct KTimer {
+  dmlmc_ctx* ctx;
+  const char* cls;
+  double bytes;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  KTimer(dmlmc_ctx* c, const char* k, double b);
+  ~KTimer();
+};
+void timing_collect(dmlmc_ctx* ctx);
+
+// ------------------------------------------------------------------ hierarchy objects
+struct Level {
+  int l = 1;              // 1-based
+  int Lx = 0, Lt = 0, dofs = 2;
+  bool fine = true;
+  double m0 = 0.0;
+  // fine level: links U[mu][site] with the antiperiodic sign folded into U_t(., Lt-1)
+  DevBuf U64, U32;
+  // coarse levels: blocks A[site][5][d][d] and inverse self blocks [site][d][d], each
+  // block column-major (entry (i, j) at j * d + i)
+  DevBuf A64, A32, Ainv64, Ainv32;
+  // interpolation to level l+1 (if not coarsest): blocks P[cs][chir][row][k]
+  int ax = 0, at = 0, N = 0;
+  DevBuf P64, P32;
+  std::vector<c128> tv_host;  // test vectors used for P (ntv x n), kept for export
+  int64_t sites() const { return (int64_t)Lx * Lt; }
+  int64_t n() const { return sites() * dofs; }
+  int rows_per_block() const { return ax * at * (dofs / 2); }
+};
+
+struct Workspace;  // per-level scratch for V-cycles and solves (solver.hip)
+
+struct CoarsenStep {
+  int ax = 0, at = 0, ntv = 0;
+};
+
+struct dmlmc_hier {
+  dmlmc_ctx* ctx = nullptr;
+  std::vector<Level> lv;
+  std::vector<CoarsenStep> plan;  // coarsening steps 1..L-1
+  uint64_t seed = 0;
+  int n_inv = 3;
+  int64_t setup_iters = 0;
+  const dmlmc_defl* attached = nullptr;
+  // solver knobs (not part of the math; iteration counts only)
+  int sap_mr_iters = 4;
+  int nu_pre = 0, nu_post = 2;
+  int coarsest_iters = 24;
+  int restart = 16;
+  std::vector<std::unique_ptr<Workspace>> ws;  // indexed by level-1
+  ~dmlmc_hier();
+};
+
+struct dmlmc_defl {
+  dmlmc_ctx* ctx = nullptr;
+  int level = 0, k = 0;
+  int64_t n = 0;
+  DevBuf X64;     // eigenvectors of Q, [k][n]
+  DevBuf W64, W32;// Gamma5 X, [k][n]
+  std::vector<double> lambda;
+  double tr_defl = 0.0;
+  int eig_iters = 0;            // outer subspace iterations (0 when imported)
+  int64_t eig_degree_sum = 0;   // Chebyshev degrees summed (Q^2 applications per vector)
+  double eig_residual = 0.0;    // max ||Q x - lambda x|| / ||Q||_bound at exit
+};
+
+// ------------------------------------------------------------------ kernel launchers
+// precision tag: R = float -> c64 path, R = double -> c128 path
+template <typename R>
+void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx,
+                   int64_t ldy, bool gamma5_left);
+template <typename R>
+void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx,
+                   int64_t ldy, bool gamma5_left);
+template <typename R>
+void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, bool gamma5_left = false);
+// mixed: y (double) = D (double) x (float) -- operator in FP64 on an FP32 input
+template <typename R>
+void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color,
+                int mr_iters);
+template <typename R>
+void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color);
+template <typename R>
+void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc, int nrhs);
+template <typename R>
+void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, int nrhs, bool add);
+
+// BLAS-like (blas.hip)
+template <typename T>
+void launch_fill_zero(dmlmc_ctx* ctx, T* p, size_t count);
+template <typename To, typename From>
+void launch_cast(dmlmc_ctx* ctx, const Cx<From>* x, Cx<To>* y, int64_t n, int nrhs, int64_t ldx, int64_t ldy);
+// per-RHS dots out[r] = sum_i conj(x[r][i]) y[r][i] (FP64 accumulation), out on device
+template <typename RX, typename RY>
+void launch_dots(dmlmc_ctx* ctx, const Cx<RX>* x, const Cx<RY>* y, int64_t n, int nrhs, int64_t ldx,
+                 int64_t ldy, c128* out);
+// per-RHS squared norms (FP64), out on device
+template <typename R>
+void launch_norms2(dmlmc_ctx* ctx, const Cx<R>* x, int64_t n, int nrhs, int64_t ld, double* out);
+// y[r] = a[r] * x[r] + y[r]   (a on device, per RHS)
+template <typename R>
+void launch_axpy_dev(dmlmc_ctx* ctx, const c128* a, const Cx<R>* x, Cx<R>* y, int64_t n, int nrhs, int64_t ld);
+// y = b - y (residual from y = D x), in place
+template <typename R>
+void launch_xmy(dmlmc_ctx* ctx, const Cx<R>* b, Cx<R>* y, int64_t n, int nrhs, int64_t ldb, int64_t ldy);
+// x64 += (double) e32
+template <typename RE>
+void launch_add_cast(dmlmc_ctx* ctx, const Cx<RE>* e, c128* x, int64_t n, int nrhs, int64_t lde, int64_t ldx);
+// Z2 noise
+template <typename R>
+void launch_z2(dmlmc_ctx* ctx, Cx<R>* out, int64_t n, uint64_t seed, int level, int64_t sample0, int nrhs,
+               int64_t ld);
+void launch_z4(dmlmc_ctx* ctx, c128* out, int64_t n, uint64_t seed, int level, int vec0, int nvec);
+
+// Block inner products with a set of nb vectors V_i: vector i of RHS r at
+// V + i * vstride + r * ldv (ldv = 0: one set shared by all RHS; ldv < 0: ldv = ld).
+//  h[r][i] = <V_i[r], w[r]> for i < nb (FP64 accumulation)
+template <typename RV>
+void launch_multidot(dmlmc_ctx* ctx, const Cx<RV>* V, int nb, const c128* w, int64_t n, int nrhs,
+                     int64_t ld, int64_t vstride, c128* h /* [nrhs][hld] */, int hld, int64_t ldv = -1);
+//  w[r] -= sgn * sum_i h[r][i] V_i[r]
+template <typename RV>
+void launch_multiaxpy(dmlmc_ctx* ctx, const Cx<RV>* V, int nb, c128* w, int64_t n, int nrhs, int64_t ld,
+                      int64_t vstride, const c128* h, int hld, int64_t ldv = -1, double sgn = 1.0);
+
+// helpers
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

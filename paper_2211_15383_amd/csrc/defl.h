@@ -1,0 +1,26 @@
+// Internal deflation interfaces.
+#pragma once
+
+#include "common.h"
+
+struct EigResult {
+  int iters = 0;
+  bool converged = false;
+  int64_t degree_sum = 0;      // Chebyshev degrees summed over the outer steps
+  double max_residual = 0.0;   // max ||Q x - lambda x|| / ||Q||_bound over the wanted pairs
+  std::vector<double> lambda;  // signed eigenvalues, ordered by |lambda| then lambda
+};
+
+// k eigenpairs of Q = Gamma5 D_level with the smallest |lambda|; X written to Xout [k][n].
+EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout);
+// W = Gamma5 X (FP64 and FP32 copies) and tr(D^-1 Pi) from D->X64 and D->lambda.
+void defl_finish(dmlmc_hier* H, dmlmc_defl* D);
+// C[r][i] = <w_i, x_r> and X <- X - W C
+void defl_coeffs_fp64(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, int b, int64_t ldx, c128* C);
+void defl_project_fp64(dmlmc_ctx* ctx, const dmlmc_defl* D, c128* X, int b, int64_t ldx, const c128* C);
+void defl_coeffs_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, int b, int64_t ldx, c128* C,
+                      DevBuf& scratch);
+void defl_project_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, c128* Y, int b, int64_t ldx, int64_t ldy,
+                       const c128* C);
+// X <- (I - W W^H) X; FP64 kernels for DMLMC_FP64, FP32 matrix-core kernels for DMLMC_MIXED.
+void defl_apply(dmlmc_hier* H, const dmlmc_defl* D, c128* X, int b, int64_t ldx, dmlmc_precision prec);

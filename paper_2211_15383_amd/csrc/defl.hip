@@ -1,0 +1,391 @@
+// Exact deflation of the coarsest operator (eqs. 4-7):
+//   * projections C = W^H X and Y = X - W C with W = Gamma5 X_k (n x k) and X (n x b):
+//     FP64 forms, and complex-FP32 forms on the matrix cores (v_mfma_f32_16x16x4_f32, four
+//     real products per complex product) with FP64 accumulation across K-chunks;
+//   * the eigensolver for the k eigenpairs of Q = Gamma5 D_L with the smallest |lambda|:
+//     Chebyshev-filtered subspace iteration on Q^2 (filter damps [a, ||Q||^2], a = the
+//     largest Ritz value of Q^2 kept in the subspace), CholQR2 orthonormalisation and
+//     Rayleigh-Ritz on Q, all FP64 on the device except the small dense eigenproblem.
+#include <algorithm>
+#include <cmath>
+
+#include "defl.h"
+#include "eigh_host.h"
+#include "setup.h"
+#include "solver.h"
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int KC = 256;  // K-chunk of the split-K product W^H X
+
+// Partial C over one K-chunk for one 16 x 16 tile (rows i of W^H, columns r of X).
+// Operand layout of v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; it receives D[4 (l / 16) + v][l % 16], v = 0..3.
+__global__ __launch_bounds__(64) void defl_c_mfma_kernel(const c64* __restrict__ W, int k, const c128* __restrict__ X,
+                                                         int b, int64_t n, int64_t ldx, c128* __restrict__ part) {
+  const int lane = threadIdx.x;
+  const int chunk = blockIdx.x;
+  const int i0 = blockIdx.y * 16, r0 = blockIdx.z * 16;
+  const int row = lane % 16, kk = lane / 16;
+  const int iA = i0 + row;   // W row for the A operand
+  const int rB = r0 + row;   // X column for the B operand
+  floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+  const int64_t p0 = (int64_t)chunk * KC;
+  const int64_t pend = (p0 + KC < n) ? p0 + KC : n;
+  for (int64_t p = p0; p < pend; p += 4) {
+    const int64_t pk = p + kk;
+    c64 a = cmk(0.f, 0.f), x = cmk(0.f, 0.f);
+    if (pk < pend) {
+      if (iA < k) a = W[(int64_t)iA * n + pk];
+      if (rB < b) {
+        const c128 xv = X[(int64_t)rB * ldx + pk];
+        x = cmk((float)xv.x, (float)xv.y);
+      }
+    }
+    // conj(W) X: re = Wr Xr + Wi Xi, im = Wr Xi - Wi Xr
+    cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x.x, cre, 0, 0, 0);
+    cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x.y, cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x.y, cim, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, x.x, cim, 0, 0, 0);
+  }
+  const int r = r0 + row;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + 4 * kk + v;
+    if (i < k && r < b) part[((int64_t)chunk * b + r) * k + i] = cmk((double)cre[v], (double)cim[v]);
+  }
+}
+
+// C[r][i] = sum over chunks (FP64)
+__global__ void defl_c_reduce_kernel(const c128* __restrict__ part, int nchunks, int k, int b, c128* __restrict__ C) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * b) return;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < nchunks; ++c) {
+    const c128 v = part[(int64_t)c * k * b + t];
+    re += v.x;
+    im += v.y;
+  }
+  C[t] = cmk(re, im);
+}
+
+// Y = X - W C on one 16 (p) x 16 (r) tile: A[p][i] = W[i][p], B[i][r] = C[r][i].
+__global__ __launch_bounds__(64) void defl_p_mfma_kernel(const c64* __restrict__ W, int k, const c128* __restrict__ C,
+                                                         const c128* __restrict__ X, c128* __restrict__ Y, int b,
+                                                         int64_t n, int64_t ldx, int64_t ldy) {
+  const int lane = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 16;
+  const int r0 = blockIdx.y * 16;
+  const int row = lane % 16, kk = lane / 16;
+  floatx4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
+  for (int i0 = 0; i0 < k; i0 += 4) {
+    const int i = i0 + kk;
+    c64 a = cmk(0.f, 0.f), c = cmk(0.f, 0.f);
+    if (i < k) {
+      if (p0 + row < n) a = W[(int64_t)i * n + p0 + row];
+      if (r0 + row < b) {
+        const c128 cv = C[(int64_t)(r0 + row) * k + i];
+        c = cmk((float)cv.x, (float)cv.y);
+      }
+    }
+    // W C: re = Wr Cr - Wi Ci, im = Wr Ci + Wi Cr
+    dre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, c.x, dre, 0, 0, 0);
+    dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, c.y, dre, 0, 0, 0);
+    dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, c.y, dim, 0, 0, 0);
+    dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, c.x, dim, 0, 0, 0);
+  }
+  const int r = r0 + row;
+  if (r >= b) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t p = p0 + 4 * kk + v;
+    if (p < n) {
+      const c128 xv = X[(int64_t)r * ldx + p];
+      Y[(int64_t)r * ldy + p] = cmk(xv.x - (double)dre[v], xv.y - (double)dim[v]);
+    }
+  }
+}
+
+// row-sum bound of |Q| = |D| (Gamma5 only flips signs): max_row sum_j |A[s][dir][i][j]|
+__global__ void rowsum_kernel(const c128* __restrict__ A, int64_t sites, int d, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= sites * d) return;
+  const int64_t s = t / d;
+  const int i = (int)(t % d);
+  double sum = 0.0;
+  for (int dir = 0; dir < 5; ++dir)
+    for (int j = 0; j < d; ++j) sum += sqrt(cabs2(A[(s * 5 + dir) * (int64_t)d * d + j * d + i]));
+  out[t] = sum;
+}
+
+__global__ void gamma5_kernel(const c128* __restrict__ x, c128* __restrict__ y, int64_t n, int d, int nv) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nv) return;
+  const int dof = (int)((t % n) % d);
+  const c128 v = x[t];
+  y[t] = (dof < d / 2) ? v : cmk(-v.x, -v.y);
+}
+
+// y = (2 / e) (Q^2 x - c x) - z  (or without -z when first), elementwise part
+__global__ void cheb_kernel(const c128* __restrict__ q2x, const c128* __restrict__ x, const c128* __restrict__ z,
+                            c128* __restrict__ y, int64_t total, double alpha, double c, int first) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  c128 v = alpha * (q2x[t] - c * x[t]);
+  if (!first) v = v - z[t];
+  y[t] = v;
+}
+
+// r_i = z_i - theta_i y_i, written over z
+__global__ void ritz_res_kernel(c128* __restrict__ z, const c128* __restrict__ y, const double* __restrict__ theta,
+                                int64_t n, int nv) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nv) return;
+  const int i = (int)(t / n);
+  z[t] = z[t] - theta[i] * y[t];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ projections
+void defl_coeffs_fp64(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, int b, int64_t ldx, c128* C) {
+  launch_multidot<double>(ctx, D->W64.as<c128>(), D->k, X, D->n, b, ldx, D->n, C, D->k, 0);
+}
+
+void defl_project_fp64(dmlmc_ctx* ctx, const dmlmc_defl* D, c128* X, int b, int64_t ldx, const c128* C) {
+  launch_multiaxpy<double>(ctx, D->W64.as<c128>(), D->k, X, D->n, b, ldx, D->n, C, D->k, 0, 1.0);
+}
+
+void defl_coeffs_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, int b, int64_t ldx, c128* C,
+                      DevBuf& scratch) {
+  const int nchunks = (int)ceil_div(D->n, KC);
+  scratch.ensure(sizeof(c128) * (size_t)nchunks * D->k * b);
+  KTimer kt(ctx, "defl_gemm", 8.0 * D->n * D->k * b);
+  dim3 grid(nchunks, (unsigned)ceil_div(D->k, 16), (unsigned)ceil_div(b, 16));
+  hipLaunchKernelGGL(defl_c_mfma_kernel, grid, dim3(64), 0, ctx->stream, D->W32.as<c64>(), D->k, X, b, D->n, ldx,
+                     scratch.as<c128>());
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(defl_c_reduce_kernel, dim3((unsigned)ceil_div((int64_t)D->k * b, 256)), dim3(256), 0,
+                     ctx->stream, scratch.as<c128>(), nchunks, D->k, b, C);
+  LAUNCH_CHECK();
+}
+
+void defl_project_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, c128* Y, int b, int64_t ldx, int64_t ldy,
+                       const c128* C) {
+  KTimer kt(ctx, "defl_gemm", 8.0 * D->n * D->k * b);
+  dim3 grid((unsigned)ceil_div(D->n, 16), (unsigned)ceil_div(b, 16));
+  hipLaunchKernelGGL(defl_p_mfma_kernel, grid, dim3(64), 0, ctx->stream, D->W32.as<c64>(), D->k, C, X, Y, b, D->n,
+                     ldx, ldy);
+  LAUNCH_CHECK();
+}
+
+// X <- (I - W W^H) X  (in place, precision per prec)
+void defl_apply(dmlmc_hier* H, const dmlmc_defl* D, c128* X, int b, int64_t ldx, dmlmc_precision prec) {
+  dmlmc_ctx* ctx = H->ctx;
+  c128* C = (c128*)hier_buf(H, "df_C", D->level, sizeof(c128) * (size_t)D->k * b);
+  if (prec == DMLMC_MIXED) {
+    defl_coeffs_mfma(ctx, D, X, b, ldx, C, hier_devbuf(H, "df_part", D->level));
+    defl_project_mfma(ctx, D, X, X, b, ldx, ldx, C);
+  } else {
+    defl_coeffs_fp64(ctx, D, X, b, ldx, C);
+    defl_project_fp64(ctx, D, X, b, ldx, C);
+  }
+}
+
+// ------------------------------------------------------------------ eigensolver
+namespace {
+
+void applyQ(dmlmc_ctx* ctx, const Level& L, const c128* x, c128* y, int nv) {
+  apply_op<double>(ctx, L, x, y, nv, /*gamma5_left=*/true);
+}
+
+// G[r][i] = <Y_i, Z_r> (ns x nv) -> host, row-major host matrix M[i][r]
+std::vector<std::complex<double>> gram(dmlmc_hier* H, const c128* Y, int nsY, const c128* Z, int nv, int64_t n) {
+  dmlmc_ctx* ctx = H->ctx;
+  c128* G = (c128*)hier_buf(H, "eg_G", 0, sizeof(c128) * (size_t)nsY * nv);
+  launch_multidot<double>(ctx, Y, nsY, Z, n, nv, n, n, G, nsY, 0);
+  std::vector<c128> h((size_t)nsY * nv);
+  HIPCHK(hipMemcpyAsync(h.data(), G, sizeof(c128) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::vector<std::complex<double>> M((size_t)nsY * nv);
+  for (int r = 0; r < nv; ++r)
+    for (int i = 0; i < nsY; ++i) M[(size_t)i * nv + r] = std::complex<double>(h[(size_t)r * nsY + i].x, h[(size_t)r * nsY + i].y);
+  return M;
+}
+
+// out_r = sum_i S[i][r] Y_i (S host ns x nv row-major); out must not alias Y
+void rotate(dmlmc_hier* H, const c128* Y, int nsY, const std::vector<std::complex<double>>& S, int nv, c128* out,
+            int64_t n) {
+  dmlmc_ctx* ctx = H->ctx;
+  std::vector<c128> h((size_t)nv * nsY);
+  for (int r = 0; r < nv; ++r)
+    for (int i = 0; i < nsY; ++i) h[(size_t)r * nsY + i] = cmk(S[(size_t)i * nv + r].real(), S[(size_t)i * nv + r].imag());
+  c128* hd = (c128*)hier_buf(H, "eg_S", 0, sizeof(c128) * h.size());
+  HIPCHK(hipMemcpyAsync(hd, h.data(), sizeof(c128) * h.size(), hipMemcpyHostToDevice, ctx->stream));
+  launch_fill_zero<c128>(ctx, out, (size_t)nv * n);
+  // out_r -= (-1) * sum_i h[r][i] Y_i
+  launch_multiaxpy<double>(ctx, Y, nsY, out, n, nv, n, n, hd, nsY, 0, -1.0);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+}
+
+// Orthonormalise the ns columns of Y by Cholesky QR, twice.  Returns false if a
+// Cholesky factorisation fails.
+bool cholqr2(dmlmc_hier* H, c128*& Y, c128*& T, int ns, int64_t n) {
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<std::complex<double>> G = gram(H, Y, ns, Y, ns, n);  // G[i][r] = <Y_i, Y_r>
+    // G = R^H R with R upper; cholesky_lower gives G = L L^H, so R = L^H and Y R^-1 = Y L^-H
+    if (!cholesky_lower(ns, G)) return false;
+    lower_inverse(ns, G);  // G = L^-1
+    // S = L^-H: S[i][r] = conj(Linv[r][i])
+    std::vector<std::complex<double>> S((size_t)ns * ns);
+    for (int i = 0; i < ns; ++i)
+      for (int r = 0; r < ns; ++r) S[(size_t)i * ns + r] = std::conj(G[(size_t)r * ns + i]);
+    rotate(H, Y, ns, S, ns, T, n);
+    std::swap(Y, T);
+  }
+  return true;
+}
+
+}  // namespace
+
+// Returns the number of subspace iterations; fills X (k x n, device), lambda (host).
+EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout) {
+  dmlmc_ctx* ctx = H->ctx;
+  const Level& L = H->lv[level - 1];
+  const int64_t n = L.n();
+  const int ns = (int)std::min<int64_t>(n / 2, k + std::max(8, k / 2));
+  REQUIRE(ns >= k, "deflation subspace larger than half the level dimension");
+  EigResult res;
+  // ||Q||_inf bound
+  double qnorm = 0.0;
+  if (L.fine) {
+    // row sums of |D|: |m0 + 2| on the diagonal, and each of the four hops -(1 -+ s_mu) U / 2
+    // has entries of modulus 1/2, two per row
+    qnorm = std::fabs(L.m0 + 2.0) + 4.0;
+  } else {
+    double* rs = (double*)hier_buf(H, "eg_rs", 0, sizeof(double) * n);
+    hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, ctx->stream,
+                       L.A64.as<c128>(), L.sites(), L.dofs, rs);
+    LAUNCH_CHECK();
+    std::vector<double> h(n);
+    HIPCHK(hipMemcpyAsync(h.data(), rs, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    qnorm = *std::max_element(h.begin(), h.end());
+  }
+  const double bq = qnorm * qnorm * 1.01;
+  c128* Y = (c128*)hier_buf(H, "eg_Y", 0, sizeof(c128) * (size_t)ns * n);
+  c128* T = (c128*)hier_buf(H, "eg_T", 0, sizeof(c128) * (size_t)ns * n);
+  c128* Z = (c128*)hier_buf(H, "eg_Z", 0, sizeof(c128) * (size_t)ns * n);
+  c128* Q1 = (c128*)hier_buf(H, "eg_Q1", 0, sizeof(c128) * (size_t)ns * n);
+  c128* Y0 = (c128*)hier_buf(H, "eg_Y0", 0, sizeof(c128) * (size_t)ns * n);
+  launch_z4(ctx, Y, n, 0x5eed5eedull, level + 64, 0, ns);
+  if (!cholqr2(H, Y, T, ns, n)) throw DmlmcError(DMLMC_ENUMERIC, "eigensolver: start block is rank-deficient");
+  double a = bq / 64.0;
+  std::vector<double> theta;
+  std::vector<std::complex<double>> S;
+  const int maxit = 100;
+  int it = 0;
+  std::vector<int> sel(k);
+  for (; it < maxit; ++it) {
+    // Rayleigh-Ritz on Q
+    applyQ(ctx, L, Y, Z, ns);
+    std::vector<std::complex<double>> Hm = gram(H, Y, ns, Z, ns, n);
+    eigh_jacobi(ns, Hm, theta, S);
+    rotate(H, Y, ns, S, ns, T, n);
+    std::swap(Y, T);
+    rotate(H, Z, ns, S, ns, T, n);
+    std::swap(Z, T);
+    // wanted: k smallest |theta| (ties: theta ascending)
+    std::vector<int> order(ns);
+    for (int i = 0; i < ns; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int i, int j) {
+      const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
+      return ai < aj || (ai == aj && theta[i] < theta[j]);
+    });
+    for (int i = 0; i < k; ++i) sel[i] = order[i];
+    // residual norms of the wanted pairs
+    double* th = (double*)hier_buf(H, "eg_th", 0, sizeof(double) * ns);
+    HIPCHK(hipMemcpyAsync(th, theta.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(ritz_res_kernel, dim3((unsigned)ceil_div(n * ns, 256)), dim3(256), 0, ctx->stream, Z, Y, th, n,
+                       ns);
+    LAUNCH_CHECK();
+    double* nr = (double*)hier_buf(H, "eg_nr", 0, sizeof(double) * ns);
+    launch_norms2<double>(ctx, Z, n, ns, n, nr);
+    std::vector<double> rn(ns);
+    HIPCHK(hipMemcpyAsync(rn.data(), nr, sizeof(double) * ns, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double worst = 0.0;
+    for (int i = 0; i < k; ++i) worst = std::max(worst, std::sqrt(rn[sel[i]]));
+    res.max_residual = worst / qnorm;
+    if (worst <= tol * qnorm) break;
+    // filter interval: damp [a, bq] with a = the largest Ritz value of Q^2 in the subspace
+    double amax = 0.0;
+    for (int i = 0; i < ns; ++i) amax = std::max(amax, theta[i] * theta[i]);
+    a = std::min(std::max(amax, 1e-12 * bq), 0.5 * bq);
+    const double e = 0.5 * (bq - a), c = 0.5 * (bq + a);
+    // degree: the filter should amplify the largest wanted Ritz value of Q^2 (lk) over the
+    // damped interval by about e^4 per outer step: T_deg(x_k) = cosh(deg acosh(x_k))
+    double lk = 0.0;
+    for (int i = 0; i < k; ++i) lk = std::max(lk, theta[sel[i]] * theta[sel[i]]);
+    const double xk = 1.0 + 2.0 * std::max(a - lk, 1e-3 * a) / (bq - a);
+    const int deg = (int)std::min(400.0, std::max(8.0, std::ceil(4.0 / std::acosh(xk))));
+    res.degree_sum += deg;
+    // Chebyshev recurrence on Q^2: T0 = Y, T1 = (Q^2 - c)/e Y, Tj = 2 (Q^2 - c)/e T_{j-1} - T_{j-2}
+    c128* prev = Y0;
+    c128* cur = Y;
+    c128* nxt = T;
+    const int64_t tot = n * ns;
+    for (int j = 1; j <= deg; ++j) {
+      applyQ(ctx, L, cur, Q1, ns);
+      applyQ(ctx, L, Q1, Z, ns);
+      hipLaunchKernelGGL(cheb_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, ctx->stream, Z, cur, prev,
+                         nxt, tot, (j == 1 ? 1.0 : 2.0) / e, c, j == 1 ? 1 : 0);
+      LAUNCH_CHECK();
+      c128* t = prev;
+      prev = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    // cur holds the filtered block; keep the three buffers distinct for the next round
+    Y = cur;
+    T = nxt;
+    Y0 = prev;
+    if (!cholqr2(H, Y, T, ns, n)) {
+      orthonormalise(H, Y, ns, n);
+    }
+  }
+  res.iters = it;
+  res.converged = res.max_residual <= tol;
+  // gather the wanted pairs in order of |lambda| (then lambda)
+  res.lambda.resize(k);
+  for (int i = 0; i < k; ++i) {
+    res.lambda[i] = theta[sel[i]];
+    HIPCHK(hipMemcpyAsync(Xout + (int64_t)i * n, Y + (int64_t)sel[i] * n, sizeof(c128) * n, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return res;
+}
+
+void defl_finish(dmlmc_hier* H, dmlmc_defl* D) {
+  dmlmc_ctx* ctx = H->ctx;
+  const Level& L = H->lv[D->level - 1];
+  const int64_t n = D->n;
+  D->W64.alloc(sizeof(c128) * (size_t)D->k * n);
+  hipLaunchKernelGGL(gamma5_kernel, dim3((unsigned)ceil_div(n * D->k, 256)), dim3(256), 0, ctx->stream,
+                     D->X64.as<c128>(), D->W64.as<c128>(), n, L.dofs, D->k);
+  LAUNCH_CHECK();
+  D->W32.alloc(sizeof(c64) * (size_t)D->k * n);
+  launch_cast<float, double>(ctx, D->W64.as<c128>(), D->W32.as<c64>(), n * D->k, 1, 0, 0);
+  // tr(D^-1 Pi) = sum_i x_i^H Gamma5 x_i / lambda_i = sum_i <x_i, w_i> / lambda_i
+  c128* dd = (c128*)hier_buf(H, "df_dd", D->level, sizeof(c128) * D->k);
+  launch_dots<double, double>(ctx, D->X64.as<c128>(), D->W64.as<c128>(), n, D->k, n, n, dd);
+  std::vector<c128> h(D->k);
+  HIPCHK(hipMemcpyAsync(h.data(), dd, sizeof(c128) * D->k, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double tr = 0.0;
+  for (int i = 0; i < D->k; ++i) tr += h[i].x / D->lambda[i];
+  D->tr_defl = tr;
+}

@@ -1,0 +1,160 @@
+// Multigrid multilevel Monte Carlo estimate of tr(D^-1) (eq. 11) with exact deflation of
+// the coarsest term (eq. 5).  Samples are drawn in blocks of RHS; every block of a
+// difference level l < L draws its Z2 noise X on the device, solves D_l Z = X and
+// D_{l+1} Z' = P_l^H X (multi-RHS, per-RHS Krylov spaces) and forms
+// s = x^H z - y^H z' with FP64 dots; the coarsest level solves D_L Z = (I - W W^H) X and
+// forms s = x^H z.  Sample values go to the host, where the FP64 accumulation, the error
+// estimate and the multilevel sample allocation run.
+#include <chrono>
+#include <cmath>
+#include <complex>
+
+#include "defl.h"
+#include "mlmc.h"
+#include "solver.h"
+
+namespace {
+
+double level_work(const dmlmc_hier* H, int l) {
+  const Level& L = H->lv[l - 1];
+  return l == 1 ? 18.0 * L.sites() : 5.0 * L.dofs * L.dofs * L.sites();
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// Sample values of indices [i0, i0 + b) of level l, appended to out.
+static int sample_block(dmlmc_hier* H, const dmlmc_defl* defl, int l, int64_t i0, int b,
+                        const dmlmc_mlmc_params* p, std::vector<std::complex<double>>& out) {
+  dmlmc_ctx* ctx = H->ctx;
+  const int L = (int)H->lv.size();
+  const Level& F = H->lv[l - 1];
+  const int64_t n = F.n();
+  c128* X = (c128*)hier_buf(H, "ml_X", l, sizeof(c128) * (size_t)b * n);
+  c128* Z = (c128*)hier_buf(H, "ml_Z", l, sizeof(c128) * (size_t)b * n);
+  c128* s1 = (c128*)hier_buf(H, "ml_s1", l, sizeof(c128) * b);
+  launch_z2<double>(ctx, X, n, p->noise_seed, l, i0, b, n);
+  int iters = 0;
+  const int maxit = p->maxiter > 0 ? p->maxiter : 2000;
+  if (l < L) {
+    const Level& C = H->lv[l];
+    const int64_t nc = C.n();
+    c128* Y = (c128*)hier_buf(H, "ml_Y", l + 1, sizeof(c128) * (size_t)b * nc);
+    c128* Zc = (c128*)hier_buf(H, "ml_Zc", l + 1, sizeof(c128) * (size_t)b * nc);
+    c128* s2 = (c128*)hier_buf(H, "ml_s2", l, sizeof(c128) * b);
+    SolveResult r1 = solve_level(H, l, X, Z, b, p->prec, p->rtol, maxit);
+    launch_restrict<double>(ctx, F, X, Y, b);
+    SolveResult r2 = solve_level(H, l + 1, Y, Zc, b, p->prec, p->rtol, maxit);
+    if (!r1.converged || !r2.converged)
+      throw DmlmcError(DMLMC_ENOCONV, "sample solve did not converge at level " + std::to_string(l));
+    iters = r1.iters + r2.iters;
+    launch_dots<double, double>(ctx, X, Z, n, b, n, n, s1);
+    launch_dots<double, double>(ctx, Y, Zc, nc, b, nc, nc, s2);
+    std::vector<c128> h1(b), h2(b);
+    HIPCHK(hipMemcpyAsync(h1.data(), s1, sizeof(c128) * b, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(h2.data(), s2, sizeof(c128) * b, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < b; ++q) out.emplace_back(h1[q].x - h2[q].x, h1[q].y - h2[q].y);
+  } else {
+    c128* Xt = (c128*)hier_buf(H, "ml_Xt", l, sizeof(c128) * (size_t)b * n);
+    HIPCHK(hipMemcpyAsync(Xt, X, sizeof(c128) * (size_t)b * n, hipMemcpyDeviceToDevice, ctx->stream));
+    if (defl) defl_apply(H, defl, Xt, b, n, p->prec);
+    SolveResult r = solve_level(H, l, Xt, Z, b, p->prec, p->rtol, maxit);
+    if (!r.converged) throw DmlmcError(DMLMC_ENOCONV, "sample solve did not converge at the coarsest level");
+    iters = r.iters;
+    launch_dots<double, double>(ctx, X, Z, n, b, n, n, s1);
+    std::vector<c128> h1(b);
+    HIPCHK(hipMemcpyAsync(h1.data(), s1, sizeof(c128) * b, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < b; ++q) out.emplace_back(h1[q].x, h1[q].y);
+  }
+  return iters;
+}
+
+void run_mlmc(dmlmc_hier* H, const dmlmc_defl* defl, const dmlmc_mlmc_params* p, dmlmc_trace_result* res) {
+  const int L = (int)H->lv.size();
+  const int blk = p->rhs_block;
+  const double t0 = now_s();
+  std::vector<std::vector<std::complex<double>>> S(L);
+  std::vector<int64_t> target(L), cap(L);
+  std::vector<double> cost(L), level_time(L, 0.0);
+  std::vector<int64_t> iters(L, 0);
+  auto roundup = [&](int64_t m) { return ((m + blk - 1) / blk) * blk; };
+  for (int l = 1; l <= L; ++l) {
+    cost[l - 1] = level_work(H, l) + (l < L ? level_work(H, l + 1) : 0.0);
+    target[l - 1] = roundup(std::max(1, p->n0[l - 1]));
+    cap[l - 1] = p->max_samples[l - 1] > 0 ? p->max_samples[l - 1] : ((int64_t)1 << 40);
+  }
+  const double tr_defl = defl ? defl->tr_defl : 0.0;
+  double T = 0.0, Ti = 0.0, err = INFINITY;
+  std::vector<double> var(L, 0.0);
+  std::vector<std::complex<double>> mean(L);
+  while (true) {
+    for (int l = 1; l <= L; ++l) {
+      auto& s = S[l - 1];
+      while ((int64_t)s.size() < std::min(target[l - 1], cap[l - 1])) {
+        const int64_t i0 = (int64_t)s.size();
+        const int b = (int)std::min<int64_t>(blk, std::min(target[l - 1], cap[l - 1]) - i0);
+        const double ts = now_s();
+        iters[l - 1] += sample_block(H, defl, l, i0, b, p, s);
+        level_time[l - 1] += now_s() - ts;
+      }
+    }
+    // estimate (FP64 on the host)
+    T = tr_defl;
+    Ti = 0.0;
+    double vn = 0.0;
+    for (int l = 0; l < L; ++l) {
+      const auto& s = S[l];
+      std::complex<double> m(0.0, 0.0);
+      for (auto v : s) m += v;
+      m /= (double)s.size();
+      mean[l] = m;
+      double v2 = 0.0;
+      for (auto v : s) v2 += std::norm(v - m);
+      var[l] = s.size() > 1 ? v2 / (double)(s.size() - 1) : 0.0;
+      T += m.real();
+      Ti += m.imag();
+      vn += var[l] / (double)s.size();
+    }
+    err = T != 0.0 ? std::sqrt(vn) / std::fabs(T) : INFINITY;
+    if (p->fixed_counts || err <= p->eps) break;
+    // multilevel allocation
+    double sum = 0.0;
+    for (int l = 0; l < L; ++l) sum += std::sqrt(var[l] * cost[l]);
+    bool grew = false;
+    for (int l = 0; l < L; ++l) {
+      const double want = std::ceil(std::sqrt(var[l] / cost[l]) * sum / (p->eps * p->eps * T * T));
+      int64_t t = roundup(std::max<int64_t>((int64_t)want, (int64_t)S[l].size()));
+      t = std::min(t, cap[l]);
+      if (t > (int64_t)S[l].size()) {
+        target[l] = t;
+        grew = true;
+      }
+    }
+    if (!grew) break;
+  }
+  res->trace = T;
+  res->trace_imag = Ti;
+  res->rel_err = err;
+  res->tr_defl = tr_defl;
+  for (int l = 0; l < L && l < 8; ++l) {
+    res->N[l] = (int64_t)S[l].size();
+    res->mean_re[l] = mean[l].real();
+    res->mean_im[l] = mean[l].imag();
+    res->var[l] = var[l];
+    res->cost_s[l] = level_time[l];
+    res->iters[l] = iters[l];
+    if (p->samples_out[l]) {
+      const int64_t m = std::min<int64_t>((int64_t)S[l].size(), p->max_samples[l]);
+      for (int64_t i = 0; i < m; ++i) {
+        p->samples_out[l][2 * i] = S[l][i].real();
+        p->samples_out[l][2 * i + 1] = S[l][i].imag();
+      }
+    }
+  }
+  res->t_trace_s = now_s() - t0;
+}

@@ -1,0 +1,363 @@
+"""ctypes binding of libdmlmc.so (include/dmlmc.h).  Argument marshalling only.
+
+Device vectors are torch tensors on the GPU (complex128 for FP64, complex64 for the
+complex-FP32 operators); the library enqueues on torch's current HIP stream.  Every
+wrapper raises DmlmcError on a non-zero status.  There is no fallback: if the shared
+library is missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdmlmc.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+OP_D, OP_RESTRICT, OP_PROLONG, OP_SMOOTH, OP_VCYCLE, OP_DEFL_C, OP_DEFL_P, OP_GAMMA5_D = 0, 1, 2, 3, 4, 6, 7, 8
+
+EXPORTED = [
+    "dmlmc_create", "dmlmc_destroy", "dmlmc_last_error", "dmlmc_version", "dmlmc_build_hierarchy",
+    "dmlmc_free_hierarchy", "dmlmc_level_info", "dmlmc_export_level", "dmlmc_deflate",
+    "dmlmc_free_deflation", "dmlmc_deflation_info", "dmlmc_export_deflation", "dmlmc_solve_multi_rhs", "dmlmc_mlmc_trace",
+    "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_timing_enable",
+    "dmlmc_timing_reset", "dmlmc_timing_get",
+]
+
+
+class DmlmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"dmlmc status {status}: {msg}")
+        self.status = status
+
+
+class Lattice(C.Structure):
+    _fields_ = [("Lx", C.c_int), ("Lt", C.c_int), ("m0", C.c_double), ("antiperiodic_t", C.c_int),
+                ("theta", C.POINTER(C.c_double))]
+
+
+class MGParams(C.Structure):
+    _fields_ = [("nlevels", C.c_int), ("agg", (C.c_int * 2) * 7), ("ntv", C.c_int * 7), ("n_inv", C.c_int),
+                ("seed", C.c_uint64), ("import_tv", C.POINTER(C.c_void_p))]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("ir_steps", C.c_int), ("converged", C.c_int), ("relres_max", C.c_double)]
+
+
+class MLMCParams(C.Structure):
+    _fields_ = [("eps", C.c_double), ("noise_seed", C.c_uint64), ("n0", C.c_int * 8),
+                ("max_samples", C.c_int64 * 8), ("rhs_block", C.c_int), ("prec", C.c_int), ("rtol", C.c_double),
+                ("fixed_counts", C.c_int), ("maxiter", C.c_int), ("samples_out", C.POINTER(C.c_double) * 8)]
+
+
+class TraceResult(C.Structure):
+    _fields_ = [("trace", C.c_double), ("trace_imag", C.c_double), ("rel_err", C.c_double),
+                ("N", C.c_int64 * 8), ("mean_re", C.c_double * 8), ("mean_im", C.c_double * 8),
+                ("var", C.c_double * 8), ("cost_s", C.c_double * 8), ("tr_defl", C.c_double),
+                ("t_trace_s", C.c_double), ("iters", C.c_int64 * 8)]
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2211_15383_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, u64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double
+    sig = {
+        "dmlmc_create": (i32, [C.POINTER(vp), i32, vp]),
+        "dmlmc_destroy": (None, [vp]),
+        "dmlmc_last_error": (C.c_char_p, [vp]),
+        "dmlmc_version": (C.c_char_p, []),
+        "dmlmc_build_hierarchy": (i32, [vp, C.POINTER(Lattice), C.POINTER(MGParams), C.POINTER(vp)]),
+        "dmlmc_free_hierarchy": (None, [vp]),
+        "dmlmc_level_info": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
+        "dmlmc_export_level": (i32, [vp, vp, i32, vp, vp, vp]),
+        "dmlmc_deflate": (i32, [vp, vp, i32, i32, dbl, vp, C.POINTER(dbl), C.POINTER(vp), C.POINTER(dbl)]),
+        "dmlmc_free_deflation": (None, [vp]),
+        "dmlmc_deflation_info": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(dbl)]),
+        "dmlmc_export_deflation": (i32, [vp, vp, vp, C.POINTER(dbl)]),
+        "dmlmc_solve_multi_rhs": (i32, [vp, vp, i32, vp, vp, vp, i32, i64, i32, dbl, i32, C.POINTER(SolveStats)]),
+        "dmlmc_mlmc_trace": (i32, [vp, vp, vp, C.POINTER(MLMCParams), C.POINTER(TraceResult)]),
+        "dmlmc_apply": (i32, [vp, vp, i32, i32, vp, vp, i32, i32, u64]),
+        "dmlmc_set_deflation": (i32, [vp, vp]),
+        "dmlmc_z2_noise": (i32, [vp, i64, u64, i32, i64, i32, vp, i32]),
+        "dmlmc_timing_enable": (i32, [vp, i32]),
+        "dmlmc_timing_reset": (i32, [vp]),
+        "dmlmc_timing_get": (i32, [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class Context:
+    """A library context bound to a GPU and a HIP stream (torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        handle = C.c_void_p()
+        st = lib().dmlmc_create(C.byref(handle), device, C.c_void_p(stream.cuda_stream))
+        if st != OK:
+            raise DmlmcError(st, lib().dmlmc_last_error(None).decode())
+        self.h = handle
+        self.device = device
+        self.stream = stream
+
+    def check(self, st: int):
+        if st != OK:
+            raise DmlmcError(st, lib().dmlmc_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            lib().dmlmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- timing
+    def timing(self, enable: bool):
+        self.check(lib().dmlmc_timing_enable(self.h, 1 if enable else 0))
+
+    def timing_reset(self):
+        self.check(lib().dmlmc_timing_reset(self.h))
+
+    def timing_get(self, cls: str):
+        n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+        self.check(lib().dmlmc_timing_get(self.h, cls.encode(), C.byref(n), C.byref(ms), C.byref(b)))
+        return n.value, ms.value, b.value
+
+    # ---------------------------------------------------------------- noise
+    def z2_noise(self, n: int, seed: int, level: int, sample0: int, nrhs: int, prec: int = FP64):
+        dt = self.torch.complex128 if prec == FP64 else self.torch.complex64
+        out = self.torch.empty((nrhs, n), dtype=dt, device=f"cuda:{self.device}")
+        self.check(lib().dmlmc_z2_noise(self.h, n, seed, level, sample0, nrhs, C.c_void_p(_ptr(out)), prec))
+        return out
+
+
+class Hierarchy:
+    """Multigrid hierarchy of one gauge field (built on the device)."""
+
+    def __init__(self, ctx: Context, theta: np.ndarray, m0: float, aggs: Sequence[Sequence[int]],
+                 ntv: Sequence[int], n_inv: int = 3, seed: int = 7, antiperiodic: bool = True,
+                 import_tv: Optional[List[np.ndarray]] = None):
+        self.ctx = ctx
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        _, Lt, Lx = theta.shape
+        lat = Lattice(Lx, Lt, float(m0), 1 if antiperiodic else 0, theta.ctypes.data_as(C.POINTER(C.c_double)))
+        mgp = MGParams()
+        mgp.nlevels = len(aggs) + 1
+        for i, (a, n) in enumerate(zip(aggs, ntv)):
+            mgp.agg[i][0], mgp.agg[i][1] = int(a[0]), int(a[1])
+            mgp.ntv[i] = int(n)
+        mgp.n_inv = n_inv
+        mgp.seed = seed
+        keep = []
+        if import_tv is not None:
+            arr = (C.c_void_p * len(import_tv))()
+            for i, V in enumerate(import_tv):
+                Vc = np.ascontiguousarray(np.asarray(V, dtype=np.complex128).T)  # [ntv][n]
+                keep.append(Vc)
+                arr[i] = Vc.ctypes.data
+            mgp.import_tv = C.cast(arr, C.POINTER(C.c_void_p))
+            keep.append(arr)
+        handle = C.c_void_p()
+        ctx.check(lib().dmlmc_build_hierarchy(ctx.h, C.byref(lat), C.byref(mgp), C.byref(handle)))
+        self.h = handle
+        self.nlevels = mgp.nlevels
+        self.theta = theta
+
+    def close(self):
+        if self.h:
+            lib().dmlmc_free_hierarchy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level: int):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        st = lib().dmlmc_level_info(self.h, level, C.byref(a), C.byref(b), C.byref(c))
+        if st != OK:
+            raise DmlmcError(st, "level_info")
+        return a.value, b.value, c.value
+
+    def n(self, level: int) -> int:
+        Lx, Lt, d = self.level_info(level)
+        return Lx * Lt * d
+
+    def export(self, level: int, P: bool = False, Dc: bool = False, tv: bool = False):
+        out = {}
+        pP = pD = pT = None
+        if P:
+            out["P"] = np.zeros((self.n(level), self.n(level + 1)), dtype=np.complex128)
+            pP = out["P"].ctypes.data
+        if Dc:
+            Lx, Lt, d = self.level_info(level)
+            out["Dc"] = np.zeros((Lx * Lt, 5, d, d), dtype=np.complex128)
+            pD = out["Dc"].ctypes.data
+        if tv:
+            ntv = self._ntv(level)
+            out["tv"] = np.zeros((ntv, self.n(level)), dtype=np.complex128)
+            pT = out["tv"].ctypes.data
+        self.ctx.check(lib().dmlmc_export_level(self.ctx.h, self.h, level, pP, pD, pT))
+        return out
+
+    def _ntv(self, level: int) -> int:
+        _, _, dc = self.level_info(level + 1)
+        return dc // 2
+
+    # ---------------------------------------------------------------- operators
+    def apply(self, op: int, level: int, x, out, prec: int = FP64, arg: int = 0):
+        nrhs = x.shape[0] if op != OP_PROLONG else out.shape[0]
+        self.ctx.check(lib().dmlmc_apply(self.ctx.h, self.h, op, level, C.c_void_p(_ptr(x)),
+                                         C.c_void_p(_ptr(out)), nrhs, prec, arg))
+        return out
+
+    def solve(self, level: int, B, prec: int = FP64, rtol: float = 1e-10, maxiter: int = 2000, proj=None):
+        torch = self.ctx.torch
+        X = torch.empty_like(B)
+        stats = SolveStats()
+        st = lib().dmlmc_solve_multi_rhs(self.ctx.h, self.h, level, proj.h if proj is not None else None,
+                                         C.c_void_p(_ptr(B)), C.c_void_p(_ptr(X)), B.shape[0], B.shape[1], prec,
+                                         rtol, maxiter, C.byref(stats))
+        if st not in (OK,):
+            raise DmlmcError(st, lib().dmlmc_last_error(self.ctx.h).decode())
+        return X, stats
+
+    def set_deflation(self, d: Optional["Deflation"]):
+        st = lib().dmlmc_set_deflation(self.h, d.h if d is not None else None)
+        if st != OK:
+            raise DmlmcError(st, "set_deflation")
+
+
+class Deflation:
+    """Exact deflation of one level (normally the coarsest)."""
+
+    def __init__(self, hier: Hierarchy, level: int, k: int, eig_rtol: float = 1e-12,
+                 import_X: Optional[np.ndarray] = None, import_lambda: Optional[np.ndarray] = None):
+        self.hier = hier
+        ctx = hier.ctx
+        handle = C.c_void_p()
+        tr = C.c_double()
+        pX = plam = None
+        keep = []
+        if import_X is not None:
+            Xc = np.ascontiguousarray(np.asarray(import_X, dtype=np.complex128).T)  # [k][n]
+            lam = np.ascontiguousarray(import_lambda, dtype=np.float64)
+            keep += [Xc, lam]
+            pX = Xc.ctypes.data
+            plam = lam.ctypes.data_as(C.POINTER(C.c_double))
+        st = lib().dmlmc_deflate(ctx.h, hier.h, level, k, eig_rtol, pX, plam, C.byref(handle), C.byref(tr))
+        self.status = st
+        if st not in (OK, ENOCONV):
+            raise DmlmcError(st, lib().dmlmc_last_error(ctx.h).decode())
+        self.h = handle
+        self.tr_defl = tr.value
+        self.k = k
+        self.level = level
+
+    def info(self):
+        it, deg, res = C.c_int(), C.c_int64(), C.c_double()
+        st = lib().dmlmc_deflation_info(self.h, C.byref(it), C.byref(deg), C.byref(res))
+        if st != OK:
+            raise DmlmcError(st, "deflation_info")
+        return {"iters": it.value, "degree_sum": deg.value, "max_residual": res.value}
+
+    def export(self):
+        n = self.hier.n(self.level)
+        X = np.zeros((self.k, n), dtype=np.complex128)
+        lam = np.zeros(self.k, dtype=np.float64)
+        self.hier.ctx.check(lib().dmlmc_export_deflation(self.hier.ctx.h, self.h, X.ctypes.data,
+                                                         lam.ctypes.data_as(C.POINTER(C.c_double))))
+        return X, lam
+
+    def close(self):
+        if self.h:
+            lib().dmlmc_free_deflation(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class TraceEstimate:
+    trace: float
+    trace_imag: float
+    rel_err: float
+    N: List[int]
+    mean: List[complex]
+    var: List[float]
+    cost_s: List[float]
+    iters: List[int]
+    tr_defl: float
+    seconds: float
+    samples: Optional[List[np.ndarray]] = None
+
+
+def mlmc_trace(hier: Hierarchy, defl: Optional[Deflation], eps: float, noise_seed: int, n0: Sequence[int],
+               rhs_block: int, prec: int = FP64, rtol: float = 1e-10, fixed_counts: bool = False,
+               max_samples: Optional[Sequence[int]] = None, keep_samples: bool = False,
+               maxiter: int = 2000) -> TraceEstimate:
+    L = hier.nlevels
+    p = MLMCParams()
+    p.eps = eps
+    p.noise_seed = noise_seed
+    for l in range(L):
+        p.n0[l] = int(n0[l])
+        p.max_samples[l] = int(max_samples[l]) if max_samples is not None else 0
+    p.rhs_block = rhs_block
+    p.prec = prec
+    p.rtol = rtol
+    p.fixed_counts = 1 if fixed_counts else 0
+    p.maxiter = maxiter
+    bufs = []
+    if keep_samples:
+        if max_samples is None:
+            raise ValueError("keep_samples needs max_samples")
+        for l in range(L):
+            b = np.zeros(2 * int(max_samples[l]), dtype=np.float64)
+            bufs.append(b)
+            p.samples_out[l] = b.ctypes.data_as(C.POINTER(C.c_double))
+    r = TraceResult()
+    hier.ctx.check(lib().dmlmc_mlmc_trace(hier.ctx.h, hier.h, defl.h if defl is not None else None,
+                                          C.byref(p), C.byref(r)))
+    out = TraceEstimate(r.trace, r.trace_imag, r.rel_err, [r.N[l] for l in range(L)],
+                        [complex(r.mean_re[l], r.mean_im[l]) for l in range(L)], [r.var[l] for l in range(L)],
+                        [r.cost_s[l] for l in range(L)], [r.iters[l] for l in range(L)], r.tr_defl, r.t_trace_s)
+    if keep_samples:
+        out.samples = [bufs[l][: 2 * r.N[l]].view(np.complex128) for l in range(L)]
+    return out

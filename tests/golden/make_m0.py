@@ -19,7 +19,7 @@ from paper_2211_15383_amd.inputs import M0_FILE, WORKLOADS, batched_fields  # no
 
 # scan start per workload (default +0.1); the 1024^2 scan starts closer to the crossing
 # to keep the number of 2M-unknown factorisations small.
-M_START = {"schwinger1024": -0.06}
+M_START = {"schwinger1024": -0.04}
 
 
 def main(names):

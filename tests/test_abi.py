@@ -1,0 +1,57 @@
+"""The C ABI on the CPU: the library loads, exports every symbol include/dmlmc.h declares,
+and rejects invalid arguments with DMLMC_EINVAL before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "dmlmc.h")) as f:
+        text = f.read()
+    decl = r"^(?:dmlmc_status|void|const char\s*\*)\s*(dmlmc_[a-z0-9_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def test_header_matches_binding():
+    from paper_2211_15383_amd import dmlmc
+    assert sorted(dmlmc.EXPORTED) == _declared()
+
+
+def test_library_exports_all_symbols():
+    from paper_2211_15383_amd import dmlmc
+    lib = dmlmc.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.dmlmc_version().startswith(b"dmlmc")
+
+
+def test_invalid_arguments_without_device():
+    from paper_2211_15383_amd import dmlmc
+    lib = dmlmc.load()
+    h = C.c_void_p()
+    assert lib.dmlmc_create(None, 0, None) == dmlmc.EINVAL
+    assert lib.dmlmc_create(C.byref(h), -1, None) == dmlmc.EINVAL
+    assert b"device" in lib.dmlmc_last_error(None)
+    assert lib.dmlmc_build_hierarchy(None, None, None, None) == dmlmc.EINVAL
+    assert lib.dmlmc_solve_multi_rhs(None, None, 1, None, None, None, 1, 1, 0, 1e-10, 10, None) == dmlmc.EINVAL
+    assert lib.dmlmc_level_info(None, 1, None, None, None) == dmlmc.EINVAL
+    assert lib.dmlmc_deflation_info(None, None, None, None) == dmlmc.EINVAL
+    assert lib.dmlmc_set_deflation(None, None) == dmlmc.EINVAL
+    # destroy/free accept NULL
+    lib.dmlmc_destroy(None)
+    lib.dmlmc_free_hierarchy(None)
+    lib.dmlmc_free_deflation(None)
+
+
+def test_no_device_is_an_error_not_a_crash():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2211_15383_amd import dmlmc
+    lib = dmlmc.load()
+    h = C.c_void_p()
+    assert lib.dmlmc_create(C.byref(h), 0, None) == dmlmc.EHIP

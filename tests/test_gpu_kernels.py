@@ -1,0 +1,124 @@
+"""Parity of the single HIP operators with the CPU checker (GPU).
+
+Noise is compared bit-exactly; operators in FP64 to 1e-13 and in complex FP32 to 1e-6
+(relative 2-norm over the whole block), on lattices that span several workgroups and
+ragged tails.  Hierarchies are built on the device from the checker's test vectors
+(import path), so P and the Galerkin blocks are compared entry by entry.
+"""
+import numpy as np
+import pytest
+
+from oracle import multigrid as omg, noise as onoise, wilson as ow
+from paper_2211_15383_amd.inputs import link_angles
+
+from _helpers import oracle_hierarchy, random_vectors, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,seed,level,s0,nrhs", [(130, 11, 1, 0, 3), (2 * 16 * 16, 11, 2, 5, 7),
+                                                   (64 * 64 * 2, 2**63 + 5, 3, 2**40, 2), (1, 0, 0, 0, 1)])
+def test_noise_bit_exact(gpu, n, seed, level, s0, nrhs):
+    torch, dm, ctx = gpu
+    for prec in (dm.FP64, dm.MIXED):
+        x = ctx.z2_noise(n, seed, level, s0, nrhs, prec).cpu().numpy()
+        for r in range(nrhs):
+            ref = onoise.z2_noise(seed, level, s0 + r, n)
+            assert np.array_equal(x[r].real, ref), (prec, r)
+            assert np.all(x[r].imag == 0)
+
+
+def _gpu_hier(gpu, name, **kw):
+    torch, dm, ctx = gpu
+    W, m0, lv = oracle_hierarchy(name)
+    H = dm.Hierarchy(ctx, W.theta(), m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                     import_tv=[l.V for l in lv[:-1]], **kw)
+    return W, lv, H
+
+
+@pytest.mark.parametrize("Lx,Lt,nrhs", [(16, 16, 1), (12, 20, 3), (128, 128, 32), (8, 36, 5)])
+def test_wilson_stencil(gpu, Lx, Lt, nrhs):
+    torch, dm, ctx = gpu
+    theta = link_angles(Lx, Lt, 0.5, Lx * 1000 + Lt)
+    m0 = -0.07
+    H = dm.Hierarchy(ctx, theta, m0, [], [])
+    D = ow.dirac_operator(theta, m0)
+    x = random_vectors(D.shape[0], nrhs, 1)
+    ref = D @ x
+    for prec, dt, tol in ((dm.FP64, torch.complex128, 1e-13), (dm.MIXED, torch.complex64, 1e-6)):
+        xd = to_dev(torch, x, dt)
+        y = torch.empty_like(xd)
+        H.apply(dm.OP_D, 1, xd, y, prec)
+        assert rel_err(to_host(y), ref) < tol, prec
+    # gamma5-hermiticity through the GPU operator: <G5 y, D x> = <G5 D y, x>
+    xd = to_dev(torch, x, torch.complex128)
+    yv = random_vectors(D.shape[0], nrhs, 2)
+    yd = to_dev(torch, yv, torch.complex128)
+    Dx = torch.empty_like(xd)
+    G5Dy = torch.empty_like(yd)
+    H.apply(dm.OP_D, 1, xd, Dx, dm.FP64)
+    H.apply(dm.OP_GAMMA5_D, 1, yd, G5Dy, dm.FP64)
+    g5 = np.tile([1.0, -1.0], D.shape[0] // 2)
+    lhs = np.sum((g5[:, None] * yv).conj() * to_host(Dx), axis=0)
+    rhs = np.sum(to_host(G5Dy).conj() * x, axis=0)
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(lhs).max()
+
+
+@pytest.mark.parametrize("name", ["schwinger16", "tiny8x16", "rect24x16", "schwinger128"])
+def test_hierarchy_import_parity(gpu, name):
+    torch, dm, ctx = gpu
+    W, lv, H = _gpu_hier(gpu, name)
+    # the local QR of the (nearly collinear, after inverse iteration) test vectors
+    # amplifies rounding by the block condition number: 1e-11 absolute
+    for l in range(1, len(lv)):
+        e = H.export(l, P=True)
+        err = float(np.abs(e["P"] - lv[l - 1].P.toarray()).max())
+        assert err < 1e-11, ("P", l, err)
+        c = lv[l]
+        ref = omg.coarse_blocks(c.D, c.Lx, c.Lt, c.dofs)
+        Dc = H.export(l + 1, Dc=True)["Dc"]
+        err = float(np.abs(Dc - ref).max() / np.abs(ref).max())
+        assert err < 1e-11, ("Dc", l + 1, err)
+
+
+@pytest.mark.parametrize("name", ["schwinger16", "rect24x16", "schwinger128"])
+def test_transfer_and_coarse_operators(gpu, name):
+    torch, dm, ctx = gpu
+    W, lv, H = _gpu_hier(gpu, name)
+    for l in range(1, len(lv)):
+        P = lv[l - 1].P
+        nf, nc = P.shape
+        for nrhs in (1, 6, 33):
+            xf = random_vectors(nf, nrhs, l + nrhs)
+            xc = random_vectors(nc, nrhs, 10 * l + nrhs)
+            for prec, dt, tol in ((dm.FP64, torch.complex128, 1e-13), (dm.MIXED, torch.complex64, 1e-6)):
+                yc = torch.empty((nrhs, nc), dtype=dt, device="cuda:0")
+                H.apply(dm.OP_RESTRICT, l, to_dev(torch, xf, dt), yc, prec)
+                assert rel_err(to_host(yc), P.conj().T @ xf) < tol, ("R", l, prec)
+                yf = torch.empty((nrhs, nf), dtype=dt, device="cuda:0")
+                H.apply(dm.OP_PROLONG, l, to_dev(torch, xc, dt), yf, prec)
+                assert rel_err(to_host(yf), P @ xc) < tol, ("P", l, prec)
+                Dc = lv[l].D
+                yd = torch.empty((nrhs, nc), dtype=dt, device="cuda:0")
+                H.apply(dm.OP_D, l + 1, to_dev(torch, xc, dt), yd, prec)
+                assert rel_err(to_host(yd), Dc @ xc) < tol, ("Dc", l + 1, prec)
+
+
+@pytest.mark.parametrize("name", ["schwinger16", "schwinger128"])
+def test_smoother_properties(gpu, name):
+    """Smoothers keep the exact solution fixed and reduce the residual of a Z2 RHS."""
+    torch, dm, ctx = gpu
+    W, lv, H = _gpu_hier(gpu, name)
+    import scipy.sparse.linalg as spla
+    for l in range(1, len(lv)):
+        D = lv[l - 1].D
+        n = D.shape[0]
+        b = np.column_stack([onoise.z2_noise(3, l, i, n) for i in range(4)]).astype(np.complex128)
+        xs = spla.splu(D.tocsc()).solve(b)
+        out = to_dev(torch, xs, torch.complex128)
+        H.apply(dm.OP_SMOOTH, l, to_dev(torch, b, torch.complex128), out, dm.FP64, arg=2)
+        assert rel_err(to_host(out), xs) < 1e-12, ("fixed point", l)
+        x0 = torch.zeros((4, n), dtype=torch.complex128, device="cuda:0")
+        H.apply(dm.OP_SMOOTH, l, to_dev(torch, b, torch.complex128), x0, dm.FP64, arg=3)
+        r = b - D @ to_host(x0)
+        assert np.linalg.norm(r) < 0.9 * np.linalg.norm(b), ("reduction", l)

@@ -1,0 +1,117 @@
+"""Solves, deflation and sample parity against the CPU checker (GPU).
+
+* solve_multi_rhs at every level, FP64 and mixed precision: the residual is recomputed by
+  the checker's own sparse matvec and the solution compared with its sparse-LU solve;
+* deflation: the device eigensolver against dense eigh (eigenvalues, projector, small
+  trace term) and the deflation products (FP64 and FP32 matrix cores) against numpy;
+* MLMC samples: every sample value of a fixed-count run against the checker's
+  direct-solve sample values for the same noise indices (hierarchy and deflation
+  imported, so the comparison isolates the solves), error per sample measured as
+  |s_gpu - s_ref| / (|x^H D_l^-1 x| + |y^H D_{l+1}^-1 y|).
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import mlmc as omlmc, noise as onoise
+
+from _helpers import oracle_deflation, oracle_hierarchy, random_vectors, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_hier(gpu, name):
+    torch, dm, ctx = gpu
+    W, m0, lv = oracle_hierarchy(name)
+    H = dm.Hierarchy(ctx, W.theta(), m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                     import_tv=[l.V for l in lv[:-1]])
+    return W, lv, H
+
+
+@pytest.mark.parametrize("name", ["schwinger16", "rect24x16", "schwinger128"])
+@pytest.mark.parametrize("prec_name,rtol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_solve_every_level(gpu, name, prec_name, rtol):
+    torch, dm, ctx = gpu
+    prec = dm.FP64 if prec_name == "fp64" else dm.MIXED
+    W, lv, H = _gpu_hier(gpu, name)
+    for l in range(1, len(lv) + 1):
+        D = lv[l - 1].D
+        n = D.shape[0]
+        nrhs = 5
+        B = np.column_stack([onoise.z2_noise(9, l, i, n) for i in range(nrhs)]).astype(np.complex128)
+        X, st = H.solve(l, to_dev(torch, B), prec=prec, rtol=rtol, maxiter=3000)
+        Xh = to_host(X)
+        res = np.linalg.norm(B - D @ Xh, axis=0) / np.linalg.norm(B, axis=0)
+        assert res.max() <= rtol * 1.0001, (l, res.max(), st.iters)
+        ref = spla.splu(D.tocsc()).solve(B)
+        assert rel_err(Xh, ref) < rtol * 1e4, (l, rel_err(Xh, ref))
+
+
+@pytest.mark.parametrize("name,k", [("schwinger16", 16), ("rect24x16", 6), ("schwinger128", 32)])
+def test_eigensolver_against_dense(gpu, name, k):
+    torch, dm, ctx = gpu
+    W, lv, H = _gpu_hier(gpu, name)
+    ref = oracle_deflation(name, k)
+    d = dm.Deflation(H, len(lv), k, eig_rtol=1e-12)
+    assert d.status == dm.OK, d.info()
+    X, lam = d.export()
+    assert np.abs(np.abs(lam) - np.abs(ref.lam)).max() < 1e-10
+    g5 = lv[-1].gamma5.diagonal().real
+    Wg = (g5[None, :] * X).T
+    Pi = Wg @ Wg.conj().T
+    Pr = ref.W @ ref.W.conj().T
+    assert np.abs(Pi - Pr).max() < 1e-8
+    assert abs(d.tr_defl - ref.tr_defl) < 1e-9 * abs(ref.tr_defl)
+
+
+@pytest.mark.parametrize("name,k", [("schwinger16", 16), ("schwinger128", 32)])
+def test_deflation_products(gpu, name, k):
+    torch, dm, ctx = gpu
+    W, lv, H = _gpu_hier(gpu, name)
+    ref = oracle_deflation(name, k)
+    d = dm.Deflation(H, len(lv), k, import_X=ref.X, import_lambda=ref.lam)
+    assert abs(d.tr_defl - ref.tr_defl) < 1e-11 * abs(ref.tr_defl)
+    H.set_deflation(d)
+    n = ref.W.shape[0]
+    for nrhs in (1, 17, 32):
+        x = random_vectors(n, nrhs, nrhs)
+        C_ref = ref.W.conj().T @ x
+        Y_ref = x - ref.W @ C_ref
+        xd = to_dev(torch, x)
+        for prec, tol in ((dm.FP64, 1e-13), (dm.MIXED, 2e-6)):
+            C = torch.empty((nrhs, k), dtype=torch.complex128, device="cuda:0")
+            H.apply(dm.OP_DEFL_C, len(lv), xd, C, prec)
+            assert rel_err(to_host(C), C_ref) < tol, ("C", prec, nrhs)
+            Y = torch.empty_like(xd)
+            H.apply(dm.OP_DEFL_P, len(lv), xd, Y, prec)
+            assert rel_err(to_host(Y), Y_ref) < tol, ("Y", prec, nrhs)
+    H.set_deflation(None)
+
+
+@pytest.mark.parametrize("name,prec_name,rtol,tol", [("schwinger16", "fp64", 1e-13, 1e-10),
+                                                     ("schwinger16", "mixed", 1e-10, 1e-6),
+                                                     ("rect24x16", "fp64", 1e-13, 1e-10),
+                                                     ("schwinger128", "mixed", 1e-10, 1e-6)])
+def test_sample_parity(gpu, name, prec_name, rtol, tol):
+    torch, dm, ctx = gpu
+    prec = dm.FP64 if prec_name == "fp64" else dm.MIXED
+    W, lv, H = _gpu_hier(gpu, name)
+    k = W.k_defl
+    ref = oracle_deflation(name, k)
+    d = dm.Deflation(H, len(lv), k, import_X=ref.X, import_lambda=ref.lam)
+    L = len(lv)
+    nsamp = 12
+    res = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [nsamp] * L, 5, prec=prec, rtol=rtol, fixed_counts=True,
+                        max_samples=[nsamp] * L, keep_samples=True)
+    assert res.N == [nsamp + (-nsamp) % 5] * L or all(n >= nsamp for n in res.N)
+    solver = omlmc.DirectSolver(lv)
+    for l in range(1, L + 1):
+        got = res.samples[l - 1][:nsamp]
+        for i in range(nsamp):
+            if l < L:
+                s, t1, t2 = omlmc.difference_sample(lv, solver, W.noise_seed, l, i)
+                scale = abs(t1) + abs(t2)
+            else:
+                s = omlmc.coarsest_sample(lv, solver, ref, W.noise_seed, i)
+                scale = abs(s)
+            assert abs(got[i] - s) / scale < tol, (l, i, got[i], s)
