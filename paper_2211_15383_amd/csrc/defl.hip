@@ -4,8 +4,10 @@
 //     real products per complex product) with FP64 accumulation across K-chunks;
 //   * the eigensolver for the k eigenpairs of Q = Gamma5 D_L with the smallest |lambda|:
 //     Chebyshev-filtered subspace iteration on Q^2 (filter damps [a, ||Q||^2], a = the
-//     largest Ritz value of Q^2 kept in the subspace), CholQR2 orthonormalisation and
-//     Rayleigh-Ritz on Q, all FP64 on the device except the small dense eigenproblem.
+//     largest Ritz value of Q^2 kept in the subspace, degree chosen from the gap to the
+//     k-th Ritz value), CholQR2 orthonormalisation, Rayleigh-Ritz with Q^2 on the subspace
+//     and then with Q on its k leading vectors; all FP64 on the device except the small
+//     dense eigenproblems.
 #include <algorithm>
 #include <cmath>
 
@@ -283,52 +285,48 @@ EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout) 
   launch_z4(ctx, Y, n, 0x5eed5eedull, level + 64, 0, ns);
   if (!cholqr2(H, Y, T, ns, n)) throw DmlmcError(DMLMC_ENUMERIC, "eigensolver: start block is rank-deficient");
   double a = bq / 64.0;
-  std::vector<double> theta;
   std::vector<std::complex<double>> S;
   const int maxit = 100;
   int it = 0;
-  std::vector<int> sel(k);
+  std::vector<double> mu, th1;
+  std::vector<std::complex<double>> S1;
   for (; it < maxit; ++it) {
-    // Rayleigh-Ritz on Q
+    // Rayleigh-Ritz with Q^2 on the whole subspace: Y ordered by the Ritz values mu of Q^2
     applyQ(ctx, L, Y, Z, ns);
-    std::vector<std::complex<double>> Hm = gram(H, Y, ns, Z, ns, n);
-    eigh_jacobi(ns, Hm, theta, S);
+    std::vector<std::complex<double>> H2 = gram(H, Z, ns, Z, ns, n);
+    eigh_jacobi(ns, H2, mu, S);
     rotate(H, Y, ns, S, ns, T, n);
     std::swap(Y, T);
-    rotate(H, Z, ns, S, ns, T, n);
-    std::swap(Z, T);
-    // wanted: k smallest |theta| (ties: theta ascending)
-    std::vector<int> order(ns);
-    for (int i = 0; i < ns; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int i, int j) {
-      const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
-      return ai < aj || (ai == aj && theta[i] < theta[j]);
-    });
-    for (int i = 0; i < k; ++i) sel[i] = order[i];
-    // residual norms of the wanted pairs
-    double* th = (double*)hier_buf(H, "eg_th", 0, sizeof(double) * ns);
-    HIPCHK(hipMemcpyAsync(th, theta.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
-    hipLaunchKernelGGL(ritz_res_kernel, dim3((unsigned)ceil_div(n * ns, 256)), dim3(256), 0, ctx->stream, Z, Y, th, n,
-                       ns);
+    // Rayleigh-Ritz with Q on the k leading vectors (their span converges to the invariant
+    // subspace of the k smallest |lambda|, which Q maps into itself; an RR with Q on the
+    // whole subspace would give spurious Ritz values near 0 from pairs +lambda, -lambda'
+    // with similar |lambda| at the subspace boundary)
+    applyQ(ctx, L, Y, Z, k);
+    std::vector<std::complex<double>> H1 = gram(H, Y, k, Z, k, n);
+    eigh_jacobi(k, H1, th1, S1);
+    rotate(H, Y, k, S1, k, Q1, n);   // Ritz vectors of Q -> Q1[0..k)
+    rotate(H, Z, k, S1, k, Y0, n);   // Q times them -> Y0[0..k)
+    double* th = (double*)hier_buf(H, "eg_th", 0, sizeof(double) * k);
+    HIPCHK(hipMemcpyAsync(th, th1.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(ritz_res_kernel, dim3((unsigned)ceil_div(n * k, 256)), dim3(256), 0, ctx->stream, Y0, Q1, th, n,
+                       k);
     LAUNCH_CHECK();
-    double* nr = (double*)hier_buf(H, "eg_nr", 0, sizeof(double) * ns);
-    launch_norms2<double>(ctx, Z, n, ns, n, nr);
-    std::vector<double> rn(ns);
-    HIPCHK(hipMemcpyAsync(rn.data(), nr, sizeof(double) * ns, hipMemcpyDeviceToHost, ctx->stream));
+    double* nr = (double*)hier_buf(H, "eg_nr", 0, sizeof(double) * k);
+    launch_norms2<double>(ctx, Y0, n, k, n, nr);
+    std::vector<double> rn(k);
+    HIPCHK(hipMemcpyAsync(rn.data(), nr, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     double worst = 0.0;
-    for (int i = 0; i < k; ++i) worst = std::max(worst, std::sqrt(rn[sel[i]]));
+    for (int i = 0; i < k; ++i) worst = std::max(worst, std::sqrt(rn[i]));
     res.max_residual = worst / qnorm;
     if (worst <= tol * qnorm) break;
+    if (it + 1 == maxit) break;
     // filter interval: damp [a, bq] with a = the largest Ritz value of Q^2 in the subspace
-    double amax = 0.0;
-    for (int i = 0; i < ns; ++i) amax = std::max(amax, theta[i] * theta[i]);
-    a = std::min(std::max(amax, 1e-12 * bq), 0.5 * bq);
+    a = std::min(std::max(mu[ns - 1], 1e-12 * bq), 0.5 * bq);
     const double e = 0.5 * (bq - a), c = 0.5 * (bq + a);
     // degree: the filter should amplify the largest wanted Ritz value of Q^2 (lk) over the
     // damped interval by about e^4 per outer step: T_deg(x_k) = cosh(deg acosh(x_k))
-    double lk = 0.0;
-    for (int i = 0; i < k; ++i) lk = std::max(lk, theta[sel[i]] * theta[sel[i]]);
+    const double lk = std::max(mu[k - 1], 0.0);
     const double xk = 1.0 + 2.0 * std::max(a - lk, 1e-3 * a) / (bq - a);
     const int deg = (int)std::min(400.0, std::max(8.0, std::ceil(4.0 / std::acosh(xk))));
     res.degree_sum += deg;
@@ -358,12 +356,18 @@ EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout) 
   }
   res.iters = it;
   res.converged = res.max_residual <= tol;
-  // gather the wanted pairs in order of |lambda| (then lambda)
+  // the wanted pairs (Ritz vectors in Q1) in order of |lambda|, then lambda
+  std::vector<int> order(k);
+  for (int i = 0; i < k; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int i, int j) {
+    const double ai = std::fabs(th1[i]), aj = std::fabs(th1[j]);
+    return ai < aj || (ai == aj && th1[i] < th1[j]);
+  });
   res.lambda.resize(k);
   for (int i = 0; i < k; ++i) {
-    res.lambda[i] = theta[sel[i]];
-    HIPCHK(hipMemcpyAsync(Xout + (int64_t)i * n, Y + (int64_t)sel[i] * n, sizeof(c128) * n, hipMemcpyDeviceToDevice,
-                          ctx->stream));
+    res.lambda[i] = th1[order[i]];
+    HIPCHK(hipMemcpyAsync(Xout + (int64_t)i * n, Q1 + (int64_t)order[i] * n, sizeof(c128) * n,
+                          hipMemcpyDeviceToDevice, ctx->stream));
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return res;

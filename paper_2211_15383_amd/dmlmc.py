@@ -7,8 +7,10 @@ library is missing or fails to load, importing this module raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -110,6 +112,21 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+# Library objects still alive at interpreter exit are released child-first (deflations,
+# hierarchies, then contexts) before the HIP runtime shuts down.
+_LIVE = {"defl": weakref.WeakSet(), "hier": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+
+
+@atexit.register
+def _release_all():
+    for kind in ("defl", "hier", "ctx"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
 class Context:
     """A library context bound to a GPU and a HIP stream (torch's current stream)."""
 
@@ -125,6 +142,7 @@ class Context:
         self.h = handle
         self.device = device
         self.stream = stream
+        _LIVE["ctx"].add(self)
 
     def check(self, st: int):
         if st != OK:
@@ -192,6 +210,7 @@ class Hierarchy:
         self.h = handle
         self.nlevels = mgp.nlevels
         self.theta = theta
+        _LIVE["hier"].add(self)
 
     def close(self):
         if self.h:
@@ -285,6 +304,7 @@ class Deflation:
         self.tr_defl = tr.value
         self.k = k
         self.level = level
+        _LIVE["defl"].add(self)
 
     def info(self):
         it, deg, res = C.c_int(), C.c_int64(), C.c_double()
