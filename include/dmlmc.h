@@ -240,8 +240,23 @@ dmlmc_status dmlmc_apply(dmlmc_ctx *ctx, const dmlmc_hier *h, int op, int level,
 dmlmc_status dmlmc_z2_noise(dmlmc_ctx *ctx, int64_t n, uint64_t seed, int level, int64_t sample0,
                             int nrhs, void *out, dmlmc_precision prec);
 
-/* Attaches (or with d = NULL detaches) a deflation used by DMLMC_OP_DEFL_*. */
+/* Attaches (or with d = NULL detaches) a deflation used by DMLMC_OP_DEFL_* and, when it is
+ * of the coarsest level, by the coarsest solve inside every V-cycle (exact inverse on the
+ * deflation space, GMRES on the projected rest).  The caller keeps d alive while attached.
+ * dmlmc_mlmc_trace attaches its coarsest deflation for the duration of the call. */
 dmlmc_status dmlmc_set_deflation(dmlmc_hier *h, const dmlmc_defl *d);
+
+/* ---------------------------------------------------------------- solver parameters
+ * Parameters of the solver that change iteration counts and speed but not the solution
+ * (every solve still stops at its FP64 residual tolerance): SAP local minimal-residual
+ * iterations, pre/post smoothing sweeps of the V-cycle, fixed GMRES iterations of the
+ * coarsest solve without / with an attached coarsest deflation, and the FGMRES restart
+ * length (at most 31).  Values < 0 keep the current setting. */
+typedef struct {
+  int sap_mr_iters, nu_pre, nu_post, coarsest_iters, coarsest_iters_defl, restart;
+} dmlmc_solver_params;
+dmlmc_status dmlmc_set_solver_params(dmlmc_hier *h, const dmlmc_solver_params *p);
+dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p);
 
 /* ---------------------------------------------------------------- kernel timing
  * When enabled, the library brackets every launch of the named kernel classes with HIP

@@ -22,7 +22,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdmlmc.so")
 ARCH = "gfx950"
 
-SOURCES = ["stencil.hip", "blas.hip", "solver.hip", "setup.hip", "defl.hip", "mlmc.hip", "capi.hip",
+SOURCES = ["stencil.hip", "blas.hip", "gram.hip", "solver.hip", "setup.hip", "defl.hip", "mlmc.hip", "capi.hip",
            "eigh_host.cpp"]
 
 

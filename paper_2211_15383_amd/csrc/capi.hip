@@ -392,6 +392,35 @@ dmlmc_status dmlmc_set_deflation(dmlmc_hier* h, const dmlmc_defl* d) {
   if (!h) return DMLMC_EINVAL;
   if (d && d->ctx != h->ctx) return DMLMC_ESTATE;
   h->attached = d;
+  h->coarse_defl = (d && d->level == (int)h->lv.size()) ? d : nullptr;
+  return DMLMC_OK;
+}
+
+dmlmc_status dmlmc_set_solver_params(dmlmc_hier* h, const dmlmc_solver_params* p) {
+  if (!h || !p) return DMLMC_EINVAL;
+  auto ok = [](int v, int lo, int hi) { return v < 0 || (v >= lo && v <= hi); };
+  const int maxb = gs_max_basis() - 1;
+  if (!ok(p->sap_mr_iters, 0, 64) || !ok(p->nu_pre, 0, 16) || !ok(p->nu_post, 0, 16) ||
+      !ok(p->coarsest_iters, 1, maxb) || !ok(p->coarsest_iters_defl, 1, maxb) || !ok(p->restart, 2, maxb))
+    return DMLMC_EINVAL;
+  if (p->nu_pre == 0 && p->nu_post == 0) return DMLMC_EINVAL;
+  if (p->sap_mr_iters >= 0) h->sap_mr_iters = p->sap_mr_iters;
+  if (p->nu_pre >= 0) h->nu_pre = p->nu_pre;
+  if (p->nu_post >= 0) h->nu_post = p->nu_post;
+  if (p->coarsest_iters >= 0) h->coarsest_iters = p->coarsest_iters;
+  if (p->coarsest_iters_defl >= 0) h->coarsest_iters_defl = p->coarsest_iters_defl;
+  if (p->restart >= 0) h->restart = p->restart;
+  return DMLMC_OK;
+}
+
+dmlmc_status dmlmc_get_solver_params(const dmlmc_hier* h, dmlmc_solver_params* p) {
+  if (!h || !p) return DMLMC_EINVAL;
+  p->sap_mr_iters = h->sap_mr_iters;
+  p->nu_pre = h->nu_pre;
+  p->nu_post = h->nu_post;
+  p->coarsest_iters = h->coarsest_iters;
+  p->coarsest_iters_defl = h->coarsest_iters_defl;
+  p->restart = h->restart;
   return DMLMC_OK;
 }
 

@@ -184,9 +184,13 @@ struct dmlmc_hier {
   int n_inv = 3;
   int64_t setup_iters = 0;
   const dmlmc_defl* attached = nullptr;
+  // deflation of the coarsest level used inside V-cycles (exact solve on its span, GMRES
+  // on the rest); set for the duration of an estimate, or by dmlmc_set_deflation
+  const dmlmc_defl* coarse_defl = nullptr;
+  int coarsest_iters_defl = 8;
   // solver knobs (not part of the math; iteration counts only)
-  int sap_mr_iters = 4;
-  int nu_pre = 0, nu_post = 2;
+  int sap_mr_iters = 2;
+  int nu_pre = 0, nu_post = 3;
   int coarsest_iters = 24;
   int restart = 16;
   std::vector<std::unique_ptr<Workspace>> ws;  // indexed by level-1
@@ -199,6 +203,8 @@ struct dmlmc_defl {
   int64_t n = 0;
   DevBuf X64;     // eigenvectors of Q, [k][n]
   DevBuf W64, W32;// Gamma5 X, [k][n]
+  DevBuf X32;     // eigenvectors of Q in FP32, [k][n]
+  DevBuf lam_dev; // eigenvalues on the device, [k]
   std::vector<double> lambda;
   double tr_defl = 0.0;
   int eig_iters = 0;            // outer subspace iterations (0 when imported)
@@ -248,6 +254,11 @@ void launch_xmy(dmlmc_ctx* ctx, const Cx<R>* b, Cx<R>* y, int64_t n, int nrhs, i
 // x64 += (double) e32
 template <typename RE>
 void launch_add_cast(dmlmc_ctx* ctx, const Cx<RE>* e, c128* x, int64_t n, int nrhs, int64_t lde, int64_t ldx);
+// x (RX) += e (FP64), [nrhs][n]
+template <typename RX>
+void launch_add_cast_to(dmlmc_ctx* ctx, const c128* e, Cx<RX>* x, int64_t n, int nrhs);
+// y[r] = sc[r] * x[r] (complex FP32, per-RHS FP64 scale)
+void launch_scale_vec(dmlmc_ctx* ctx, const c64* x, const double* sc, c64* y, int64_t n, int nrhs);
 // Z2 noise
 template <typename R>
 void launch_z2(dmlmc_ctx* ctx, Cx<R>* out, int64_t n, uint64_t seed, int level, int64_t sample0, int nrhs,

@@ -22,5 +22,9 @@ void defl_coeffs_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, int b,
                       DevBuf& scratch);
 void defl_project_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, c128* Y, int b, int64_t ldx, int64_t ldy,
                        const c128* C);
+// b -> (r, e0) with C = W^H b, r = b - W C = b - D e0, e0 = X Lambda^-1 C (exact inverse on
+// the deflation space), for a deflated coarsest-level solve; FP32 matrix cores for MIXED.
+void defl_coarse_split(dmlmc_hier* H, const dmlmc_defl* D, const c128* b, int nrhs, c128* r, c128* e0,
+                       dmlmc_precision prec);
 // X <- (I - W W^H) X; FP64 kernels for DMLMC_FP64, FP32 matrix-core kernels for DMLMC_MIXED.
 void defl_apply(dmlmc_hier* H, const dmlmc_defl* D, c128* X, int b, int64_t ldx, dmlmc_precision prec);

@@ -76,7 +76,7 @@ __global__ void defl_c_reduce_kernel(const c128* __restrict__ part, int nchunks,
 // Y = X - W C on one 16 (p) x 16 (r) tile: A[p][i] = W[i][p], B[i][r] = C[r][i].
 __global__ __launch_bounds__(64) void defl_p_mfma_kernel(const c64* __restrict__ W, int k, const c128* __restrict__ C,
                                                          const c128* __restrict__ X, c128* __restrict__ Y, int b,
-                                                         int64_t n, int64_t ldx, int64_t ldy) {
+                                                         int64_t n, int64_t ldx, int64_t ldy, double xscale) {
   const int lane = threadIdx.x;
   const int64_t p0 = (int64_t)blockIdx.x * 16;
   const int r0 = blockIdx.y * 16;
@@ -104,10 +104,19 @@ __global__ __launch_bounds__(64) void defl_p_mfma_kernel(const c64* __restrict__
   for (int v = 0; v < 4; ++v) {
     const int64_t p = p0 + 4 * kk + v;
     if (p < n) {
-      const c128 xv = X[(int64_t)r * ldx + p];
-      Y[(int64_t)r * ldy + p] = cmk(xv.x - (double)dre[v], xv.y - (double)dim[v]);
+      const c128 xv = xscale != 0.0 ? X[(int64_t)r * ldx + p] : cmk(0.0, 0.0);
+      Y[(int64_t)r * ldy + p] = cmk(xscale * xv.x - (double)dre[v], xscale * xv.y - (double)dim[v]);
     }
   }
+}
+
+// Cs[r][i] = sgn * C[r][i] / lambda_i
+__global__ void scale_coeffs_kernel(const c128* __restrict__ C, const double* __restrict__ lam, int k, int b,
+                                    double sgn, c128* __restrict__ Cs) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * b) return;
+  const int i = (int)(t % k);
+  Cs[t] = (sgn / lam[i]) * C[t];
 }
 
 // row-sum bound of |Q| = |D| (Gamma5 only flips signs): max_row sum_j |A[s][dir][i][j]|
@@ -179,8 +188,41 @@ void defl_project_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, c128*
   KTimer kt(ctx, "defl_gemm", 8.0 * D->n * D->k * b);
   dim3 grid((unsigned)ceil_div(D->n, 16), (unsigned)ceil_div(b, 16));
   hipLaunchKernelGGL(defl_p_mfma_kernel, grid, dim3(64), 0, ctx->stream, D->W32.as<c64>(), D->k, C, X, Y, b, D->n,
-                     ldx, ldy);
+                     ldx, ldy, 1.0);
   LAUNCH_CHECK();
+}
+
+// Exact solve on the deflation space: with Q x_i = lambda_i x_i, D^-1 W W^H = X Lambda^-1 W^H,
+// so for b:  C = W^H b,  e0 = X Lambda^-1 C  and  b - D e0 = (I - W W^H) b = r.
+void defl_coarse_split(dmlmc_hier* H, const dmlmc_defl* D, const c128* b, int nrhs, c128* r, c128* e0,
+                       dmlmc_precision prec) {
+  dmlmc_ctx* ctx = H->ctx;
+  const int64_t n = D->n;
+  const int k = D->k;
+  c128* C = (c128*)hier_buf(H, "dc_C", D->level, sizeof(c128) * (size_t)k * nrhs);
+  c128* Cs = (c128*)hier_buf(H, "dc_Cs", D->level, sizeof(c128) * (size_t)k * nrhs);
+  const unsigned g = (unsigned)ceil_div((int64_t)k * nrhs, 256);
+  if (prec == DMLMC_MIXED) {
+    defl_coeffs_mfma(ctx, D, b, nrhs, n, C, hier_devbuf(H, "dc_part", D->level));
+    defl_project_mfma(ctx, D, b, r, nrhs, n, n, C);
+    hipLaunchKernelGGL(scale_coeffs_kernel, dim3(g), dim3(256), 0, ctx->stream, C, D->lam_dev.as<double>(), k, nrhs,
+                       -1.0, Cs);
+    LAUNCH_CHECK();
+    KTimer kt(ctx, "defl_gemm", 8.0 * n * k * nrhs);
+    dim3 grid((unsigned)ceil_div(n, 16), (unsigned)ceil_div(nrhs, 16));
+    hipLaunchKernelGGL(defl_p_mfma_kernel, grid, dim3(64), 0, ctx->stream, D->X32.as<c64>(), k, Cs, b, e0, nrhs, n, n,
+                       n, 0.0);
+    LAUNCH_CHECK();
+  } else {
+    defl_coeffs_fp64(ctx, D, b, nrhs, n, C);
+    HIPCHK(hipMemcpyAsync(r, b, sizeof(c128) * (size_t)n * nrhs, hipMemcpyDeviceToDevice, ctx->stream));
+    defl_project_fp64(ctx, D, r, nrhs, n, C);
+    hipLaunchKernelGGL(scale_coeffs_kernel, dim3(g), dim3(256), 0, ctx->stream, C, D->lam_dev.as<double>(), k, nrhs,
+                       -1.0, Cs);
+    LAUNCH_CHECK();
+    launch_fill_zero<c128>(ctx, e0, (size_t)n * nrhs);
+    launch_multiaxpy<double>(ctx, D->X64.as<c128>(), k, e0, n, nrhs, n, n, Cs, k, 0, 1.0);
+  }
 }
 
 // X <- (I - W W^H) X  (in place, precision per prec)
@@ -383,6 +425,10 @@ void defl_finish(dmlmc_hier* H, dmlmc_defl* D) {
   LAUNCH_CHECK();
   D->W32.alloc(sizeof(c64) * (size_t)D->k * n);
   launch_cast<float, double>(ctx, D->W64.as<c128>(), D->W32.as<c64>(), n * D->k, 1, 0, 0);
+  D->X32.alloc(sizeof(c64) * (size_t)D->k * n);
+  launch_cast<float, double>(ctx, D->X64.as<c128>(), D->X32.as<c64>(), n * D->k, 1, 0, 0);
+  D->lam_dev.alloc(sizeof(double) * D->k);
+  HIPCHK(hipMemcpyAsync(D->lam_dev.p, D->lambda.data(), sizeof(double) * D->k, hipMemcpyHostToDevice, ctx->stream));
   // tr(D^-1 Pi) = sum_i x_i^H Gamma5 x_i / lambda_i = sum_i <x_i, w_i> / lambda_i
   c128* dd = (c128*)hier_buf(H, "df_dd", D->level, sizeof(c128) * D->k);
   launch_dots<double, double>(ctx, D->X64.as<c128>(), D->W64.as<c128>(), n, D->k, n, n, dd);

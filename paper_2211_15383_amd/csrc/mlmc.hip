@@ -76,6 +76,13 @@ static int sample_block(dmlmc_hier* H, const dmlmc_defl* defl, int l, int64_t i0
 
 void run_mlmc(dmlmc_hier* H, const dmlmc_defl* defl, const dmlmc_mlmc_params* p, dmlmc_trace_result* res) {
   const int L = (int)H->lv.size();
+  // the coarsest deflation also serves the coarsest solve inside every V-cycle
+  struct Restore {
+    dmlmc_hier* H;
+    const dmlmc_defl* prev;
+    ~Restore() { H->coarse_defl = prev; }
+  } restore{H, H->coarse_defl};
+  if (defl) H->coarse_defl = defl;
   const int blk = p->rhs_block;
   const double t0 = now_s();
   std::vector<std::vector<std::complex<double>>> S(L);

@@ -12,6 +12,10 @@ struct Workspace {
 void* hier_buf(dmlmc_hier* H, const char* name, int level, size_t bytes);
 
 DevBuf& hier_devbuf(dmlmc_hier* H, const char* name, int level);
+// As hier_buf, zero-filled when (re)allocated (for self-resetting completion counters).
+void* hier_buf_zeroed(dmlmc_hier* H, const char* name, int level, size_t bytes);
+// Largest Krylov basis (vectors) the fused Gram-Schmidt passes accept.
+int gs_max_basis();
 
 struct KrylovArrays {
   int m = 0, hld = 0;
@@ -25,12 +29,20 @@ struct KrylovArrays {
   double* nrm2 = nullptr;
   double* res = nullptr;
   double* invb = nullptr;
+  int* counter = nullptr;  // [nrhs] completion counters of the fused reductions (self-resetting)
 };
 KrylovArrays krylov_arrays(dmlmc_hier* H, const char* prefix, int level, int m, int nrhs);
 void krylov_init(dmlmc_ctx* ctx, const KrylovArrays& k, int nrhs);
 template <typename RV>
 void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs, const KrylovArrays& k);
+// Single-pass form: unnormalised complex-FP32 basis u_i with scales s_i = 1/||u_i||
+// (scale[i][nrhs]); w is the new vector (complex FP32 or FP64); FP64 arithmetic.
+template <typename RW>
+void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, int j, int64_t n, int nrhs,
+                       const KrylovArrays& k);
 void krylov_solution(dmlmc_ctx* ctx, const KrylovArrays& k, int iters, int nrhs);
+// y[r][i] *= scale[i][r] for i < iters
+void krylov_scale_y(dmlmc_ctx* ctx, const KrylovArrays& k, const double* scale, int iters, int nrhs);
 template <typename RZ, typename RX>
 void launch_combine(dmlmc_ctx* ctx, const Cx<RZ>* Z, int iters, const KrylovArrays& k, Cx<RX>* x, int64_t n, int nrhs);
 template <typename RV>

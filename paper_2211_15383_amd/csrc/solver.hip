@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "defl.h"
 #include "solver.h"
 
 namespace {
@@ -27,53 +28,6 @@ __global__ void init_cycle_kernel(const double* __restrict__ nrm2, c128* __restr
   res[r] = beta;
 }
 
-// Column j of the Hessenberg matrix from the two Gram-Schmidt passes and ||w||; applies
-// the previous Givens rotations, forms the new one, updates g and the residual estimate.
-__global__ void arnoldi_finish_kernel(int j, int m, const c128* __restrict__ h1, const c128* __restrict__ h2,
-                                      int hld, const double* __restrict__ nrm2, c128* __restrict__ H,
-                                      double* __restrict__ cs, c128* __restrict__ sn, c128* __restrict__ g,
-                                      double* __restrict__ res, double* __restrict__ invb, int nrhs) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  c128* col = H + (int64_t)r * (m + 1) * m + (int64_t)j * (m + 1);
-  for (int i = 0; i <= j; ++i) col[i] = h1[r * hld + i] + h2[r * hld + i];
-  const double beta = sqrt(fmax(nrm2[r], 0.0));
-  for (int i = 0; i < j; ++i) {
-    const double c = cs[r * m + i];
-    const c128 s = sn[r * m + i];
-    const c128 a = col[i], b = col[i + 1];
-    col[i] = c * a + s * b;
-    col[i + 1] = c * b - conj(s) * a;
-  }
-  const c128 a = col[j];
-  const double aa = sqrt(cabs2(a));
-  const double rho = sqrt(aa * aa + beta * beta);
-  double c;
-  c128 s;
-  if (rho == 0.0) {
-    c = 1.0;
-    s = cmk(0.0, 0.0);
-    col[j] = cmk(0.0, 0.0);
-  } else if (aa == 0.0) {
-    c = 0.0;
-    s = cmk(1.0, 0.0);
-    col[j] = cmk(beta, 0.0);
-  } else {
-    const c128 ph = cmk(a.x / aa, a.y / aa);
-    c = aa / rho;
-    s = (beta / rho) * ph;
-    col[j] = rho * ph;
-  }
-  cs[r * m + j] = c;
-  sn[r * m + j] = s;
-  c128* gr = g + (int64_t)r * (m + 1);
-  const c128 gj = gr[j];
-  gr[j + 1] = cmk(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));  // -conj(s) g_j
-  gr[j] = c * gj;
-  res[r] = sqrt(cabs2(gr[j + 1]));
-  invb[r] = beta > 0.0 ? 1.0 / beta : 0.0;
-}
-
 // y = R^-1 g over the first k columns (upper triangular, zero pivots give zero).
 __global__ void backsub_kernel(int k, int m, const c128* __restrict__ H, const c128* __restrict__ g,
                                c128* __restrict__ y, int nrhs) {
@@ -88,6 +42,12 @@ __global__ void backsub_kernel(int k, int m, const c128* __restrict__ H, const c
     y[r * m + i] = dd > 0.0 ? cmk((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd)
                             : cmk(0.0, 0.0);
   }
+}
+
+__global__ void scale_y_kernel(c128* __restrict__ y, int m, const double* __restrict__ scale, int iters, int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  for (int i = 0; i < iters; ++i) y[r * m + i] = scale[(int64_t)i * nrhs + r] * y[r * m + i];
 }
 
 // v_out (RV) = w * invb[r]
@@ -132,6 +92,17 @@ void* hier_buf(dmlmc_hier* H, const char* name, int level, size_t bytes) {
   return b.p;
 }
 
+void* hier_buf_zeroed(dmlmc_hier* H, const char* name, int level, size_t bytes) {
+  if ((int)H->ws.size() < (int)H->lv.size() + 1) H->ws.resize(H->lv.size() + 1);
+  if (!H->ws[level]) H->ws[level].reset(new Workspace());
+  DevBuf& b = H->ws[level]->bufs[name];
+  if (b.bytes < bytes) {
+    b.alloc(bytes);
+    HIPCHK(hipMemsetAsync(b.p, 0, bytes, H->ctx->stream));
+  }
+  return b.p;
+}
+
 DevBuf& hier_devbuf(dmlmc_hier* H, const char* name, int level) {
   hier_buf(H, name, level, 0);
   return H->ws[level]->bufs[name];
@@ -154,6 +125,7 @@ KrylovArrays krylov_arrays(dmlmc_hier* H, const char* prefix, int level, int m, 
   k.nrm2 = (double*)hier_buf(H, (p + "n2").c_str(), level, sizeof(double) * nrhs);
   k.res = (double*)hier_buf(H, (p + "res").c_str(), level, sizeof(double) * nrhs);
   k.invb = (double*)hier_buf(H, (p + "ib").c_str(), level, sizeof(double) * nrhs);
+  k.counter = (int*)hier_buf_zeroed(H, (p + "cnt").c_str(), level, sizeof(int) * nrhs);
   return k;
 }
 
@@ -163,21 +135,8 @@ void krylov_init(dmlmc_ctx* ctx, const KrylovArrays& k, int nrhs) {
   LAUNCH_CHECK();
 }
 
-// One Arnoldi step: orthogonalise w (FP64, [nrhs][n]) against V_0..V_j (RV) by CGS2,
-// update the Hessenberg column and rotations, store V_{j+1} = w / ||w||.
-template <typename RV>
-void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs, const KrylovArrays& k) {
-  const int64_t vstride = (int64_t)nrhs * n;
-  launch_multidot<RV>(ctx, V, j + 1, w, n, nrhs, n, vstride, k.h1, k.hld);
-  launch_multiaxpy<RV>(ctx, V, j + 1, w, n, nrhs, n, vstride, k.h1, k.hld);
-  launch_multidot<RV>(ctx, V, j + 1, w, n, nrhs, n, vstride, k.h2, k.hld);
-  launch_multiaxpy<RV>(ctx, V, j + 1, w, n, nrhs, n, vstride, k.h2, k.hld);
-  launch_norms2<double>(ctx, w, n, nrhs, n, k.nrm2);
-  hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(ceil_div(nrhs, 64)), dim3(64), 0, ctx->stream, j, k.m, k.h1, k.h2,
-                     k.hld, k.nrm2, k.H, k.cs, k.sn, k.g, k.res, k.invb, nrhs);
-  LAUNCH_CHECK();
-  hipLaunchKernelGGL((scale_store_kernel<RV>), dim3(gridn(n), nrhs), dim3(256), 0, ctx->stream, w, k.invb,
-                     V + (int64_t)(j + 1) * vstride, n);
+void krylov_scale_y(dmlmc_ctx* ctx, const KrylovArrays& k, const double* scale, int iters, int nrhs) {
+  hipLaunchKernelGGL(scale_y_kernel, dim3(ceil_div(nrhs, 64)), dim3(64), 0, ctx->stream, k.y, k.m, scale, iters, nrhs);
   LAUNCH_CHECK();
 }
 
@@ -204,29 +163,62 @@ void launch_scale_store(dmlmc_ctx* ctx, const c128* w, const double* invb, Cx<RV
 // ---------------------------------------------------------------- coarsest solve
 // Fixed-count GMRES from x = 0 on D_L (precision R for the operator and basis, FP64 dots
 // and Givens); no host synchronisation.
+// With a deflation of this level attached, the deflation space is inverted exactly and
+// GMRES runs on the projected remainder only.
 template <typename R>
-void coarsest_gmres(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs) {
+void coarsest_gmres(dmlmc_hier* H, int l, const Cx<R>* b_in, Cx<R>* x, int nrhs) {
   dmlmc_ctx* ctx = H->ctx;
   const Level& L = H->lv[l - 1];
   const int64_t n = L.n();
-  const int m = std::max(1, H->coarsest_iters);
   const bool f32 = std::is_same<R, float>::value;
+  const dmlmc_defl* D = H->coarse_defl;
+  const bool use_defl = D != nullptr && D->level == l;
+  const int m = std::max(1, use_defl ? H->coarsest_iters_defl : H->coarsest_iters);
+  const Cx<R>* b = b_in;
+  c128* e0 = nullptr;
+  if (use_defl) {
+    c128* b64 = (c128*)hier_buf(H, "cd_b", l, sizeof(c128) * (size_t)nrhs * n);
+    c128* r64 = (c128*)hier_buf(H, "cd_r", l, sizeof(c128) * (size_t)nrhs * n);
+    e0 = (c128*)hier_buf(H, "cd_e0", l, sizeof(c128) * (size_t)nrhs * n);
+    Cx<R>* rR = (Cx<R>*)hier_buf(H, f32 ? "cd_r32" : "cd_r64", l, sizeof(Cx<R>) * (size_t)nrhs * n);
+    launch_cast<double, R>(ctx, b_in, b64, n, nrhs, n, n);
+    defl_coarse_split(H, D, b64, nrhs, r64, e0, f32 ? DMLMC_MIXED : DMLMC_FP64);
+    launch_cast<R, double>(ctx, r64, rR, n, nrhs, n, n);
+    b = rR;
+  }
   Cx<R>* V = (Cx<R>*)hier_buf(H, f32 ? "cg_V32" : "cg_V64", l, sizeof(Cx<R>) * (size_t)(m + 1) * nrhs * n);
-  c128* w = (c128*)hier_buf(H, "cg_w", l, sizeof(c128) * (size_t)nrhs * n);
   Cx<R>* wr = (Cx<R>*)hier_buf(H, f32 ? "cg_wr32" : "cg_wr64", l, sizeof(Cx<R>) * (size_t)nrhs * n);
   KrylovArrays k = krylov_arrays(H, "cg_", l, m, nrhs);
+  const int64_t vstride = (int64_t)nrhs * n;
   launch_norms2<R>(ctx, b, n, nrhs, n, k.nrm2);
   krylov_init(ctx, k, nrhs);
-  launch_cast<double, R>(ctx, b, w, n, nrhs, n, n);
-  launch_scale_store<R>(ctx, w, k.invb, V, n, nrhs);
-  const int64_t vstride = (int64_t)nrhs * n;
-  for (int j = 0; j < m; ++j) {
-    apply_op<R>(ctx, L, V + j * vstride, wr, nrhs);
-    launch_cast<double, R>(ctx, wr, w, n, nrhs, n, n);
-    arnoldi_step<R>(ctx, V, w, j, n, nrhs, k);
+  if (f32) {
+    // single-pass Gram-Schmidt on an unnormalised complex-FP32 basis (FP64 arithmetic)
+    double* scale = (double*)hier_buf(H, "cg_sc", l, sizeof(double) * (size_t)(m + 1) * nrhs);
+    c64* U = (c64*)V;
+    c64* vin = (c64*)hier_buf(H, "cg_vin32", l, sizeof(c64) * (size_t)nrhs * n);
+    HIPCHK(hipMemcpyAsync(U, b, sizeof(c64) * (size_t)vstride, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(scale, k.invb, sizeof(double) * nrhs, hipMemcpyDeviceToDevice, ctx->stream));
+    for (int j = 0; j < m; ++j) {
+      launch_scale_vec(ctx, U + j * vstride, scale + (int64_t)j * nrhs, vin, n, nrhs);
+      apply_op<float>(ctx, L, vin, (c64*)wr, nrhs);
+      arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k);
+    }
+    krylov_solution(ctx, k, m, nrhs);
+    krylov_scale_y(ctx, k, scale, m, nrhs);
+  } else {
+    c128* w = (c128*)hier_buf(H, "cg_w", l, sizeof(c128) * (size_t)nrhs * n);
+    launch_cast<double, R>(ctx, b, w, n, nrhs, n, n);
+    launch_scale_store<R>(ctx, w, k.invb, V, n, nrhs);
+    for (int j = 0; j < m; ++j) {
+      apply_op<R>(ctx, L, V + j * vstride, wr, nrhs);
+      launch_cast<double, R>(ctx, wr, w, n, nrhs, n, n);
+      arnoldi_step<R>(ctx, V, w, j, n, nrhs, k);
+    }
+    krylov_solution(ctx, k, m, nrhs);
   }
-  krylov_solution(ctx, k, m, nrhs);
   launch_combine<R, R>(ctx, V, m, k, x, n, nrhs);
+  if (use_defl) launch_add_cast_to<R>(ctx, e0, x, n, nrhs);
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -284,33 +276,44 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, 
   const int64_t n = L.n();
   const bool f32 = std::is_same<RP, float>::value;
   const int64_t vstride = (int64_t)nrhs * n;
-  c128* V = (c128*)hier_buf(H, "fg_V", l, sizeof(c128) * (size_t)(m + 1) * vstride);
   Cx<RP>* Z = (Cx<RP>*)hier_buf(H, f32 ? "fg_Z32" : "fg_Z64", l, sizeof(Cx<RP>) * (size_t)m * vstride);
-  c128* w = (c128*)hier_buf(H, "fg_w", l, sizeof(c128) * (size_t)vstride);
-  Cx<RP>* vin = nullptr;
-  Cx<RP>* wr = nullptr;
-  if (f32) {
-    vin = (Cx<RP>*)hier_buf(H, "fg_vin32", l, sizeof(Cx<RP>) * (size_t)vstride);
-    wr = (Cx<RP>*)hier_buf(H, "fg_wr32", l, sizeof(Cx<RP>) * (size_t)vstride);
-  }
   KrylovArrays k = krylov_arrays(H, "fg_", l, m, nrhs);
   launch_norms2<double>(ctx, r, n, nrhs, n, k.nrm2);
   krylov_init(ctx, k, nrhs);
-  launch_scale_store<double>(ctx, r, k.invb, V, n, nrhs);
   int it = 0;
   res_host.assign(nrhs, 0.0);
+  // complex-FP32 inner cycle: single-pass Gram-Schmidt (FP64 arithmetic) on an
+  // unnormalised complex-FP32 basis; FP64 cycle: two passes on an FP64 basis
+  c64* U = nullptr;
+  double* scale = nullptr;
+  c128* V = nullptr;
+  c128* w = nullptr;
+  Cx<RP>* vin = nullptr;
+  Cx<RP>* wr = nullptr;
+  if (f32) {
+    U = (c64*)hier_buf(H, "fg_U32", l, sizeof(c64) * (size_t)(m + 1) * vstride);
+    scale = (double*)hier_buf(H, "fg_sc", l, sizeof(double) * (size_t)(m + 1) * nrhs);
+    vin = (Cx<RP>*)hier_buf(H, "fg_vin32", l, sizeof(Cx<RP>) * (size_t)vstride);
+    wr = (Cx<RP>*)hier_buf(H, "fg_wr32", l, sizeof(Cx<RP>) * (size_t)vstride);
+    launch_cast<float, double>(ctx, r, U, n, nrhs, n, n);
+    HIPCHK(hipMemcpyAsync(scale, k.invb, sizeof(double) * nrhs, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    V = (c128*)hier_buf(H, "fg_V", l, sizeof(c128) * (size_t)(m + 1) * vstride);
+    w = (c128*)hier_buf(H, "fg_w", l, sizeof(c128) * (size_t)vstride);
+    launch_scale_store<double>(ctx, r, k.invb, V, n, nrhs);
+  }
   for (int j = 0; j < m; ++j) {
     Cx<RP>* zj = Z + j * vstride;
     if (f32) {
-      launch_cast<float, double>(ctx, V + j * vstride, (c64*)vin, n, nrhs, n, n);
+      launch_scale_vec(ctx, U + j * vstride, scale + (int64_t)j * nrhs, (c64*)vin, n, nrhs);
       vcycle<RP>(H, l, vin, zj, nrhs);
       apply_op<RP>(ctx, L, zj, wr, nrhs);
-      launch_cast<double, RP>(ctx, wr, w, n, nrhs, n, n);
+      arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k);
     } else {
       vcycle<RP>(H, l, (const Cx<RP>*)(V + j * vstride), zj, nrhs);
       apply_op<RP>(ctx, L, zj, (Cx<RP>*)w, nrhs);
+      arnoldi_step<double>(ctx, V, w, j, n, nrhs, k);
     }
-    arnoldi_step<double>(ctx, V, w, j, n, nrhs, k);
     it = j + 1;
     HIPCHK(hipMemcpyAsync(res_host.data(), k.res, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -389,6 +392,5 @@ template void vcycle<float>(dmlmc_hier*, int, const c64*, c64*, int);
 template void vcycle<double>(dmlmc_hier*, int, const c128*, c128*, int);
 template void smooth<float>(dmlmc_hier*, int, c64*, const c64*, int, int);
 template void smooth<double>(dmlmc_hier*, int, c128*, const c128*, int, int);
-template void arnoldi_step<double>(dmlmc_ctx*, c128*, c128*, int, int64_t, int, const KrylovArrays&);
 template void launch_combine<double, double>(dmlmc_ctx*, const c128*, int, const KrylovArrays&, c128*, int64_t, int);
 template void launch_scale_store<double>(dmlmc_ctx*, const c128*, const double*, c128*, int64_t, int);

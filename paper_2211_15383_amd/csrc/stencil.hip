@@ -345,6 +345,123 @@ __global__ __launch_bounds__(256) void prolong_kernel(const Cx<R>* __restrict__ 
   }
 }
 
+
+// ---------------------------------------------------------------- matrix-core forms (d = 16, complex FP32)
+// One wavefront computes a 16 (dofs) x 16 (RHS) tile of one site with v_mfma_f32_16x16x4_f32:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 (l / 16) + v][l % 16].
+// A complex product A X takes four real products (re: Ar Xr - Ai Xi, im: Ar Xi + Ai Xr).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void cmfma(f32x4& dre, f32x4& dim, c64 a, c64 x) {
+  dre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x.x, dre, 0, 0, 0);
+  dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, x.y, dre, 0, 0, 0);
+  dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x.y, dim, 0, 0, 0);
+  dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x.x, dim, 0, 0, 0);
+}
+
+// D += sum_dir A[s][dir] X[nb(dir)] for the tile (rows of the site, RHS r0..r0+15).
+__device__ __forceinline__ void site_product16(const c64* __restrict__ A, const c64* __restrict__ in, int64_t s,
+                                               const int64_t* sites, int64_t ldx, int rhs, bool rv, int row, int kq,
+                                               f32x4& dre, f32x4& dim) {
+  const c64* xr = in + (int64_t)rhs * ldx;
+  for (int dir = 0; dir < 5; ++dir) {
+    const c64* Ad = A + (s * 5 + dir) * 256;
+    const c64* xb = xr + sites[dir] * 16;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = 4 * t + kq;
+      const c64 a = Ad[j * 16 + row];
+      const c64 x = rv ? xb[j] : cmk(0.f, 0.f);
+      cmfma(dre, dim, a, x);
+    }
+  }
+}
+
+template <bool G5>
+__global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ in,
+                                                            c64* __restrict__ out, int Lx, int Lt, int nrhs,
+                                                            int64_t ldx, int64_t ldy) {
+  const int64_t V = (int64_t)Lx * Lt;
+  const int lane = threadIdx.x & 63;
+  const int ntile = (nrhs + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t s = wave / ntile;
+  if (s >= V) return;  // uniform per wavefront; no block-level synchronisation below
+  const int tile = (int)(wave % ntile);
+  const int row = lane & 15, kq = lane >> 4;
+  const int rhs = tile * 16 + row;
+  const bool rv = rhs < nrhs;
+  const Nbr nb = neighbours(s, Lx, Lt);
+  const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
+  f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
+  site_product16(A, in, s, sites, ldx, rv ? rhs : 0, rv, row, kq, dre, dim);
+  if (!rv) return;
+  c64* o = out + (int64_t)rhs * ldy + s * 16;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * kq + v;
+    const float sg = (G5 && i >= 8) ? -1.f : 1.f;
+    o[i] = cmk(sg * dre[v], sg * dim[v]);
+  }
+}
+
+// Red/black point-block Gauss-Seidel, d = 16: R = b - D x on the colour sites, then
+// x += A_ss^-1 R, both products on the matrix cores; R passes through LDS to reach the
+// B-operand layout.  Every wavefront reaches the barrier (no early exit).
+__global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ Ainv,
+                                                               c64* __restrict__ x, const c64* __restrict__ b, int Lx,
+                                                               int Lt, int nrhs, int color, int even_lx) {
+  __shared__ c64 Rl[4][16][16];  // [wave][dof][rhs]
+  const int64_t V = (int64_t)Lx * Lt;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ntile = (nrhs + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + w;
+  const int64_t k = wave / ntile;
+  const int tile = (int)(wave % ntile);
+  int64_t s;
+  bool active;
+  if (even_lx) {
+    const int64_t half = Lx / 2;
+    const int64_t t = k / half;
+    s = 2 * (k % half) + ((t + color) & 1) + t * Lx;
+    active = t < Lt;
+  } else {
+    s = k;
+    active = (s < V) && ((((s % Lx) + (s / Lx)) & 1) == color);
+  }
+  if (!active) s = 0;
+  const int row = lane & 15, kq = lane >> 4;
+  const int rhs = tile * 16 + row;
+  const bool rv = active && rhs < nrhs;
+  const int64_t ld = V * 16;
+  const Nbr nb = neighbours(s, Lx, Lt);
+  const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
+  f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
+  site_product16(A, x, s, sites, ld, rv ? rhs : 0, rv, row, kq, dre, dim);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * kq + v;
+    const c64 bb = rv ? b[(int64_t)rhs * ld + s * 16 + i] : cmk(0.f, 0.f);
+    Rl[w][i][row] = cmk(bb.x - dre[v], bb.y - dim[v]);
+  }
+  __syncthreads();
+  f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = {0.f, 0.f, 0.f, 0.f};
+  const c64* Ai = Ainv + s * 256;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = 4 * t + kq;
+    cmfma(ere, eim, Ai[j * 16 + row], Rl[w][j][row]);
+  }
+  if (!rv) return;
+  c64* xo = x + (int64_t)rhs * ld + s * 16;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * kq + v;
+    const c64 o = xo[i];
+    xo[i] = cmk(o.x + ere[v], o.y + eim[v]);
+  }
+}
+
 inline int rhs_block_for(int64_t threads, int nrhs) {
   // enough workgroups to fill 256 CUs several times; otherwise split the RHS over y
   const int64_t wgs = ceil_div(threads, 256);
@@ -381,6 +498,18 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
   const Cx<R>* A = std::is_same<R, float>::value ? (const Cx<R>*)L.A32.p : (const Cx<R>*)L.A64.p;
   KTimer kt(ctx, "coarse",
             (double)nrhs * L.n() * 2 * sizeof(Cx<R>) + (double)V * 5 * d * d * sizeof(Cx<R>));
+  if (std::is_same<R, float>::value && d == 16) {
+    const int64_t waves = V * ((nrhs + 15) / 16);
+    dim3 grid((unsigned)ceil_div(waves, 4));
+    if (gamma5_left)
+      hipLaunchKernelGGL((coarse16_mfma_kernel<true>), grid, dim3(256), 0, ctx->stream, (const c64*)A, (const c64*)x,
+                         (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    else
+      hipLaunchKernelGGL((coarse16_mfma_kernel<false>), grid, dim3(256), 0, ctx->stream, (const c64*)A, (const c64*)x,
+                         (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    LAUNCH_CHECK();
+    return;
+  }
   constexpr int RB = 4;
   dim3 grid((unsigned)ceil_div(V, spb), (unsigned)ceil_div(nrhs, RB));
   dim3 block((unsigned)(spb * d));
@@ -436,6 +565,13 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
   const int rb = rhs_block_for(nsites * d, nrhs);
   KTimer kt(ctx, "coarse_gs",
             (double)nrhs * (V / 2) * d * 4 * sizeof(Cx<R>) + (double)(V / 2) * 6 * d * d * sizeof(Cx<R>));
+  if (std::is_same<R, float>::value && d == 16) {
+    const int64_t waves = nsites * ((nrhs + 15) / 16);
+    hipLaunchKernelGGL(coarse16_gs_mfma_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, ctx->stream,
+                       (const c64*)A, (const c64*)Ai, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, even);
+    LAUNCH_CHECK();
+    return;
+  }
   dim3 grid((unsigned)ceil_div(nsites, spb), (unsigned)ceil_div(nrhs, rb));
   dim3 block((unsigned)(spb * d));
   size_t shm = (size_t)spb * d * sizeof(Cx<R>);

@@ -26,7 +26,8 @@ EXPORTED = [
     "dmlmc_create", "dmlmc_destroy", "dmlmc_last_error", "dmlmc_version", "dmlmc_build_hierarchy",
     "dmlmc_free_hierarchy", "dmlmc_level_info", "dmlmc_export_level", "dmlmc_deflate",
     "dmlmc_free_deflation", "dmlmc_deflation_info", "dmlmc_export_deflation", "dmlmc_solve_multi_rhs", "dmlmc_mlmc_trace",
-    "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_timing_enable",
+    "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_set_solver_params",
+    "dmlmc_get_solver_params", "dmlmc_timing_enable",
     "dmlmc_timing_reset", "dmlmc_timing_get",
 ]
 
@@ -49,6 +50,11 @@ class MGParams(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("ir_steps", C.c_int), ("converged", C.c_int), ("relres_max", C.c_double)]
+
+
+class SolverParams(C.Structure):
+    _fields_ = [("sap_mr_iters", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarsest_iters", C.c_int),
+                ("coarsest_iters_defl", C.c_int), ("restart", C.c_int)]
 
 
 class MLMCParams(C.Structure):
@@ -87,6 +93,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_apply": (i32, [vp, vp, i32, i32, vp, vp, i32, i32, u64]),
         "dmlmc_set_deflation": (i32, [vp, vp]),
         "dmlmc_z2_noise": (i32, [vp, i64, u64, i32, i64, i32, vp, i32]),
+        "dmlmc_set_solver_params": (i32, [vp, C.POINTER(SolverParams)]),
+        "dmlmc_get_solver_params": (i32, [vp, C.POINTER(SolverParams)]),
         "dmlmc_timing_enable": (i32, [vp, i32]),
         "dmlmc_timing_reset": (i32, [vp]),
         "dmlmc_timing_get": (i32, [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
@@ -272,6 +280,18 @@ class Hierarchy:
         if st not in (OK,):
             raise DmlmcError(st, lib().dmlmc_last_error(self.ctx.h).decode())
         return X, stats
+
+    def solver_params(self, **kw):
+        """Sets the given solver parameters (see dmlmc_solver_params); returns all of them."""
+        p = SolverParams(-1, -1, -1, -1, -1, -1)
+        for key, v in kw.items():
+            setattr(p, key, int(v))
+        st = lib().dmlmc_set_solver_params(self.h, C.byref(p))
+        if st != OK:
+            raise DmlmcError(st, f"invalid solver parameters {kw}")
+        q = SolverParams()
+        lib().dmlmc_get_solver_params(self.h, C.byref(q))
+        return {f: getattr(q, f) for f, _ in SolverParams._fields_}
 
     def set_deflation(self, d: Optional["Deflation"]):
         st = lib().dmlmc_set_deflation(self.h, d.h if d is not None else None)
