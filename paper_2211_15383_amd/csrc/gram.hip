@@ -1,20 +1,44 @@
-// Fused Gram-Schmidt passes of the Arnoldi step (classical Gram-Schmidt with one
-// reorthogonalisation, FP64 arithmetic), one launch per pass:
-//   A: h1 = V^H w                         (read V, w)
-//   B: w' = w - V h1, ||w'||^2             (read V, w; write w')
-//   C: h2 = V^H w', then the Hessenberg column, Givens rotation and residual estimate
-//      (read V, w')
-//   D: v_{j+1} = (w' - V h2) / beta, beta^2 = ||w'||^2 - |h2|^2   (read V, w'; write v)
-// Each reduction is finished by the last workgroup of its RHS (partials summed in a fixed
-// order, so results are deterministic); the completion counters reset themselves.
+// Gram-Schmidt passes of the Arnoldi step, FP64 arithmetic.
+//
+// Two-pass form (classical Gram-Schmidt with one reorthogonalisation, FP64 basis):
+//   A: h1 = V^H w                        (read V, w)
+//   B: w' = w - V h1, ||w'||^2            (read V, w; write w')
+//   C: h2 = V^H w', Hessenberg column, Givens rotation, residual estimate
+//   D: v_{j+1} = (w' - V h2) / beta, beta^2 = ||w'||^2 - |h2|^2
+// Single-pass form (complex-FP32 cycles: unnormalised FP32 basis u_i, scales s_i = 1/||u_i||):
+//   A: h_i = s_i <u_i, w>                (read U, w)
+//   B: u_{j+1} = w - sum_i h_i s_i u_i, ||u_{j+1}||^2, Hessenberg column, Givens, s_{j+1}
+//
+// Reductions: each workgroup reduces in LDS; with one workgroup per RHS the workgroup
+// finishes the pass itself, otherwise it writes partial sums and a small kernel (one
+// workgroup per RHS) adds them in a fixed order.  No atomics or device-scope fences.
 #include <cmath>
 
 #include "solver.h"
 
 namespace {
 
-constexpr int NBMAX = 32;        // basis vectors per pass
-constexpr int NVMAX = 2 * NBMAX; // reduced doubles per pass
+constexpr int NBMAX = 32;         // basis vectors per pass
+constexpr int NVMAX = 2 * NBMAX;  // reduced doubles per pass
+
+enum FinishMode { FIN_STORE = 0, FIN_SCALED = 1, FIN_CGS2 = 2, FIN_CGS1 = 3 };
+
+struct Fin {
+  int mode = FIN_STORE;
+  int j = 0, m = 0, hld = 0, nrhs = 0;
+  double* out = nullptr;        // FIN_STORE: nv doubles per RHS at out + r * ostride
+  int ostride = 0;
+  const c128* h1 = nullptr;     // FIN_CGS2: first-pass coefficients; FIN_CGS1: the coefficients
+  c128* h = nullptr;            // FIN_SCALED / FIN_CGS2: where the (scaled) coefficients go
+  double* scale = nullptr;      // FIN_SCALED / FIN_CGS1: [i][nrhs]
+  const double* nrm2 = nullptr; // FIN_CGS2: ||w'||^2
+  c128* H = nullptr;
+  double* cs = nullptr;
+  c128* sn = nullptr;
+  c128* g = nullptr;
+  double* res = nullptr;
+  double* invb = nullptr;
+};
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -22,13 +46,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Reduces acc[0..nv) over the 256-thread block, writes the block partials, and lets the
-// last block of RHS r sum all partials into out[0..nv).  Returns true in the last block
-// (after out is written and visible to the whole block).
-__device__ bool reduce_last_block(double* acc, int nv, double* __restrict__ part, int* __restrict__ counter, int r,
-                                  double* __restrict__ out, double* lds /* [4 * NVMAX] */) {
+// acc[0..nv) summed over the 256-thread block into red[0..nv) (LDS); all threads return
+// after red is complete.
+__device__ void block_reduce(const double* acc, int nv, double* lds /* [4][NVMAX] */, double* red) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int G = gridDim.x;
 #pragma unroll
   for (int q = 0; q < NVMAX; ++q) {
     if (q < nv) {
@@ -37,128 +58,19 @@ __device__ bool reduce_last_block(double* acc, int nv, double* __restrict__ part
     }
   }
   __syncthreads();
-  double* pr = part + ((int64_t)r * G + blockIdx.x) * nv;
-  for (int q = threadIdx.x; q < nv; q += blockDim.x) pr[q] = lds[q] + lds[NVMAX + q] + lds[2 * NVMAX + q] + lds[3 * NVMAX + q];
-  __threadfence();
-  __shared__ int last;
+  for (int q = threadIdx.x; q < nv; q += blockDim.x)
+    red[q] = lds[q] + lds[NVMAX + q] + lds[2 * NVMAX + q] + lds[3 * NVMAX + q];
   __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter + r, 1) == G - 1);
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  const double* base = part + (int64_t)r * G * nv;
-  for (int q = threadIdx.x; q < nv; q += blockDim.x) {
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) s += base[(int64_t)g * nv + q];
-    out[q] = s;
-  }
-  if (threadIdx.x == 0) counter[r] = 0;
-  __threadfence_block();
-  __syncthreads();
-  return true;
 }
 
-template <typename RV>
-__global__ __launch_bounds__(256) void gs_dots_kernel(const Cx<RV>* __restrict__ V, int nb, const c128* __restrict__ w,
-                                                      int64_t n, int64_t vstride, double* __restrict__ part,
-                                                      int* __restrict__ counter, c128* __restrict__ h, int hld) {
-  __shared__ double lds[4 * NVMAX];
-  const int r = blockIdx.y;
-  double acc[NVMAX];
-#pragma unroll
-  for (int q = 0; q < NVMAX; ++q) acc[q] = 0.0;
-  const c128* wr = w + (int64_t)r * n;
-  const Cx<RV>* Vr = V + (int64_t)r * n;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    const c128 b = wr[p];
-#pragma unroll
-    for (int i = 0; i < NBMAX; ++i) {
-      if (i < nb) {
-        const Cx<RV> a = Vr[i * vstride + p];
-        acc[2 * i] += (double)a.x * b.x + (double)a.y * b.y;
-        acc[2 * i + 1] += (double)a.x * b.y - (double)a.y * b.x;
-      }
-    }
-  }
-  reduce_last_block(acc, 2 * nb, part, counter, r, (double*)(h + (int64_t)r * hld), lds);
-}
-
-template <typename RV>
-__global__ __launch_bounds__(256) void gs_update_norm_kernel(const Cx<RV>* __restrict__ V, int nb,
-                                                             c128* __restrict__ w, int64_t n, int64_t vstride,
-                                                             const c128* __restrict__ h, int hld,
-                                                             double* __restrict__ part, int* __restrict__ counter,
-                                                             double* __restrict__ nrm2) {
-  __shared__ double lds[4 * NVMAX];
-  __shared__ c128 hs[NBMAX];
-  const int r = blockIdx.y;
-  if (threadIdx.x < nb) hs[threadIdx.x] = h[(int64_t)r * hld + threadIdx.x];
-  __syncthreads();
-  double acc[NVMAX];
-#pragma unroll
-  for (int q = 0; q < NVMAX; ++q) acc[q] = 0.0;
-  c128* wr = w + (int64_t)r * n;
-  const Cx<RV>* Vr = V + (int64_t)r * n;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    c128 v = wr[p];
-#pragma unroll
-    for (int i = 0; i < NBMAX; ++i) {
-      if (i < nb) {
-        const Cx<RV> a = Vr[i * vstride + p];
-        const c128 hi = hs[i];
-        v.x -= hi.x * (double)a.x - hi.y * (double)a.y;
-        v.y -= hi.x * (double)a.y + hi.y * (double)a.x;
-      }
-    }
-    wr[p] = v;
-    acc[0] += v.x * v.x + v.y * v.y;
-  }
-  reduce_last_block(acc, 1, part, counter, r, nrm2 + r, lds);
-}
-
-// Pass C with the Hessenberg bookkeeping done by the last block of each RHS.
-template <typename RV>
-__global__ __launch_bounds__(256) void gs_dots_finish_kernel(const Cx<RV>* __restrict__ V, int nb,
-                                                             const c128* __restrict__ w, int64_t n, int64_t vstride,
-                                                             double* __restrict__ part, int* __restrict__ counter,
-                                                             int j, int m, const c128* __restrict__ h1,
-                                                             c128* __restrict__ h2, int hld,
-                                                             const double* __restrict__ nrm2, c128* __restrict__ H,
-                                                             double* __restrict__ cs, c128* __restrict__ sn,
-                                                             c128* __restrict__ g, double* __restrict__ res,
-                                                             double* __restrict__ invb) {
-  __shared__ double lds[4 * NVMAX];
-  const int r = blockIdx.y;
-  double acc[NVMAX];
-#pragma unroll
-  for (int q = 0; q < NVMAX; ++q) acc[q] = 0.0;
-  const c128* wr = w + (int64_t)r * n;
-  const Cx<RV>* Vr = V + (int64_t)r * n;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    const c128 b = wr[p];
-#pragma unroll
-    for (int i = 0; i < NBMAX; ++i) {
-      if (i < nb) {
-        const Cx<RV> a = Vr[i * vstride + p];
-        acc[2 * i] += (double)a.x * b.x + (double)a.y * b.y;
-        acc[2 * i + 1] += (double)a.x * b.y - (double)a.y * b.x;
-      }
-    }
-  }
-  if (!reduce_last_block(acc, 2 * nb, part, counter, r, (double*)(h2 + (int64_t)r * hld), lds)) return;
-  if (threadIdx.x != 0) return;
-  // Hessenberg column j = h1 + h2; beta = ||w' - V h2|| = sqrt(||w'||^2 - |h2|^2)
-  c128* col = H + (int64_t)r * (m + 1) * m + (int64_t)j * (m + 1);
-  double h2n = 0.0;
-  for (int i = 0; i <= j; ++i) {
-    const c128 b2 = h2[(int64_t)r * hld + i];
-    h2n += b2.x * b2.x + b2.y * b2.y;
-    col[i] = h1[(int64_t)r * hld + i] + b2;
-  }
-  const double beta = sqrt(fmax(nrm2[r] - h2n, 0.0));
+// Hessenberg column j (col rows 0..j hold the Gram-Schmidt coefficients) and beta:
+// previous rotations, a new rotation, g and the residual estimate.
+__device__ void hessenberg_update(const Fin& f, int r, double beta) {
+  const int m = f.m, j = f.j;
+  c128* col = f.H + (int64_t)r * (m + 1) * m + (int64_t)j * (m + 1);
   for (int i = 0; i < j; ++i) {
-    const double c = cs[r * m + i];
-    const c128 s = sn[r * m + i];
+    const double c = f.cs[r * m + i];
+    const c128 s = f.sn[r * m + i];
     const c128 a = col[i], b = col[i + 1];
     col[i] = c * a + s * b;
     col[i + 1] = c * b - conj(s) * a;
@@ -182,14 +94,140 @@ __global__ __launch_bounds__(256) void gs_dots_finish_kernel(const Cx<RV>* __res
     s = (beta / rho) * ph;
     col[j] = rho * ph;
   }
-  cs[r * m + j] = c;
-  sn[r * m + j] = s;
-  c128* gr = g + (int64_t)r * (m + 1);
+  f.cs[r * m + j] = c;
+  f.sn[r * m + j] = s;
+  c128* gr = f.g + (int64_t)r * (m + 1);
   const c128 gj = gr[j];
   gr[j + 1] = cmk(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));  // -conj(s) g_j
   gr[j] = c * gj;
-  res[r] = sqrt(cabs2(gr[j + 1]));
-  invb[r] = beta > 0.0 ? 1.0 / beta : 0.0;
+  f.res[r] = sqrt(cabs2(gr[j + 1]));
+}
+
+// Completes a pass for RHS r from the reduced sums red[0..nv) (whole block calls it).
+__device__ void finish_pass(const Fin& f, int r, int nv, const double* red) {
+  const int nb = f.j + 1;
+  switch (f.mode) {
+    case FIN_STORE:
+      for (int q = threadIdx.x; q < nv; q += blockDim.x) f.out[(int64_t)r * f.ostride + q] = red[q];
+      break;
+    case FIN_SCALED:
+      for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        const double sc = f.scale[(int64_t)i * f.nrhs + r];
+        f.h[(int64_t)r * f.hld + i] = cmk(red[2 * i] * sc, red[2 * i + 1] * sc);
+      }
+      break;
+    case FIN_CGS2:
+      if (threadIdx.x == 0) {
+        c128* col = f.H + (int64_t)r * (f.m + 1) * f.m + (int64_t)f.j * (f.m + 1);
+        double h2n = 0.0;
+        for (int i = 0; i < nb; ++i) {
+          const c128 b2 = cmk(red[2 * i], red[2 * i + 1]);
+          h2n += b2.x * b2.x + b2.y * b2.y;
+          f.h[(int64_t)r * f.hld + i] = b2;
+          col[i] = f.h1[(int64_t)r * f.hld + i] + b2;
+        }
+        const double beta = sqrt(fmax(f.nrm2[r] - h2n, 0.0));
+        hessenberg_update(f, r, beta);
+        f.invb[r] = beta > 0.0 ? 1.0 / beta : 0.0;
+      }
+      break;
+    case FIN_CGS1:
+      if (threadIdx.x == 0) {
+        const double beta = sqrt(fmax(red[0], 0.0));
+        f.scale[(int64_t)nb * f.nrhs + r] = beta > 0.0 ? 1.0 / beta : 0.0;
+        c128* col = f.H + (int64_t)r * (f.m + 1) * f.m + (int64_t)f.j * (f.m + 1);
+        for (int i = 0; i < nb; ++i) col[i] = f.h1[(int64_t)r * f.hld + i];
+        hessenberg_update(f, r, beta);
+      }
+      break;
+  }
+}
+
+// Block reduce, then either finish (one workgroup per RHS) or write partials.
+__device__ void reduce_or_partial(const double* acc, int nv, double* lds, double* red, double* __restrict__ part,
+                                  const Fin& f, int r) {
+  block_reduce(acc, nv, lds, red);
+  if (gridDim.x == 1) {
+    finish_pass(f, r, nv, red);
+  } else {
+    double* pr = part + ((int64_t)r * gridDim.x + blockIdx.x) * nv;
+    for (int q = threadIdx.x; q < nv; q += blockDim.x) pr[q] = red[q];
+  }
+}
+
+__global__ __launch_bounds__(64) void partial_finish_kernel(const double* __restrict__ part, int G, int nv, Fin f) {
+  __shared__ double red[NVMAX];
+  const int r = blockIdx.x;
+  for (int q = threadIdx.x; q < nv; q += blockDim.x) {
+    double s = 0.0;
+    const double* base = part + (int64_t)r * G * nv + q;
+    for (int g = 0; g < G; ++g) s += base[(int64_t)g * nv];
+    red[q] = s;
+  }
+  __syncthreads();
+  finish_pass(f, r, nv, red);
+}
+
+template <typename R>
+struct __align__(4 * sizeof(R)) Pair {
+  Cx<R> a, b;
+};
+
+// ---------------------------------------------------------------- two-pass form kernels
+template <typename RV>
+__global__ __launch_bounds__(256) void gs_dots_kernel(const Cx<RV>* __restrict__ V, int nb, const c128* __restrict__ w,
+                                                      int64_t n, int64_t vstride, double* __restrict__ part, Fin f) {
+  __shared__ double lds[4 * NVMAX];
+  __shared__ double red[NVMAX];
+  const int r = blockIdx.y;
+  double acc[NVMAX];
+#pragma unroll
+  for (int q = 0; q < NVMAX; ++q) acc[q] = 0.0;
+  const c128* wr = w + (int64_t)r * n;
+  const Cx<RV>* Vr = V + (int64_t)r * n;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const c128 b = wr[p];
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) {
+      if (i < nb) {
+        const Cx<RV> a = Vr[i * vstride + p];
+        acc[2 * i] += (double)a.x * b.x + (double)a.y * b.y;
+        acc[2 * i + 1] += (double)a.x * b.y - (double)a.y * b.x;
+      }
+    }
+  }
+  reduce_or_partial(acc, 2 * nb, lds, red, part, f, r);
+}
+
+template <typename RV>
+__global__ __launch_bounds__(256) void gs_update_norm_kernel(const Cx<RV>* __restrict__ V, int nb,
+                                                             c128* __restrict__ w, int64_t n, int64_t vstride,
+                                                             const c128* __restrict__ h, int hld,
+                                                             double* __restrict__ part, Fin f) {
+  __shared__ double lds[4 * NVMAX];
+  __shared__ double red[NVMAX];
+  __shared__ c128 hs[NBMAX];
+  const int r = blockIdx.y;
+  if (threadIdx.x < nb) hs[threadIdx.x] = h[(int64_t)r * hld + threadIdx.x];
+  __syncthreads();
+  double acc[1] = {0.0};
+  c128* wr = w + (int64_t)r * n;
+  const Cx<RV>* Vr = V + (int64_t)r * n;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    c128 v = wr[p];
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) {
+      if (i < nb) {
+        const Cx<RV> a = Vr[i * vstride + p];
+        const c128 hi = hs[i];
+        v.x -= hi.x * (double)a.x - hi.y * (double)a.y;
+        v.y -= hi.x * (double)a.y + hi.y * (double)a.x;
+      }
+    }
+    wr[p] = v;
+    acc[0] += v.x * v.x + v.y * v.y;
+  }
+  reduce_or_partial(acc, 1, lds, red, part, f, r);
 }
 
 template <typename RV>
@@ -220,165 +258,155 @@ __global__ __launch_bounds__(256) void gs_update_store_kernel(Cx<RV>* __restrict
   }
 }
 
-// ---------------------------------------------------------------- single-pass form (mixed path)
-// Basis vectors are stored unnormalised in complex FP32 (u_i) with per-vector scales
-// s_i = 1 / ||u_i|| (scale[i][r]); all dots and updates accumulate in FP64.
-//   A: h_i = s_i <u_i, w>                          (read U, w)
-//   B: u_{j+1} = w - sum_i h_i s_i u_i, ||u_{j+1}||^2, then the Hessenberg column,
-//      Givens rotation, residual estimate and s_{j+1} in the last block (read U, w; write u)
+// ---------------------------------------------------------------- single-pass form kernels
 template <typename RW>
 __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U, int nb,
                                                        const Cx<RW>* __restrict__ w, int64_t n, int64_t vstride,
-                                                       const double* __restrict__ scale, int nrhs,
-                                                       double* __restrict__ part, int* __restrict__ counter,
-                                                       c128* __restrict__ h, int hld) {
+                                                       double* __restrict__ part, Fin f) {
   __shared__ double lds[4 * NVMAX];
+  __shared__ double red[NVMAX];
   const int r = blockIdx.y;
   double acc[NVMAX];
 #pragma unroll
   for (int q = 0; q < NVMAX; ++q) acc[q] = 0.0;
-  const Cx<RW>* wr = w + (int64_t)r * n;
-  const c64* Ur = U + (int64_t)r * n;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    const Cx<RW> bw = wr[p];
-    const double bx = (double)bw.x, by = (double)bw.y;
+  // element pairs (n is even): 16-byte loads of the FP32 basis
+  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * n);
+  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * n);
+  const int64_t np = n / 2, vs = vstride / 2;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const Pair<RW> bw = wr[p];
+    const double b0x = (double)bw.a.x, b0y = (double)bw.a.y, b1x = (double)bw.b.x, b1y = (double)bw.b.y;
 #pragma unroll
     for (int i = 0; i < NBMAX; ++i) {
       if (i < nb) {
-        const c64 a = Ur[i * vstride + p];
-        acc[2 * i] += (double)a.x * bx + (double)a.y * by;
-        acc[2 * i + 1] += (double)a.x * by - (double)a.y * bx;
+        const Pair<float> u = Ur[i * vs + p];
+        acc[2 * i] += (double)u.a.x * b0x + (double)u.a.y * b0y + (double)u.b.x * b1x + (double)u.b.y * b1y;
+        acc[2 * i + 1] += (double)u.a.x * b0y - (double)u.a.y * b0x + (double)u.b.x * b1y - (double)u.b.y * b1x;
       }
     }
   }
-  __shared__ double hs[2 * NBMAX];
-  if (!reduce_last_block(acc, 2 * nb, part, counter, r, hs, lds)) return;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    const double sc = scale[(int64_t)i * nrhs + r];
-    h[(int64_t)r * hld + i] = cmk(hs[2 * i] * sc, hs[2 * i + 1] * sc);
-  }
+  reduce_or_partial(acc, 2 * nb, lds, red, part, f, r);
 }
 
 template <typename RW>
-__global__ __launch_bounds__(256) void gs1_update_finish_kernel(c64* __restrict__ U, int nb,
-                                                                const Cx<RW>* __restrict__ w, int64_t n,
-                                                                int64_t vstride, double* __restrict__ scale, int nrhs,
-                                                                double* __restrict__ part, int* __restrict__ counter,
-                                                                int j, int m, c128* __restrict__ hcol, int hld,
-                                                                c128* __restrict__ H, double* __restrict__ cs,
-                                                                c128* __restrict__ sn, c128* __restrict__ g,
-                                                                double* __restrict__ res) {
+__global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, int nb, const Cx<RW>* __restrict__ w,
+                                                         int64_t n, int64_t vstride, const c128* __restrict__ h,
+                                                         int hld, const double* __restrict__ scale, int nrhs,
+                                                         double* __restrict__ part, Fin f) {
   __shared__ double lds[4 * NVMAX];
+  __shared__ double red[NVMAX];
   __shared__ c128 hs[NBMAX];
   const int r = blockIdx.y;
   if (threadIdx.x < nb) {
-    const c128 hv = hcol[(int64_t)r * hld + threadIdx.x];
+    const c128 hv = h[(int64_t)r * hld + threadIdx.x];
     const double sc = scale[(int64_t)threadIdx.x * nrhs + r];
     hs[threadIdx.x] = cmk(hv.x * sc, hv.y * sc);
   }
   __syncthreads();
   double acc[1] = {0.0};
-  const Cx<RW>* wr = w + (int64_t)r * n;
-  const c64* Ur = U + (int64_t)r * n;
-  c64* out = U + (int64_t)nb * vstride + (int64_t)r * n;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    const Cx<RW> bw = wr[p];
-    double vx = (double)bw.x, vy = (double)bw.y;
+  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * n);
+  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * n);
+  Pair<float>* out = reinterpret_cast<Pair<float>*>(U + (int64_t)nb * vstride + (int64_t)r * n);
+  const int64_t np = n / 2, vs = vstride / 2;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const Pair<RW> bw = wr[p];
+    double v0x = (double)bw.a.x, v0y = (double)bw.a.y, v1x = (double)bw.b.x, v1y = (double)bw.b.y;
 #pragma unroll
     for (int i = 0; i < NBMAX; ++i) {
       if (i < nb) {
-        const c64 a = Ur[i * vstride + p];
+        const Pair<float> u = Ur[i * vs + p];
         const c128 hi = hs[i];
-        vx -= hi.x * (double)a.x - hi.y * (double)a.y;
-        vy -= hi.x * (double)a.y + hi.y * (double)a.x;
+        v0x -= hi.x * (double)u.a.x - hi.y * (double)u.a.y;
+        v0y -= hi.x * (double)u.a.y + hi.y * (double)u.a.x;
+        v1x -= hi.x * (double)u.b.x - hi.y * (double)u.b.y;
+        v1y -= hi.x * (double)u.b.y + hi.y * (double)u.b.x;
       }
     }
-    const c64 st = cmk((float)vx, (float)vy);
+    Pair<float> st;
+    st.a = cmk((float)v0x, (float)v0y);
+    st.b = cmk((float)v1x, (float)v1y);
     out[p] = st;
-    acc[0] += (double)st.x * st.x + (double)st.y * st.y;
+    acc[0] += (double)st.a.x * st.a.x + (double)st.a.y * st.a.y + (double)st.b.x * st.b.x + (double)st.b.y * st.b.y;
   }
-  __shared__ double nn_s;
-  if (!reduce_last_block(acc, 1, part, counter, r, &nn_s, lds)) return;
-  const double nn = nn_s;
-  if (threadIdx.x != 0) return;
-  const double beta = sqrt(fmax(nn, 0.0));
-  scale[(int64_t)nb * nrhs + r] = beta > 0.0 ? 1.0 / beta : 0.0;
-  c128* col = H + (int64_t)r * (m + 1) * m + (int64_t)j * (m + 1);
-  for (int i = 0; i <= j; ++i) col[i] = hcol[(int64_t)r * hld + i];
-  for (int i = 0; i < j; ++i) {
-    const double c = cs[r * m + i];
-    const c128 s = sn[r * m + i];
-    const c128 a = col[i], b = col[i + 1];
-    col[i] = c * a + s * b;
-    col[i + 1] = c * b - conj(s) * a;
-  }
-  const c128 a = col[j];
-  const double aa = sqrt(cabs2(a));
-  const double rho = sqrt(aa * aa + beta * beta);
-  double c;
-  c128 s;
-  if (rho == 0.0) {
-    c = 1.0;
-    s = cmk(0.0, 0.0);
-    col[j] = cmk(0.0, 0.0);
-  } else if (aa == 0.0) {
-    c = 0.0;
-    s = cmk(1.0, 0.0);
-    col[j] = cmk(beta, 0.0);
-  } else {
-    const c128 ph = cmk(a.x / aa, a.y / aa);
-    c = aa / rho;
-    s = (beta / rho) * ph;
-    col[j] = rho * ph;
-  }
-  cs[r * m + j] = c;
-  sn[r * m + j] = s;
-  c128* gr = g + (int64_t)r * (m + 1);
-  const c128 gj = gr[j];
-  gr[j + 1] = cmk(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
-  gr[j] = c * gj;
-  res[r] = sqrt(cabs2(gr[j + 1]));
+  reduce_or_partial(acc, 1, lds, red, part, f, r);
 }
 
+// Workgroups per RHS: about 16 element pairs per thread, at most 2048 / nrhs in total
+// (bounds the partial sums).  One workgroup per RHS finishes the pass in the same launch.
 int gs_blocks(int64_t n, int nrhs) {
-  const int64_t want = ceil_div(n, 4096);
-  const int64_t cap = std::max<int64_t>(1, 2048 / std::max(1, nrhs));
-  return (int)std::max<int64_t>(1, std::min(want, cap));
+  nrhs = std::max(1, nrhs);
+  int64_t g = ceil_div(n, 2 * 256 * 16);
+  g = std::min<int64_t>(g, std::max(1, 2048 / nrhs));
+  return (int)std::max<int64_t>(1, g);
+}
+
+void launch_partial_finish(dmlmc_ctx* ctx, const double* part, int G, int nv, const Fin& f, int nrhs) {
+  if (G <= 1) return;
+  hipLaunchKernelGGL(partial_finish_kernel, dim3(nrhs), dim3(64), 0, ctx->stream, part, G, nv, f);
+  LAUNCH_CHECK();
+}
+
+Fin base_fin(const KrylovArrays& k, int j, int nrhs) {
+  Fin f;
+  f.j = j;
+  f.m = k.m;
+  f.hld = k.hld;
+  f.nrhs = nrhs;
+  f.H = k.H;
+  f.cs = k.cs;
+  f.sn = k.sn;
+  f.g = k.g;
+  f.res = k.res;
+  f.invb = k.invb;
+  return f;
 }
 
 }  // namespace
 
 int gs_max_basis() { return NBMAX; }
 
-// One Arnoldi step: orthogonalise w (FP64, [nrhs][n]) against V_0..V_j (RV) by CGS2,
-// update the Hessenberg column and rotations, store V_{j+1} = w / ||w||.  w is
-// overwritten by the once-orthogonalised vector.
+// One Arnoldi step, two-pass form: orthogonalise w (FP64, [nrhs][n]) against V_0..V_j,
+// update the Hessenberg column and rotations, store V_{j+1} = w / ||w||.
 template <typename RV>
 void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs, const KrylovArrays& k) {
   const int nb = j + 1;
-  if (nb > NBMAX) throw DmlmcError(DMLMC_EINVAL, "Krylov basis larger than the fused Gram-Schmidt limit");
+  if (nb > NBMAX) throw DmlmcError(DMLMC_EINVAL, "Krylov basis larger than the Gram-Schmidt limit");
   const int64_t vstride = (int64_t)nrhs * n;
-  const int G = gs_blocks(n, nrhs);
+  const int G = gs_blocks(2 * n, nrhs);  // one element per thread and iteration here
   ctx->scratch_dots.ensure(sizeof(double) * (size_t)nrhs * G * NVMAX);
   double* part = ctx->scratch_dots.as<double>();
   dim3 grid(G, nrhs);
+  Fin fa = base_fin(k, j, nrhs);
+  fa.mode = FIN_STORE;
+  fa.out = (double*)k.h1;
+  fa.ostride = 2 * k.hld;
   {
     KTimer kt(ctx, "gs_dots", (double)nrhs * n * (nb * sizeof(Cx<RV>) + sizeof(c128)));
-    hipLaunchKernelGGL((gs_dots_kernel<RV>), grid, dim3(256), 0, ctx->stream, V, nb, w, n, vstride, part, k.counter,
-                       k.h1, k.hld);
+    hipLaunchKernelGGL((gs_dots_kernel<RV>), grid, dim3(256), 0, ctx->stream, V, nb, w, n, vstride, part, fa);
     LAUNCH_CHECK();
+    launch_partial_finish(ctx, part, G, 2 * nb, fa, nrhs);
   }
+  Fin fb = base_fin(k, j, nrhs);
+  fb.mode = FIN_STORE;
+  fb.out = k.nrm2;
+  fb.ostride = 1;
   {
     KTimer kt(ctx, "gs_update", (double)nrhs * n * (nb * sizeof(Cx<RV>) + 2 * sizeof(c128)));
     hipLaunchKernelGGL((gs_update_norm_kernel<RV>), grid, dim3(256), 0, ctx->stream, V, nb, w, n, vstride, k.h1,
-                       k.hld, part, k.counter, k.nrm2);
+                       k.hld, part, fb);
     LAUNCH_CHECK();
+    launch_partial_finish(ctx, part, G, 1, fb, nrhs);
   }
+  Fin fc = base_fin(k, j, nrhs);
+  fc.mode = FIN_CGS2;
+  fc.h1 = k.h1;
+  fc.h = k.h2;
+  fc.nrm2 = k.nrm2;
   {
     KTimer kt(ctx, "gs_dots", (double)nrhs * n * (nb * sizeof(Cx<RV>) + sizeof(c128)));
-    hipLaunchKernelGGL((gs_dots_finish_kernel<RV>), grid, dim3(256), 0, ctx->stream, V, nb, w, n, vstride, part,
-                       k.counter, j, k.m, k.h1, k.h2, k.hld, k.nrm2, k.H, k.cs, k.sn, k.g, k.res, k.invb);
+    hipLaunchKernelGGL((gs_dots_kernel<RV>), grid, dim3(256), 0, ctx->stream, V, nb, w, n, vstride, part, fc);
     LAUNCH_CHECK();
+    launch_partial_finish(ctx, part, G, 2 * nb, fc, nrhs);
   }
   {
     KTimer kt(ctx, "gs_update", (double)nrhs * n * (nb * sizeof(Cx<RV>) + sizeof(c128) + sizeof(Cx<RV>)));
@@ -388,32 +416,42 @@ void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs
   }
 }
 
+// One Arnoldi step, single-pass form on an unnormalised complex-FP32 basis.
 template <typename RW>
 void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, int j, int64_t n, int nrhs,
                        const KrylovArrays& k) {
   const int nb = j + 1;
-  if (nb > NBMAX) throw DmlmcError(DMLMC_EINVAL, "Krylov basis larger than the fused Gram-Schmidt limit");
+  if (nb > NBMAX) throw DmlmcError(DMLMC_EINVAL, "Krylov basis larger than the Gram-Schmidt limit");
   const int64_t vstride = (int64_t)nrhs * n;
   const int G = gs_blocks(n, nrhs);
   ctx->scratch_dots.ensure(sizeof(double) * (size_t)nrhs * G * NVMAX);
   double* part = ctx->scratch_dots.as<double>();
   dim3 grid(G, nrhs);
+  Fin fa = base_fin(k, j, nrhs);
+  fa.mode = FIN_SCALED;
+  fa.h = k.h1;
+  fa.scale = scale;
   {
     KTimer kt(ctx, "gs_dots", (double)nrhs * n * (nb * sizeof(c64) + sizeof(Cx<RW>)));
-    hipLaunchKernelGGL((gs1_dots_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, scale, nrhs,
-                       part, k.counter, k.h1, k.hld);
+    hipLaunchKernelGGL((gs1_dots_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, part, fa);
     LAUNCH_CHECK();
+    launch_partial_finish(ctx, part, G, 2 * nb, fa, nrhs);
   }
+  Fin fb = base_fin(k, j, nrhs);
+  fb.mode = FIN_CGS1;
+  fb.h1 = k.h1;
+  fb.scale = scale;
   {
     KTimer kt(ctx, "gs_update", (double)nrhs * n * ((nb + 1) * sizeof(c64) + sizeof(Cx<RW>)));
-    hipLaunchKernelGGL((gs1_update_finish_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, scale,
-                       nrhs, part, k.counter, j, k.m, k.h1, k.hld, k.H, k.cs, k.sn, k.g, k.res);
+    hipLaunchKernelGGL((gs1_update_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, k.h1, k.hld,
+                       scale, nrhs, part, fb);
     LAUNCH_CHECK();
+    launch_partial_finish(ctx, part, G, 1, fb, nrhs);
   }
 }
 
 template void arnoldi_step<double>(dmlmc_ctx*, c128*, c128*, int, int64_t, int, const KrylovArrays&);
+template void arnoldi_step<float>(dmlmc_ctx*, c64*, c128*, int, int64_t, int, const KrylovArrays&);
 template void arnoldi_step_cgs1<float>(dmlmc_ctx*, c64*, double*, const c64*, int, int64_t, int, const KrylovArrays&);
 template void arnoldi_step_cgs1<double>(dmlmc_ctx*, c64*, double*, const c128*, int, int64_t, int,
                                         const KrylovArrays&);
-template void arnoldi_step<float>(dmlmc_ctx*, c64*, c128*, int, int64_t, int, const KrylovArrays&);

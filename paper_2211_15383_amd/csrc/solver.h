@@ -12,8 +12,6 @@ struct Workspace {
 void* hier_buf(dmlmc_hier* H, const char* name, int level, size_t bytes);
 
 DevBuf& hier_devbuf(dmlmc_hier* H, const char* name, int level);
-// As hier_buf, zero-filled when (re)allocated (for self-resetting completion counters).
-void* hier_buf_zeroed(dmlmc_hier* H, const char* name, int level, size_t bytes);
 // Largest Krylov basis (vectors) the fused Gram-Schmidt passes accept.
 int gs_max_basis();
 
@@ -29,7 +27,6 @@ struct KrylovArrays {
   double* nrm2 = nullptr;
   double* res = nullptr;
   double* invb = nullptr;
-  int* counter = nullptr;  // [nrhs] completion counters of the fused reductions (self-resetting)
 };
 KrylovArrays krylov_arrays(dmlmc_hier* H, const char* prefix, int level, int m, int nrhs);
 void krylov_init(dmlmc_ctx* ctx, const KrylovArrays& k, int nrhs);

@@ -92,17 +92,6 @@ void* hier_buf(dmlmc_hier* H, const char* name, int level, size_t bytes) {
   return b.p;
 }
 
-void* hier_buf_zeroed(dmlmc_hier* H, const char* name, int level, size_t bytes) {
-  if ((int)H->ws.size() < (int)H->lv.size() + 1) H->ws.resize(H->lv.size() + 1);
-  if (!H->ws[level]) H->ws[level].reset(new Workspace());
-  DevBuf& b = H->ws[level]->bufs[name];
-  if (b.bytes < bytes) {
-    b.alloc(bytes);
-    HIPCHK(hipMemsetAsync(b.p, 0, bytes, H->ctx->stream));
-  }
-  return b.p;
-}
-
 DevBuf& hier_devbuf(dmlmc_hier* H, const char* name, int level) {
   hier_buf(H, name, level, 0);
   return H->ws[level]->bufs[name];
@@ -125,7 +114,6 @@ KrylovArrays krylov_arrays(dmlmc_hier* H, const char* prefix, int level, int m, 
   k.nrm2 = (double*)hier_buf(H, (p + "n2").c_str(), level, sizeof(double) * nrhs);
   k.res = (double*)hier_buf(H, (p + "res").c_str(), level, sizeof(double) * nrhs);
   k.invb = (double*)hier_buf(H, (p + "ib").c_str(), level, sizeof(double) * nrhs);
-  k.counter = (int*)hier_buf_zeroed(H, (p + "cnt").c_str(), level, sizeof(int) * nrhs);
   return k;
 }
 

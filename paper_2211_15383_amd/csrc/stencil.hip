@@ -282,10 +282,12 @@ __global__ __launch_bounds__(256) void coarse_gs_kernel(const Cx<R>* __restrict_
 
 // Restriction y_c = P^H x_f.  P blocks: P[cs][c][row][k] (row-major, N columns), row =
 // local site * h + dof within chirality, local site = lx + ax * lt, h = d_f / 2.
-template <typename R>
+// Thread per (coarse dof, group of RB right-hand sides): each P entry is loaded once per
+// RB vectors.
+template <typename R, int RB>
 __global__ __launch_bounds__(256) void restrict_kernel(const Cx<R>* __restrict__ P, const Cx<R>* __restrict__ xf,
                                                        Cx<R>* __restrict__ yc, int Lxf, int Ltf, int df, int ax,
-                                                       int at, int N, int nrhs, int rb) {
+                                                       int at, int N, int nrhs) {
   const int Lxc = Lxf / ax, Ltc = Ltf / at;
   const int64_t Vc = (int64_t)Lxc * Ltc;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (cs, c, k)
@@ -298,28 +300,35 @@ __global__ __launch_bounds__(256) void restrict_kernel(const Cx<R>* __restrict__
   const int rows = ax * at * h;
   const Cx<R>* Pb = P + (cs * 2 + c) * (int64_t)rows * N + k;
   const int64_t ldf = (int64_t)Lxf * Ltf * df, ldc = Vc * 2 * N;
-  const int r0 = blockIdx.y * rb;
-  const int r1 = min(r0 + rb, nrhs);
-  for (int r = r0; r < r1; ++r) {
-    const Cx<R>* xr = xf + r * ldf;
-    Cx<R> acc = cmk((R)0, (R)0);
-    int row = 0;
-    for (int lt = 0; lt < at; ++lt) {
-      const int64_t srow = (int64_t)(T * at + lt) * Lxf + (int64_t)X * ax;
-      for (int lx = 0; lx < ax; ++lx) {
-        const int64_t fbase = (srow + lx) * df + c * h;
-        for (int j = 0; j < h; ++j, ++row) cfmac(acc, Pb[(int64_t)row * N], xr[fbase + j]);
+  const int r0 = blockIdx.y * RB;
+  const int nr = min(RB, nrhs - r0);
+  Cx<R> acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) acc[q] = cmk((R)0, (R)0);
+  const Cx<R>* xr = xf + (int64_t)r0 * ldf;
+  int row = 0;
+  for (int lt = 0; lt < at; ++lt) {
+    const int64_t srow = (int64_t)(T * at + lt) * Lxf + (int64_t)X * ax;
+    for (int lx = 0; lx < ax; ++lx) {
+      const int64_t fbase = (srow + lx) * df + c * h;
+      for (int j = 0; j < h; ++j, ++row) {
+        const Cx<R> pv = Pb[(int64_t)row * N];
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+          if (q < nr) cfmac(acc[q], pv, xr[q * ldf + fbase + j]);
       }
     }
-    yc[r * ldc + cs * 2 * N + c * N + k] = acc;
   }
+#pragma unroll
+  for (int q = 0; q < RB; ++q)
+    if (q < nr) yc[(int64_t)(r0 + q) * ldc + cs * 2 * N + c * N + k] = acc[q];
 }
 
-// Prolongation x_f (+)= P e_c; thread per fine (site, dof).
-template <typename R>
+// Prolongation x_f (+)= P e_c; thread per (fine dof, group of RB right-hand sides).
+template <typename R, int RB>
 __global__ __launch_bounds__(256) void prolong_kernel(const Cx<R>* __restrict__ P, const Cx<R>* __restrict__ ec,
                                                       Cx<R>* __restrict__ xf, int Lxf, int Ltf, int df, int ax, int at,
-                                                      int N, int nrhs, int rb, int add) {
+                                                      int N, int nrhs, int add) {
   const int64_t nf = (int64_t)Lxf * Ltf * df;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= nf) return;
@@ -335,16 +344,23 @@ __global__ __launch_bounds__(256) void prolong_kernel(const Cx<R>* __restrict__ 
   const int rows = ax * at * h;
   const Cx<R>* Pr = P + ((cs * 2 + c) * (int64_t)rows + row) * N;
   const int64_t ldc = Vc * 2 * N;
-  const int r0 = blockIdx.y * rb;
-  const int r1 = min(r0 + rb, nrhs);
-  for (int r = r0; r < r1; ++r) {
-    const Cx<R>* er = ec + r * ldc + cs * 2 * N + c * N;
-    Cx<R> acc = add ? xf[r * nf + tid] : cmk((R)0, (R)0);
-    for (int kk = 0; kk < N; ++kk) cfma(acc, Pr[kk], er[kk]);
-    xf[r * nf + tid] = acc;
+  const int r0 = blockIdx.y * RB;
+  const int nr = min(RB, nrhs - r0);
+  const Cx<R>* er = ec + (int64_t)r0 * ldc + cs * 2 * N + c * N;
+  Cx<R> acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q)
+    acc[q] = (add && q < nr) ? xf[(int64_t)(r0 + q) * nf + tid] : cmk((R)0, (R)0);
+  for (int kk = 0; kk < N; ++kk) {
+    const Cx<R> pv = Pr[kk];
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (q < nr) cfma(acc[q], pv, er[q * ldc + kk]);
   }
+#pragma unroll
+  for (int q = 0; q < RB; ++q)
+    if (q < nr) xf[(int64_t)(r0 + q) * nf + tid] = acc[q];
 }
-
 
 // ---------------------------------------------------------------- matrix-core forms (d = 16, complex FP32)
 // One wavefront computes a 16 (dofs) x 16 (RHS) tile of one site with v_mfma_f32_16x16x4_f32:
@@ -359,20 +375,47 @@ __device__ __forceinline__ void cmfma(f32x4& dre, f32x4& dim, c64 a, c64 x) {
   dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x.x, dim, 0, 0, 0);
 }
 
-// D += sum_dir A[s][dir] X[nb(dir)] for the tile (rows of the site, RHS r0..r0+15).
-__device__ __forceinline__ void site_product16(const c64* __restrict__ A, const c64* __restrict__ in, int64_t s,
-                                               const int64_t* sites, int64_t ldx, int rhs, bool rv, int row, int kq,
-                                               f32x4& dre, f32x4& dim) {
-  const c64* xr = in + (int64_t)rhs * ldx;
+// The five x tiles (16 RHS x 16 dofs each) a site needs are first staged in LDS with
+// 16-byte loads, one 128-byte row per RHS; rows are padded to 17 entries so that the
+// B-operand reads (16 lanes, consecutive RHS, one dof) hit distinct banks.
+constexpr int XPAD = 17;
+
+struct __align__(16) C64Pair {
+  c64 a, b;
+};
+
+__device__ __forceinline__ void stage_x_tiles(const c64* __restrict__ x, int64_t ld, const int64_t* sites, int r0,
+                                              int nrhs, bool valid, c64 (*Xl)[16][XPAD]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int q = lane + 64 * u;
+    const int rr = q >> 3, part = q & 7;
+    const bool ok = valid && (r0 + rr < nrhs);
+#pragma unroll
+    for (int dir = 0; dir < 5; ++dir) {
+      C64Pair v;
+      if (ok) {
+        v = *reinterpret_cast<const C64Pair*>(x + (int64_t)(r0 + rr) * ld + sites[dir] * 16 + 2 * part);
+      } else {
+        v.a = cmk(0.f, 0.f);
+        v.b = v.a;
+      }
+      Xl[dir][rr][2 * part] = v.a;
+      Xl[dir][rr][2 * part + 1] = v.b;
+    }
+  }
+}
+
+// D += sum_dir A[s][dir] X[nb(dir)] for the tile, X from the LDS tiles.
+__device__ __forceinline__ void site_product16(const c64* __restrict__ A, int64_t s, c64 (*Xl)[16][XPAD], int row,
+                                               int kq, f32x4& dre, f32x4& dim) {
   for (int dir = 0; dir < 5; ++dir) {
     const c64* Ad = A + (s * 5 + dir) * 256;
-    const c64* xb = xr + sites[dir] * 16;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int j = 4 * t + kq;
-      const c64 a = Ad[j * 16 + row];
-      const c64 x = rv ? xb[j] : cmk(0.f, 0.f);
-      cmfma(dre, dim, a, x);
+      cmfma(dre, dim, Ad[j * 16 + row], Xl[dir][row][j]);
     }
   }
 }
@@ -381,21 +424,24 @@ template <bool G5>
 __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ in,
                                                             c64* __restrict__ out, int Lx, int Lt, int nrhs,
                                                             int64_t ldx, int64_t ldy) {
+  __shared__ c64 Xs[4][5][16][XPAD];
   const int64_t V = (int64_t)Lx * Lt;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ntile = (nrhs + 15) / 16;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int64_t s = wave / ntile;
-  if (s >= V) return;  // uniform per wavefront; no block-level synchronisation below
+  const int64_t wave = (int64_t)blockIdx.x * 4 + w;
+  const int64_t s0 = wave / ntile;
+  const bool valid = s0 < V;  // every wavefront reaches the barrier
+  const int64_t s = valid ? s0 : 0;
   const int tile = (int)(wave % ntile);
   const int row = lane & 15, kq = lane >> 4;
   const int rhs = tile * 16 + row;
-  const bool rv = rhs < nrhs;
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
+  stage_x_tiles(in, ldx, sites, tile * 16, nrhs, valid, Xs[w]);
+  __syncthreads();
   f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
-  site_product16(A, in, s, sites, ldx, rv ? rhs : 0, rv, row, kq, dre, dim);
-  if (!rv) return;
+  site_product16(A, s, Xs[w], row, kq, dre, dim);
+  if (!valid || rhs >= nrhs) return;
   c64* o = out + (int64_t)rhs * ldy + s * 16;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -407,11 +453,12 @@ __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restric
 
 // Red/black point-block Gauss-Seidel, d = 16: R = b - D x on the colour sites, then
 // x += A_ss^-1 R, both products on the matrix cores; R passes through LDS to reach the
-// B-operand layout.  Every wavefront reaches the barrier (no early exit).
+// B-operand layout.  Every wavefront reaches the barriers (no early exit).
 __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ Ainv,
                                                                c64* __restrict__ x, const c64* __restrict__ b, int Lx,
                                                                int Lt, int nrhs, int color, int even_lx) {
-  __shared__ c64 Rl[4][16][16];  // [wave][dof][rhs]
+  __shared__ c64 Xs[4][5][16][XPAD];
+  __shared__ c64 Rl[4][16][XPAD];  // [wave][rhs][dof]
   const int64_t V = (int64_t)Lx * Lt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ntile = (nrhs + 15) / 16;
@@ -436,13 +483,15 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const c64* __rest
   const int64_t ld = V * 16;
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
+  stage_x_tiles(x, ld, sites, tile * 16, nrhs, active, Xs[w]);
+  __syncthreads();
   f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
-  site_product16(A, x, s, sites, ld, rv ? rhs : 0, rv, row, kq, dre, dim);
+  site_product16(A, s, Xs[w], row, kq, dre, dim);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = 4 * kq + v;
     const c64 bb = rv ? b[(int64_t)rhs * ld + s * 16 + i] : cmk(0.f, 0.f);
-    Rl[w][i][row] = cmk(bb.x - dre[v], bb.y - dim[v]);
+    Rl[w][row][i] = cmk(bb.x - dre[v], bb.y - dim[v]);
   }
   __syncthreads();
   f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = {0.f, 0.f, 0.f, 0.f};
@@ -450,14 +499,14 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const c64* __rest
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int j = 4 * t + kq;
-    cmfma(ere, eim, Ai[j * 16 + row], Rl[w][j][row]);
+    cmfma(ere, eim, Ai[j * 16 + row], Rl[w][row][j]);
   }
   if (!rv) return;
   c64* xo = x + (int64_t)rhs * ld + s * 16;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = 4 * kq + v;
-    const c64 o = xo[i];
+    const c64 o = Xs[w][0][row][i];  // x_s before the update (staged above)
     xo[i] = cmk(o.x + ere[v], o.y + eim[v]);
   }
 }
@@ -585,12 +634,12 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
   const Cx<R>* P = std::is_same<R, float>::value ? (const Cx<R>*)L.P32.p : (const Cx<R>*)L.P64.p;
   const int64_t Vc = (int64_t)(L.Lx / L.ax) * (L.Lt / L.at);
   const int64_t threads = Vc * 2 * L.N;
-  const int rb = rhs_block_for(threads, nrhs);
   KTimer kt(ctx, "restrict",
             (double)nrhs * (L.n() + threads) * sizeof(Cx<R>) + (double)L.n() * L.N * sizeof(Cx<R>));
-  dim3 grid((unsigned)ceil_div(threads, 256), (unsigned)ceil_div(nrhs, rb));
-  hipLaunchKernelGGL((restrict_kernel<R>), grid, dim3(256), 0, ctx->stream, P, xf, yc, L.Lx, L.Lt, L.dofs, L.ax,
-                     L.at, L.N, nrhs, rb);
+  constexpr int RB = 4;
+  dim3 grid((unsigned)ceil_div(threads, 256), (unsigned)ceil_div(nrhs, RB));
+  hipLaunchKernelGGL((restrict_kernel<R, RB>), grid, dim3(256), 0, ctx->stream, P, xf, yc, L.Lx, L.Lt, L.dofs, L.ax,
+                     L.at, L.N, nrhs);
   LAUNCH_CHECK();
 }
 
@@ -598,13 +647,13 @@ template <typename R>
 void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, int nrhs, bool add) {
   const Cx<R>* P = std::is_same<R, float>::value ? (const Cx<R>*)L.P32.p : (const Cx<R>*)L.P64.p;
   const int64_t nf = L.n();
-  const int rb = rhs_block_for(nf, nrhs);
   const int64_t nc = (int64_t)(L.Lx / L.ax) * (L.Lt / L.at) * 2 * L.N;
   KTimer kt(ctx, "prolong",
             (double)nrhs * ((add ? 2 : 1) * nf + nc) * sizeof(Cx<R>) + (double)nf * L.N * sizeof(Cx<R>));
-  dim3 grid((unsigned)ceil_div(nf, 256), (unsigned)ceil_div(nrhs, rb));
-  hipLaunchKernelGGL((prolong_kernel<R>), grid, dim3(256), 0, ctx->stream, P, ec, xf, L.Lx, L.Lt, L.dofs, L.ax,
-                     L.at, L.N, nrhs, rb, add ? 1 : 0);
+  constexpr int RB = 4;
+  dim3 grid((unsigned)ceil_div(nf, 256), (unsigned)ceil_div(nrhs, RB));
+  hipLaunchKernelGGL((prolong_kernel<R, RB>), grid, dim3(256), 0, ctx->stream, P, ec, xf, L.Lx, L.Lt, L.dofs, L.ax,
+                     L.at, L.N, nrhs, add ? 1 : 0);
   LAUNCH_CHECK();
 }
 
