@@ -263,8 +263,12 @@ dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p
  * events on the context stream and accumulates their durations.  Classes:
  * "wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong", "gs_dots", "gs_update",
  * "defl_gemm".  dmlmc_timing_get returns (launches, total milliseconds, bytes per
- * launch summed) for a class. */
+ * launch summed; flops for "defl_gemm") for a class.
+ * dmlmc_timing_select restricts the bracketing to a comma-separated list of classes
+ * (NULL or "" = every class), so that a timed run carries events only around the kernels
+ * it measures.  Unknown names are accepted and simply never match. */
 dmlmc_status dmlmc_timing_enable(dmlmc_ctx *ctx, int enable);
+dmlmc_status dmlmc_timing_select(dmlmc_ctx *ctx, const char *classes);
 dmlmc_status dmlmc_timing_reset(dmlmc_ctx *ctx);
 dmlmc_status dmlmc_timing_get(dmlmc_ctx *ctx, const char *cls, int64_t *launches, double *ms,
                               double *bytes);

@@ -47,6 +47,7 @@ void check_level(const dmlmc_hier* h, int level) {
 // ---------------------------------------------------------------- timing
 KTimer::KTimer(dmlmc_ctx* c, const char* k, double b) : ctx(c), cls(k), bytes(b) {
   if (!ctx || !ctx->timing) return;
+  if (!ctx->timing_only.empty() && !ctx->timing_only.count(k)) return;
   if (!ctx->event_pool.empty()) {
     e0 = ctx->event_pool.back().first;
     e1 = ctx->event_pool.back().second;
@@ -507,6 +508,24 @@ dmlmc_status dmlmc_timing_enable(dmlmc_ctx* ctx, int enable) {
   return guarded(ctx, [&]() {
     timing_collect(ctx);
     ctx->timing = enable != 0;
+  });
+}
+
+dmlmc_status dmlmc_timing_select(dmlmc_ctx* ctx, const char* classes) {
+  if (!ctx) return DMLMC_EINVAL;
+  return guarded(ctx, [&]() {
+    timing_collect(ctx);
+    ctx->timing_only.clear();
+    if (!classes) return;
+    std::string all(classes), cur;
+    for (char c : all + ",") {
+      if (c == ',') {
+        if (!cur.empty()) ctx->timing_only.insert(cur);
+        cur.clear();
+      } else if (c != ' ') {
+        cur += c;
+      }
+    }
   });
 }
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -133,6 +134,7 @@ struct dmlmc_ctx {
   bool own_stream = false;
   std::string err;
   bool timing = false;
+  std::set<std::string> timing_only;  // empty: every class
   std::map<std::string, TimerClass> timers;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
   DevBuf scratch_dots;   // reduction partials
@@ -158,8 +160,9 @@ struct Level {
   double m0 = 0.0;
   // fine level: links U[mu][site] with the antiperiodic sign folded into U_t(., Lt-1)
   DevBuf U64, U32;
-  // coarse levels: blocks A[site][5][d][d] and inverse self blocks [site][d][d], each
-  // block column-major (entry (i, j) at j * d + i)
+  // coarse levels: blocks A[site][5][d][d] and inverse self blocks [site][d][d]; FP64
+  // blocks column-major (entry (i, j) at j * d + i); FP32 blocks the same except at
+  // d = 16, where they are row-major (entry (i, j) at i * 16 + j, the matrix-core layout)
   DevBuf A64, A32, Ainv64, Ainv32;
   // interpolation to level l+1 (if not coarsest): blocks P[cs][chir][row][k]
   int ax = 0, at = 0, N = 0;

@@ -9,6 +9,10 @@
 //   A: h_i = s_i <u_i, w>                (read U, w)
 //   B: u_{j+1} = w - sum_i h_i s_i u_i, ||u_{j+1}||^2, Hessenberg column, Givens, s_{j+1}
 //
+// Small vectors (n <= 16384, the coarsest levels) take the single-pass step in one
+// 1024-thread workgroup per RHS: dots, reduction, update, norm and the Givens step in
+// one launch, the basis re-read from L2.
+//
 // Reductions: each workgroup reduces in LDS; with one workgroup per RHS the workgroup
 // finishes the pass itself, otherwise it writes partial sums and a small kernel (one
 // workgroup per RHS) adds them in a fixed order.  No atomics or device-scope fences.
@@ -262,10 +266,12 @@ __global__ __launch_bounds__(256) void gs_update_store_kernel(Cx<RV>* __restrict
 template <typename RW>
 __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U, int nb,
                                                        const Cx<RW>* __restrict__ w, int64_t n, int64_t vstride,
-                                                       double* __restrict__ part, Fin f) {
+                                                       const double* __restrict__ wscale, double* __restrict__ part,
+                                                       Fin f) {
   __shared__ double lds[4 * NVMAX];
   __shared__ double red[NVMAX];
   const int r = blockIdx.y;
+  const double ws = wscale ? wscale[r] : 1.0;
   double acc[NVMAX];
 #pragma unroll
   for (int q = 0; q < NVMAX; ++q) acc[q] = 0.0;
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U
   const int64_t np = n / 2, vs = vstride / 2;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
     const Pair<RW> bw = wr[p];
-    const double b0x = (double)bw.a.x, b0y = (double)bw.a.y, b1x = (double)bw.b.x, b1y = (double)bw.b.y;
+    const double b0x = ws * bw.a.x, b0y = ws * bw.a.y, b1x = ws * bw.b.x, b1y = ws * bw.b.y;
 #pragma unroll
     for (int i = 0; i < NBMAX; ++i) {
       if (i < nb) {
@@ -292,11 +298,13 @@ template <typename RW>
 __global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, int nb, const Cx<RW>* __restrict__ w,
                                                          int64_t n, int64_t vstride, const c128* __restrict__ h,
                                                          int hld, const double* __restrict__ scale, int nrhs,
-                                                         double* __restrict__ part, Fin f) {
+                                                         const double* __restrict__ wscale, double* __restrict__ part,
+                                                         Fin f) {
   __shared__ double lds[4 * NVMAX];
   __shared__ double red[NVMAX];
   __shared__ c128 hs[NBMAX];
   const int r = blockIdx.y;
+  const double ws = wscale ? wscale[r] : 1.0;
   if (threadIdx.x < nb) {
     const c128 hv = h[(int64_t)r * hld + threadIdx.x];
     const double sc = scale[(int64_t)threadIdx.x * nrhs + r];
@@ -310,7 +318,7 @@ __global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, in
   const int64_t np = n / 2, vs = vstride / 2;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
     const Pair<RW> bw = wr[p];
-    double v0x = (double)bw.a.x, v0y = (double)bw.a.y, v1x = (double)bw.b.x, v1y = (double)bw.b.y;
+    double v0x = ws * bw.a.x, v0y = ws * bw.a.y, v1x = ws * bw.b.x, v1y = ws * bw.b.y;
 #pragma unroll
     for (int i = 0; i < NBMAX; ++i) {
       if (i < nb) {
@@ -329,6 +337,118 @@ __global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, in
     acc[0] += (double)st.a.x * st.a.x + (double)st.a.y * st.a.y + (double)st.b.x * st.b.x + (double)st.b.y * st.b.y;
   }
   reduce_or_partial(acc, 1, lds, red, part, f, r);
+}
+
+// Whole single-pass step for RHS blockIdx.x in one workgroup of 1024 threads; element
+// pair p of the vectors belongs to thread p % 1024 (PPT pairs per thread, n <= 2048 PPT).
+constexpr int FUSED_THREADS = 1024;
+constexpr int FUSED_PPT = 8;
+constexpr int FUSED_CHUNK = 8;  // basis vectors per reduction round
+
+template <typename RW>
+__global__ __launch_bounds__(FUSED_THREADS) void gs1_fused_kernel(c64* __restrict__ U, int nb,
+                                                                  const Cx<RW>* __restrict__ w, int64_t n,
+                                                                  int64_t vstride, const double* __restrict__ wscale,
+                                                                  Fin f) {
+  constexpr int NW = FUSED_THREADS / 64;
+  __shared__ double lds[NW][2 * FUSED_CHUNK];
+  __shared__ double red[NVMAX];
+  __shared__ c128 cf[NBMAX];  // h_i s_i, the coefficients of the unnormalised u_i
+  const int r = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nrhs = f.nrhs;
+  const double ws = wscale ? wscale[r] : 1.0;
+  const int64_t np = n / 2, vs = vstride / 2;
+  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * n);
+  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * n);
+  Pair<RW> wl[FUSED_PPT];
+#pragma unroll
+  for (int q = 0; q < FUSED_PPT; ++q) {
+    const int64_t p = tid + (int64_t)q * FUSED_THREADS;
+    if (p < np) {
+      wl[q] = wr[p];
+    } else {
+      wl[q].a = cmk((RW)0, (RW)0);
+      wl[q].b = wl[q].a;
+    }
+  }
+  // h_i = s_i <u_i, ws w>, FUSED_CHUNK basis vectors per reduction round
+  for (int c0 = 0; c0 < nb; c0 += FUSED_CHUNK) {
+    double acc[2 * FUSED_CHUNK];
+#pragma unroll
+    for (int q = 0; q < 2 * FUSED_CHUNK; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < FUSED_CHUNK; ++i) {
+      if (c0 + i < nb) {
+#pragma unroll
+        for (int q = 0; q < FUSED_PPT; ++q) {
+          const int64_t p = tid + (int64_t)q * FUSED_THREADS;
+          if (p < np) {
+            const Pair<float> u = Ur[(c0 + i) * vs + p];
+            const Pair<RW> b = wl[q];
+            acc[2 * i] += (double)u.a.x * b.a.x + (double)u.a.y * b.a.y + (double)u.b.x * b.b.x +
+                          (double)u.b.y * b.b.y;
+            acc[2 * i + 1] += (double)u.a.x * b.a.y - (double)u.a.y * b.a.x + (double)u.b.x * b.b.y -
+                              (double)u.b.y * b.b.x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * FUSED_CHUNK; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0) lds[wv][q] = v;
+    }
+    __syncthreads();
+    if (tid < 2 * FUSED_CHUNK && c0 + tid / 2 < nb) {
+      double sum = 0.0;
+      for (int k = 0; k < NW; ++k) sum += lds[k][tid];
+      red[2 * c0 + tid] = sum;
+    }
+    __syncthreads();
+  }
+  if (tid < nb) {
+    const double sc = f.scale[(int64_t)tid * nrhs + r];
+    const c128 h = cmk(ws * sc * red[2 * tid], ws * sc * red[2 * tid + 1]);
+    f.h[(int64_t)r * f.hld + tid] = h;
+    cf[tid] = cmk(h.x * sc, h.y * sc);
+  }
+  __syncthreads();
+  // u_{j+1} = ws w - sum_i (h_i s_i) u_i, its norm from the stored FP32 values
+  Pair<float>* out = reinterpret_cast<Pair<float>*>(U + (int64_t)nb * vstride + (int64_t)r * n);
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < FUSED_PPT; ++q) {
+    const int64_t p = tid + (int64_t)q * FUSED_THREADS;
+    if (p < np) {
+      double v0x = ws * wl[q].a.x, v0y = ws * wl[q].a.y, v1x = ws * wl[q].b.x, v1y = ws * wl[q].b.y;
+      for (int i = 0; i < nb; ++i) {
+        const Pair<float> u = Ur[i * vs + p];
+        const c128 hi = cf[i];
+        v0x -= hi.x * (double)u.a.x - hi.y * (double)u.a.y;
+        v0y -= hi.x * (double)u.a.y + hi.y * (double)u.a.x;
+        v1x -= hi.x * (double)u.b.x - hi.y * (double)u.b.y;
+        v1y -= hi.x * (double)u.b.y + hi.y * (double)u.b.x;
+      }
+      Pair<float> st;
+      st.a = cmk((float)v0x, (float)v0y);
+      st.b = cmk((float)v1x, (float)v1y);
+      out[p] = st;
+      nrm += (double)st.a.x * st.a.x + (double)st.a.y * st.a.y + (double)st.b.x * st.b.x + (double)st.b.y * st.b.y;
+    }
+  }
+  nrm = wave_sum(nrm);
+  if (lane == 0) lds[wv][0] = nrm;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int k = 0; k < NW; ++k) sum += lds[k][0];
+    const double beta = sqrt(fmax(sum, 0.0));
+    f.scale[(int64_t)nb * nrhs + r] = beta > 0.0 ? 1.0 / beta : 0.0;
+    c128* col = f.H + (int64_t)r * (f.m + 1) * f.m + (int64_t)f.j * (f.m + 1);
+    for (int i = 0; i < nb; ++i) col[i] = f.h[(int64_t)r * f.hld + i];
+    hessenberg_update(f, r, beta);
+  }
 }
 
 // Workgroups per RHS: about 16 element pairs per thread, at most 2048 / nrhs in total
@@ -419,10 +539,21 @@ void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs
 // One Arnoldi step, single-pass form on an unnormalised complex-FP32 basis.
 template <typename RW>
 void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, int j, int64_t n, int nrhs,
-                       const KrylovArrays& k) {
+                       const KrylovArrays& k, const double* wscale) {
   const int nb = j + 1;
   if (nb > NBMAX) throw DmlmcError(DMLMC_EINVAL, "Krylov basis larger than the Gram-Schmidt limit");
   const int64_t vstride = (int64_t)nrhs * n;
+  if (n <= 2 * (int64_t)FUSED_THREADS * FUSED_PPT) {
+    Fin f = base_fin(k, j, nrhs);
+    f.mode = FIN_CGS1;
+    f.h = k.h1;
+    f.scale = scale;
+    KTimer kt(ctx, "gs_dots", (double)nrhs * n * ((2 * nb + 1) * sizeof(c64) + sizeof(Cx<RW>)));
+    hipLaunchKernelGGL((gs1_fused_kernel<RW>), dim3(nrhs), dim3(FUSED_THREADS), 0, ctx->stream, U, nb, w, n, vstride,
+                       wscale, f);
+    LAUNCH_CHECK();
+    return;
+  }
   const int G = gs_blocks(n, nrhs);
   ctx->scratch_dots.ensure(sizeof(double) * (size_t)nrhs * G * NVMAX);
   double* part = ctx->scratch_dots.as<double>();
@@ -433,7 +564,7 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
   fa.scale = scale;
   {
     KTimer kt(ctx, "gs_dots", (double)nrhs * n * (nb * sizeof(c64) + sizeof(Cx<RW>)));
-    hipLaunchKernelGGL((gs1_dots_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, part, fa);
+    hipLaunchKernelGGL((gs1_dots_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale, part, fa);
     LAUNCH_CHECK();
     launch_partial_finish(ctx, part, G, 2 * nb, fa, nrhs);
   }
@@ -444,7 +575,7 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
   {
     KTimer kt(ctx, "gs_update", (double)nrhs * n * ((nb + 1) * sizeof(c64) + sizeof(Cx<RW>)));
     hipLaunchKernelGGL((gs1_update_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, k.h1, k.hld,
-                       scale, nrhs, part, fb);
+                       scale, nrhs, wscale, part, fb);
     LAUNCH_CHECK();
     launch_partial_finish(ctx, part, G, 1, fb, nrhs);
   }
@@ -452,6 +583,7 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
 
 template void arnoldi_step<double>(dmlmc_ctx*, c128*, c128*, int, int64_t, int, const KrylovArrays&);
 template void arnoldi_step<float>(dmlmc_ctx*, c64*, c128*, int, int64_t, int, const KrylovArrays&);
-template void arnoldi_step_cgs1<float>(dmlmc_ctx*, c64*, double*, const c64*, int, int64_t, int, const KrylovArrays&);
+template void arnoldi_step_cgs1<float>(dmlmc_ctx*, c64*, double*, const c64*, int, int64_t, int, const KrylovArrays&,
+                                       const double*);
 template void arnoldi_step_cgs1<double>(dmlmc_ctx*, c64*, double*, const c128*, int, int64_t, int,
-                                        const KrylovArrays&);
+                                        const KrylovArrays&, const double*);

@@ -217,6 +217,26 @@ int colour_mod(int extent) {
   return extent;
 }
 
+// FP32 copies of coarse blocks (d x d each): row-major at d = 16, the layout of the
+// matrix-core stencil kernels, column-major (as the FP64 source) otherwise.
+__global__ void cast_blocks_kernel(const c128* __restrict__ src, c64* __restrict__ dst, int64_t total, int d,
+                                   int rowmajor) {
+  const int64_t dd = (int64_t)d * d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = i / dd;
+    const int e = (int)(i % dd);
+    const int se = rowmajor ? (e % d) * d + e / d : e;
+    dst[i] = ccast<float>(src[blk * dd + se]);
+  }
+}
+
+void cast_blocks(dmlmc_ctx* ctx, const c128* src, c64* dst, int64_t nblocks, int d) {
+  const int64_t total = nblocks * d * d;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
+  hipLaunchKernelGGL(cast_blocks_kernel, dim3(grid), dim3(256), 0, ctx->stream, src, dst, total, d, d == 16 ? 1 : 0);
+  LAUNCH_CHECK();
+}
+
 }  // namespace
 
 void upload_links(dmlmc_ctx* ctx, Level& L, const double* theta_host, int antiperiodic) {
@@ -275,7 +295,7 @@ Level galerkin_level(dmlmc_ctx* ctx, const Level& F) {
     }
   }
   C.A32.alloc(sizeof(c64) * (size_t)Vc * 5 * dc * dc);
-  launch_cast<float, double>(ctx, C.A64.as<c128>(), C.A32.as<c64>(), (int64_t)Vc * 5 * dc * dc, 1, 0, 0);
+  cast_blocks(ctx, C.A64.as<c128>(), C.A32.as<c64>(), (int64_t)Vc * 5, dc);
   // inverse self blocks for the block Gauss-Seidel smoother
   C.Ainv64.alloc(sizeof(c128) * (size_t)Vc * dc * dc);
   DevBuf fail(sizeof(int));
@@ -284,7 +304,7 @@ Level galerkin_level(dmlmc_ctx* ctx, const Level& F) {
                      C.A64.as<c128>(), dc, C.Ainv64.as<c128>(), fail.as<int>());
   LAUNCH_CHECK();
   C.Ainv32.alloc(sizeof(c64) * (size_t)Vc * dc * dc);
-  launch_cast<float, double>(ctx, C.Ainv64.as<c128>(), C.Ainv32.as<c64>(), (int64_t)Vc * dc * dc, 1, 0, 0);
+  cast_blocks(ctx, C.Ainv64.as<c128>(), C.Ainv32.as<c64>(), (int64_t)Vc, dc);
   int nfail = 0;
   HIPCHK(hipMemcpyAsync(&nfail, fail.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -33,10 +33,11 @@ void krylov_init(dmlmc_ctx* ctx, const KrylovArrays& k, int nrhs);
 template <typename RV>
 void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs, const KrylovArrays& k);
 // Single-pass form: unnormalised complex-FP32 basis u_i with scales s_i = 1/||u_i||
-// (scale[i][nrhs]); w is the new vector (complex FP32 or FP64); FP64 arithmetic.
+// (scale[i][nrhs]); the new vector is wscale[r] * w (wscale NULL: factor 1), w complex
+// FP32 or FP64; FP64 arithmetic.
 template <typename RW>
 void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, int j, int64_t n, int nrhs,
-                       const KrylovArrays& k);
+                       const KrylovArrays& k, const double* wscale = nullptr);
 void krylov_solution(dmlmc_ctx* ctx, const KrylovArrays& k, int iters, int nrhs);
 // y[r][i] *= scale[i][r] for i < iters
 void krylov_scale_y(dmlmc_ctx* ctx, const KrylovArrays& k, const double* scale, int iters, int nrhs);

@@ -184,13 +184,12 @@ void coarsest_gmres(dmlmc_hier* H, int l, const Cx<R>* b_in, Cx<R>* x, int nrhs)
     // single-pass Gram-Schmidt on an unnormalised complex-FP32 basis (FP64 arithmetic)
     double* scale = (double*)hier_buf(H, "cg_sc", l, sizeof(double) * (size_t)(m + 1) * nrhs);
     c64* U = (c64*)V;
-    c64* vin = (c64*)hier_buf(H, "cg_vin32", l, sizeof(c64) * (size_t)nrhs * n);
     HIPCHK(hipMemcpyAsync(U, b, sizeof(c64) * (size_t)vstride, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(scale, k.invb, sizeof(double) * nrhs, hipMemcpyDeviceToDevice, ctx->stream));
     for (int j = 0; j < m; ++j) {
-      launch_scale_vec(ctx, U + j * vstride, scale + (int64_t)j * nrhs, vin, n, nrhs);
-      apply_op<float>(ctx, L, vin, (c64*)wr, nrhs);
-      arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k);
+      // D (s_j u_j) = s_j (D u_j): the scale enters the Gram-Schmidt step
+      apply_op<float>(ctx, L, U + j * vstride, (c64*)wr, nrhs);
+      arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k, scale + (int64_t)j * nrhs);
     }
     krylov_solution(ctx, k, m, nrhs);
     krylov_scale_y(ctx, k, scale, m, nrhs);

@@ -363,9 +363,17 @@ __global__ __launch_bounds__(256) void prolong_kernel(const Cx<R>* __restrict__ 
 }
 
 // ---------------------------------------------------------------- matrix-core forms (d = 16, complex FP32)
-// One wavefront computes a 16 (dofs) x 16 (RHS) tile of one site with v_mfma_f32_16x16x4_f32:
+// One wavefront computes 16 (dofs) x 16 (RHS) tiles of one site with v_mfma_f32_16x16x4_f32:
 // lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 (l / 16) + v][l % 16].
 // A complex product A X takes four real products (re: Ar Xr - Ai Xi, im: Ar Xi + Ai Xr).
+//
+// The contraction over the 16 input dofs is split into four K = 4 steps; step t gives the
+// k-th operand slot to dof j = 4k + t.  Lane (row, kq) = (l % 16, l / 16) therefore needs
+// A[row][4kq .. 4kq+3] (32 contiguous bytes of a row-major block) and x[rhs row][4kq .. 4kq+3]
+// (32 contiguous bytes of a vector), and the D fragment it receives (dofs 4kq .. 4kq+3 of
+// RHS row) is already in the B-operand layout of a following product.  Every operand is
+// read from global memory with two 16-byte loads per lane; nothing passes through LDS.
+// FP32 blocks at d = 16 are stored row-major for this reason (see Level).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void cmfma(f32x4& dre, f32x4& dim, c64 a, c64 x) {
@@ -375,140 +383,283 @@ __device__ __forceinline__ void cmfma(f32x4& dre, f32x4& dim, c64 a, c64 x) {
   dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x.x, dim, 0, 0, 0);
 }
 
-// The five x tiles (16 RHS x 16 dofs each) a site needs are first staged in LDS with
-// 16-byte loads, one 128-byte row per RHS; rows are padded to 17 entries so that the
-// B-operand reads (16 lanes, consecutive RHS, one dof) hit distinct banks.
-constexpr int XPAD = 17;
-
 struct __align__(16) C64Pair {
   c64 a, b;
 };
 
-__device__ __forceinline__ void stage_x_tiles(const c64* __restrict__ x, int64_t ld, const int64_t* sites, int r0,
-                                              int nrhs, bool valid, c64 (*Xl)[16][XPAD]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int q = lane + 64 * u;
-    const int rr = q >> 3, part = q & 7;
-    const bool ok = valid && (r0 + rr < nrhs);
-#pragma unroll
-    for (int dir = 0; dir < 5; ++dir) {
-      C64Pair v;
-      if (ok) {
-        v = *reinterpret_cast<const C64Pair*>(x + (int64_t)(r0 + rr) * ld + sites[dir] * 16 + 2 * part);
-      } else {
-        v.a = cmk(0.f, 0.f);
-        v.b = v.a;
-      }
-      Xl[dir][rr][2 * part] = v.a;
-      Xl[dir][rr][2 * part + 1] = v.b;
-    }
-  }
+struct Quad {
+  c64 v[4];
+};
+
+__device__ __forceinline__ Quad load_quad(const c64* __restrict__ p) {
+  const C64Pair* q = reinterpret_cast<const C64Pair*>(p);
+  const C64Pair u = q[0], w = q[1];
+  Quad r;
+  r.v[0] = u.a;
+  r.v[1] = u.b;
+  r.v[2] = w.a;
+  r.v[3] = w.b;
+  return r;
 }
 
-// D += sum_dir A[s][dir] X[nb(dir)] for the tile, X from the LDS tiles.
-__device__ __forceinline__ void site_product16(const c64* __restrict__ A, int64_t s, c64 (*Xl)[16][XPAD], int row,
-                                               int kq, f32x4& dre, f32x4& dim) {
-  for (int dir = 0; dir < 5; ++dir) {
-    const c64* Ad = A + (s * 5 + dir) * 256;
+__device__ __forceinline__ Quad zero_quad() {
+  Quad r;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int j = 4 * t + kq;
-      cmfma(dre, dim, Ad[j * 16 + row], Xl[dir][row][j]);
-    }
-  }
+  for (int v = 0; v < 4; ++v) r.v[v] = cmk(0.f, 0.f);
+  return r;
 }
 
+__device__ __forceinline__ void store_quad(c64* __restrict__ p, f32x4 re, f32x4 im, float sg) {
+  C64Pair* q = reinterpret_cast<C64Pair*>(p);
+  C64Pair u, w;
+  u.a = cmk(sg * re[0], sg * im[0]);
+  u.b = cmk(sg * re[1], sg * im[1]);
+  w.a = cmk(sg * re[2], sg * im[2]);
+  w.b = cmk(sg * re[3], sg * im[3]);
+  q[0] = u;
+  q[1] = w;
+}
+
+// D += A X for one 16 x 16 block (a: lane's A row quarter, x: lane's B quarter).
+__device__ __forceinline__ void block_mfma(f32x4& dre, f32x4& dim, const Quad& a, const Quad& x) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) cmfma(dre, dim, a.v[t], x.v[t]);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  This
+// renumbering hands every XCD a contiguous range of logical workgroups, so neighbouring
+// sites (the stencil's re-reads) are fetched through the same L2.  It is a bijection on
+// [0, gridDim.x): the largest multiple of 8 is permuted, the tail keeps its numbers.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t g = blockIdx.x, n = gridDim.x;
+  const int64_t full = n & ~(int64_t)7;
+  if (g >= full) return g;
+  return (g & 7) * (full >> 3) + (g >> 3);
+}
+
+// y_s = sum_dir A[s][dir] x_{s+dir} (optionally Gamma5 y), one site per wavefront, all
+// RHS in tiles of 16 processed two at a time (block operands loaded once per pair).
 template <bool G5>
 __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ in,
                                                             c64* __restrict__ out, int Lx, int Lt, int nrhs,
                                                             int64_t ldx, int64_t ldy) {
-  __shared__ c64 Xs[4][5][16][XPAD];
   const int64_t V = (int64_t)Lx * Lt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ntile = (nrhs + 15) / 16;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + w;
-  const int64_t s0 = wave / ntile;
-  const bool valid = s0 < V;  // every wavefront reaches the barrier
-  const int64_t s = valid ? s0 : 0;
-  const int tile = (int)(wave % ntile);
+  const int64_t s = xcd_block() * 4 + w;
+  if (s >= V) return;  // wave-uniform: the MFMAs below always run with a full wavefront
   const int row = lane & 15, kq = lane >> 4;
-  const int rhs = tile * 16 + row;
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
-  stage_x_tiles(in, ldx, sites, tile * 16, nrhs, valid, Xs[w]);
-  __syncthreads();
-  f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
-  site_product16(A, s, Xs[w], row, kq, dre, dim);
-  if (!valid || rhs >= nrhs) return;
-  c64* o = out + (int64_t)rhs * ldy + s * 16;
+  const float sg = (G5 && kq >= 2) ? -1.f : 1.f;
+  for (int r0 = 0; r0 < nrhs; r0 += 32) {
+    const int ra = r0 + row, rb = r0 + 16 + row;
+    const bool va = ra < nrhs, vb = rb < nrhs, two = r0 + 16 < nrhs;
+    f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = 4 * kq + v;
-    const float sg = (G5 && i >= 8) ? -1.f : 1.f;
-    o[i] = cmk(sg * dre[v], sg * dim[v]);
+    for (int dir = 0; dir < 5; ++dir) {
+      const Quad a = load_quad(A + (s * 5 + dir) * 256 + row * 16 + 4 * kq);
+      const int64_t off = sites[dir] * 16 + 4 * kq;
+      const Quad xa = va ? load_quad(in + (int64_t)ra * ldx + off) : zero_quad();
+      block_mfma(are, aim, a, xa);
+      if (two) {
+        const Quad xb = vb ? load_quad(in + (int64_t)rb * ldx + off) : zero_quad();
+        block_mfma(bre, bim, a, xb);
+      }
+    }
+    if (va) store_quad(out + (int64_t)ra * ldy + s * 16 + 4 * kq, are, aim, sg);
+    if (two && vb) store_quad(out + (int64_t)rb * ldy + s * 16 + 4 * kq, bre, bim, sg);
   }
 }
 
-// Red/black point-block Gauss-Seidel, d = 16: R = b - D x on the colour sites, then
-// x += A_ss^-1 R, both products on the matrix cores; R passes through LDS to reach the
-// B-operand layout.  Every wavefront reaches the barriers (no early exit).
+// Red/black point-block Gauss-Seidel, d = 16, on the sites of one colour:
+// x_s = A_ss^-1 (b_s - sum_{dir != self} A[s][dir] x_{s+dir}); the neighbours all have the
+// other colour (even extents), so the sweep over one colour is order-independent.  The
+// residual fragment stays in registers as the B operand of the inverse-block product.
 __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ Ainv,
                                                                c64* __restrict__ x, const c64* __restrict__ b, int Lx,
-                                                               int Lt, int nrhs, int color, int even_lx) {
-  __shared__ c64 Xs[4][5][16][XPAD];
-  __shared__ c64 Rl[4][16][XPAD];  // [wave][rhs][dof]
-  const int64_t V = (int64_t)Lx * Lt;
+                                                               int Lt, int nrhs, int color) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ntile = (nrhs + 15) / 16;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + w;
-  const int64_t k = wave / ntile;
-  const int tile = (int)(wave % ntile);
-  int64_t s;
-  bool active;
-  if (even_lx) {
-    const int64_t half = Lx / 2;
-    const int64_t t = k / half;
-    s = 2 * (k % half) + ((t + color) & 1) + t * Lx;
-    active = t < Lt;
-  } else {
-    s = k;
-    active = (s < V) && ((((s % Lx) + (s / Lx)) & 1) == color);
-  }
-  if (!active) s = 0;
-  const int row = lane & 15, kq = lane >> 4;
-  const int rhs = tile * 16 + row;
-  const bool rv = active && rhs < nrhs;
+  const int64_t k = xcd_block() * 4 + w;
+  const int64_t half = Lx / 2;
+  const int64_t t = k / half;
+  if (t >= Lt) return;  // wave-uniform
+  const int64_t s = 2 * (k % half) + ((t + color) & 1) + t * Lx;
+  const int64_t V = (int64_t)Lx * Lt;
   const int64_t ld = V * 16;
+  const int row = lane & 15, kq = lane >> 4;
   const Nbr nb = neighbours(s, Lx, Lt);
-  const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
-  stage_x_tiles(x, ld, sites, tile * 16, nrhs, active, Xs[w]);
-  __syncthreads();
-  f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
-  site_product16(A, s, Xs[w], row, kq, dre, dim);
+  const int64_t sites[4] = {nb.xp, nb.xm, nb.tp, nb.tm};
+  for (int r0 = 0; r0 < nrhs; r0 += 32) {
+    const int ra = r0 + row, rb = r0 + 16 + row;
+    const bool va = ra < nrhs, vb = rb < nrhs, two = r0 + 16 < nrhs;
+    f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = 4 * kq + v;
-    const c64 bb = rv ? b[(int64_t)rhs * ld + s * 16 + i] : cmk(0.f, 0.f);
-    Rl[w][row][i] = cmk(bb.x - dre[v], bb.y - dim[v]);
-  }
-  __syncthreads();
-  f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = {0.f, 0.f, 0.f, 0.f};
-  const c64* Ai = Ainv + s * 256;
+    for (int dir = 0; dir < 4; ++dir) {
+      const Quad a = load_quad(A + (s * 5 + dir + 1) * 256 + row * 16 + 4 * kq);
+      const int64_t off = sites[dir] * 16 + 4 * kq;
+      const Quad xa = va ? load_quad(x + (int64_t)ra * ld + off) : zero_quad();
+      block_mfma(are, aim, a, xa);
+      if (two) {
+        const Quad xb = vb ? load_quad(x + (int64_t)rb * ld + off) : zero_quad();
+        block_mfma(bre, bim, a, xb);
+      }
+    }
+    const int64_t own = s * 16 + 4 * kq;
+    const Quad ai = load_quad(Ainv + s * 256 + row * 16 + 4 * kq);
+    Quad q = va ? load_quad(b + (int64_t)ra * ld + own) : zero_quad();
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int j = 4 * t + kq;
-    cmfma(ere, eim, Ai[j * 16 + row], Rl[w][row][j]);
-  }
-  if (!rv) return;
-  c64* xo = x + (int64_t)rhs * ld + s * 16;
+    for (int v = 0; v < 4; ++v) q.v[v] = cmk(q.v[v].x - are[v], q.v[v].y - aim[v]);
+    f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere;
+    block_mfma(ere, eim, ai, q);
+    if (va) store_quad(x + (int64_t)ra * ld + own, ere, eim, 1.f);
+    if (two) {
+      Quad qb = vb ? load_quad(b + (int64_t)rb * ld + own) : zero_quad();
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = 4 * kq + v;
-    const c64 o = Xs[w][0][row][i];  // x_s before the update (staged above)
-    xo[i] = cmk(o.x + ere[v], o.y + eim[v]);
+      for (int v = 0; v < 4; ++v) qb.v[v] = cmk(qb.v[v].x - bre[v], qb.v[v].y - bim[v]);
+      f32x4 fre = {0.f, 0.f, 0.f, 0.f}, fim = fre;
+      block_mfma(fre, fim, ai, qb);
+      if (vb) store_quad(x + (int64_t)rb * ld + own, fre, fim, 1.f);
+    }
   }
+}
+
+// ---------------------------------------------------------------- matrix-core transfers (2N = 16, complex FP32)
+// Per aggregate, prolongation is X_f (E x b) (+)= P_full (E x 16) E_c (16 x b) and
+// restriction Y_c (16 x b) = P_full^H X_f, with E = ax at d_f fine entries ordered
+// (lt, lx, dof) and P_full[e][c N + k] = P[cs][c][row(e)][k] when chirality(e) = c, else 0.
+// Entries 4q .. 4q+3 of an aggregate are contiguous in memory (ax d_f % 4 == 0), so the
+// B operands and D fragments of both products move as 32-byte quads.
+struct AggMap {
+  int Lxf, df, ax, at, N, h, rows, E, Lxc;
+  __device__ __forceinline__ int64_t fine_offset(int64_t cs, int e) const {
+    const int X = (int)(cs % Lxc), T = (int)(cs / Lxc);
+    const int lt = e / (ax * df), rem = e % (ax * df);
+    return ((int64_t)(T * at + lt) * Lxf + (int64_t)X * ax) * df + rem;
+  }
+  // index of P[cs][c][row(e)][0] for entry e, and its chirality c
+  __device__ __forceinline__ int64_t prow(int64_t cs, int e, int& c) const {
+    const int lt = e / (ax * df), rem = e % (ax * df);
+    const int lx = rem / df, dof = rem % df;
+    c = dof / h;
+    const int row = (lx + ax * lt) * h + dof % h;
+    return ((cs * 2 + c) * (int64_t)rows + row) * N;
+  }
+};
+
+// One wavefront per (aggregate, group of mtw 16-entry tiles), all RHS, two RHS tiles at a time.
+__global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restrict__ P, const c64* __restrict__ ec,
+                                                             c64* __restrict__ xf, AggMap g, int64_t Vc, int mtw,
+                                                             int nrhs, int add) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int groups = g.E / 16 / mtw;
+  const int64_t wave = xcd_block() * 4 + w;
+  const int64_t cs = wave / groups;
+  if (cs >= Vc) return;  // wave-uniform
+  const int grp = (int)(wave % groups);
+  const int row = lane & 15, kq = lane >> 4;
+  const int64_t nf = (int64_t)g.Lxf * (Vc / g.Lxc) * g.at * g.df;
+  const int64_t ldc = Vc * 16;
+  // coarse dof 4 kq + t has chirality kq / 2 and test vector 4 (kq % 2) + t
+  const int cj = kq >> 1, k0 = 4 * (kq & 1);
+  for (int r0 = 0; r0 < nrhs; r0 += 32) {
+    const int ra = r0 + row, rb = r0 + 16 + row;
+    const bool va = ra < nrhs, vb = rb < nrhs, two = r0 + 16 < nrhs;
+    const Quad ea = va ? load_quad(ec + (int64_t)ra * ldc + cs * 16 + 4 * kq) : zero_quad();
+    const Quad eb = (two && vb) ? load_quad(ec + (int64_t)rb * ldc + cs * 16 + 4 * kq) : zero_quad();
+    for (int mt = grp * mtw; mt < (grp + 1) * mtw; ++mt) {
+      int ce;
+      const int64_t pr = g.prow(cs, 16 * mt + row, ce);
+      const Quad a = (ce == cj) ? load_quad(P + pr + k0) : zero_quad();
+      const int64_t fo = g.fine_offset(cs, 16 * mt + 4 * kq);
+      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
+      block_mfma(are, aim, a, ea);
+      if (va) {
+        c64* o = xf + (int64_t)ra * nf + fo;
+        if (add) {
+          const Quad x = load_quad(o);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            are[v] += x.v[v].x;
+            aim[v] += x.v[v].y;
+          }
+        }
+        store_quad(o, are, aim, 1.f);
+      }
+      if (two) {
+        f32x4 bre = {0.f, 0.f, 0.f, 0.f}, bim = bre;
+        block_mfma(bre, bim, a, eb);
+        if (vb) {
+          c64* o = xf + (int64_t)rb * nf + fo;
+          if (add) {
+            const Quad x = load_quad(o);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              bre[v] += x.v[v].x;
+              bim[v] += x.v[v].y;
+            }
+          }
+          store_quad(o, bre, bim, 1.f);
+        }
+      }
+    }
+  }
+}
+
+// One wavefront per aggregate, all its 16-entry tiles accumulated, two RHS tiles at a time.
+__global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restrict__ P, const c64* __restrict__ xf,
+                                                              c64* __restrict__ yc, AggMap g, int64_t Vc, int nrhs) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t cs = xcd_block() * 4 + w;
+  if (cs >= Vc) return;  // wave-uniform
+  const int row = lane & 15, kq = lane >> 4;
+  const int64_t nf = (int64_t)g.Lxf * (Vc / g.Lxc) * g.at * g.df;
+  const int64_t ldc = Vc * 16;
+  // A operand: lane (row, kq) supplies conj(P_full[e][row]) for e = 16 kt + 4 kq + t
+  const int cj = row >> 3, kj = row & 7;
+  const int ntile = g.E / 16;
+  for (int r0 = 0; r0 < nrhs; r0 += 32) {
+    const int ra = r0 + row, rb = r0 + 16 + row;
+    const bool va = ra < nrhs, vb = rb < nrhs, two = r0 + 16 < nrhs;
+    f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
+    for (int kt = 0; kt < ntile; ++kt) {
+      Quad a;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        int ce;
+        const int64_t pr = g.prow(cs, 16 * kt + 4 * kq + t, ce);
+        const c64 pv = (ce == cj) ? P[pr + kj] : cmk(0.f, 0.f);
+        a.v[t] = cmk(pv.x, -pv.y);
+      }
+      const int64_t fo = g.fine_offset(cs, 16 * kt + 4 * kq);
+      const Quad xa = va ? load_quad(xf + (int64_t)ra * nf + fo) : zero_quad();
+      block_mfma(are, aim, a, xa);
+      if (two) {
+        const Quad xb = vb ? load_quad(xf + (int64_t)rb * nf + fo) : zero_quad();
+        block_mfma(bre, bim, a, xb);
+      }
+    }
+    if (va) store_quad(yc + (int64_t)ra * ldc + cs * 16 + 4 * kq, are, aim, 1.f);
+    if (two && vb) store_quad(yc + (int64_t)rb * ldc + cs * 16 + 4 * kq, bre, bim, 1.f);
+  }
+}
+
+bool transfer16_ok(const Level& L) {
+  const int E = L.ax * L.at * L.dofs;
+  return L.N == 8 && L.dofs % 2 == 0 && (L.ax * L.dofs) % 4 == 0 && E % 16 == 0;
+}
+
+AggMap agg_map(const Level& L) {
+  AggMap g;
+  g.Lxf = L.Lx;
+  g.df = L.dofs;
+  g.ax = L.ax;
+  g.at = L.at;
+  g.N = L.N;
+  g.h = L.dofs / 2;
+  g.rows = L.ax * L.at * g.h;
+  g.E = L.ax * L.at * L.dofs;
+  g.Lxc = L.Lx / L.ax;
+  return g;
 }
 
 inline int rhs_block_for(int64_t threads, int nrhs) {
@@ -548,8 +699,9 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
   KTimer kt(ctx, "coarse",
             (double)nrhs * L.n() * 2 * sizeof(Cx<R>) + (double)V * 5 * d * d * sizeof(Cx<R>));
   if (std::is_same<R, float>::value && d == 16) {
-    const int64_t waves = V * ((nrhs + 15) / 16);
-    dim3 grid((unsigned)ceil_div(waves, 4));
+    REQUIRE(ldx % 2 == 0 && ldy % 2 == 0 && ((uintptr_t)x | (uintptr_t)y) % 16 == 0,
+            "matrix-core coarse stencil needs 16-byte aligned RHS rows");
+    dim3 grid((unsigned)ceil_div(V, 4));
     if (gamma5_left)
       hipLaunchKernelGGL((coarse16_mfma_kernel<true>), grid, dim3(256), 0, ctx->stream, (const c64*)A, (const c64*)x,
                          (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
@@ -612,15 +764,20 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
   const int even = (L.Lx % 2 == 0) ? 1 : 0;
   const int64_t nsites = even ? V / 2 : V;
   const int rb = rhs_block_for(nsites * d, nrhs);
-  KTimer kt(ctx, "coarse_gs",
-            (double)nrhs * (V / 2) * d * 4 * sizeof(Cx<R>) + (double)(V / 2) * 6 * d * d * sizeof(Cx<R>));
   if (std::is_same<R, float>::value && d == 16) {
-    const int64_t waves = nsites * ((nrhs + 15) / 16);
-    hipLaunchKernelGGL(coarse16_gs_mfma_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, ctx->stream,
-                       (const c64*)A, (const c64*)Ai, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, even);
+    // direct form: reads b and the neighbours' x, writes x (three vector passes over the
+    // colour's sites) and the four hop blocks and the inverse self block
+    REQUIRE(even && L.Lt % 2 == 0, "block Gauss-Seidel needs even extents");
+    REQUIRE(((uintptr_t)x | (uintptr_t)b) % 16 == 0, "matrix-core Gauss-Seidel needs 16-byte aligned vectors");
+    KTimer kt(ctx, "coarse_gs",
+              (double)nrhs * (V / 2) * d * 3 * sizeof(Cx<R>) + (double)(V / 2) * 5 * d * d * sizeof(Cx<R>));
+    hipLaunchKernelGGL(coarse16_gs_mfma_kernel, dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0, ctx->stream,
+                       (const c64*)A, (const c64*)Ai, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color);
     LAUNCH_CHECK();
     return;
   }
+  KTimer kt(ctx, "coarse_gs",
+            (double)nrhs * (V / 2) * d * 4 * sizeof(Cx<R>) + (double)(V / 2) * 6 * d * d * sizeof(Cx<R>));
   dim3 grid((unsigned)ceil_div(nsites, spb), (unsigned)ceil_div(nrhs, rb));
   dim3 block((unsigned)(spb * d));
   size_t shm = (size_t)spb * d * sizeof(Cx<R>);
@@ -636,6 +793,13 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
   const int64_t threads = Vc * 2 * L.N;
   KTimer kt(ctx, "restrict",
             (double)nrhs * (L.n() + threads) * sizeof(Cx<R>) + (double)L.n() * L.N * sizeof(Cx<R>));
+  if (std::is_same<R, float>::value && transfer16_ok(L)) {
+    REQUIRE(((uintptr_t)xf | (uintptr_t)yc) % 16 == 0, "matrix-core restriction needs 16-byte aligned vectors");
+    hipLaunchKernelGGL(restrict16_mfma_kernel, dim3((unsigned)ceil_div(Vc, 4)), dim3(256), 0, ctx->stream,
+                       (const c64*)P, (const c64*)xf, (c64*)yc, agg_map(L), Vc, nrhs);
+    LAUNCH_CHECK();
+    return;
+  }
   constexpr int RB = 4;
   dim3 grid((unsigned)ceil_div(threads, 256), (unsigned)ceil_div(nrhs, RB));
   hipLaunchKernelGGL((restrict_kernel<R, RB>), grid, dim3(256), 0, ctx->stream, P, xf, yc, L.Lx, L.Lt, L.dofs, L.ax,
@@ -650,6 +814,18 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
   const int64_t nc = (int64_t)(L.Lx / L.ax) * (L.Lt / L.at) * 2 * L.N;
   KTimer kt(ctx, "prolong",
             (double)nrhs * ((add ? 2 : 1) * nf + nc) * sizeof(Cx<R>) + (double)nf * L.N * sizeof(Cx<R>));
+  if (std::is_same<R, float>::value && transfer16_ok(L)) {
+    REQUIRE(((uintptr_t)ec | (uintptr_t)xf) % 16 == 0, "matrix-core prolongation needs 16-byte aligned vectors");
+    const AggMap g = agg_map(L);
+    const int tiles = g.E / 16;
+    const int mtw = tiles % 4 == 0 ? std::min(4, tiles) : (tiles % 2 == 0 ? 2 : 1);
+    const int64_t Vc = nc / 16;
+    const int64_t waves = Vc * (tiles / mtw);
+    hipLaunchKernelGGL(prolong16_mfma_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, ctx->stream,
+                       (const c64*)P, (const c64*)ec, (c64*)xf, g, Vc, mtw, nrhs, add ? 1 : 0);
+    LAUNCH_CHECK();
+    return;
+  }
   constexpr int RB = 4;
   dim3 grid((unsigned)ceil_div(nf, 256), (unsigned)ceil_div(nrhs, RB));
   hipLaunchKernelGGL((prolong_kernel<R, RB>), grid, dim3(256), 0, ctx->stream, P, ec, xf, L.Lx, L.Lt, L.dofs, L.ax,

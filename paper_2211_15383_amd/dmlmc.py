@@ -27,7 +27,7 @@ EXPORTED = [
     "dmlmc_free_hierarchy", "dmlmc_level_info", "dmlmc_export_level", "dmlmc_deflate",
     "dmlmc_free_deflation", "dmlmc_deflation_info", "dmlmc_export_deflation", "dmlmc_solve_multi_rhs", "dmlmc_mlmc_trace",
     "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_set_solver_params",
-    "dmlmc_get_solver_params", "dmlmc_timing_enable",
+    "dmlmc_get_solver_params", "dmlmc_timing_enable", "dmlmc_timing_select",
     "dmlmc_timing_reset", "dmlmc_timing_get",
 ]
 
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_get_solver_params": (i32, [vp, C.POINTER(SolverParams)]),
         "dmlmc_timing_enable": (i32, [vp, i32]),
         "dmlmc_timing_reset": (i32, [vp]),
+        "dmlmc_timing_select": (i32, [vp, C.c_char_p]),
         "dmlmc_timing_get": (i32, [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
@@ -170,6 +171,11 @@ class Context:
     # ---------------------------------------------------------------- timing
     def timing(self, enable: bool):
         self.check(lib().dmlmc_timing_enable(self.h, 1 if enable else 0))
+
+    def timing_select(self, classes=None):
+        """Restricts timing to the given class names (iterable of str); None = all."""
+        arg = None if not classes else ",".join(classes).encode()
+        self.check(lib().dmlmc_timing_select(self.h, arg))
 
     def timing_reset(self):
         self.check(lib().dmlmc_timing_reset(self.h))

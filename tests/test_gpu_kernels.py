@@ -122,3 +122,13 @@ def test_smoother_properties(gpu, name):
         H.apply(dm.OP_SMOOTH, l, to_dev(torch, b, torch.complex128), x0, dm.FP64, arg=3)
         r = b - D @ to_host(x0)
         assert np.linalg.norm(r) < 0.9 * np.linalg.norm(b), ("reduction", l)
+        # complex-FP32 smoothers (matrix-core block Gauss-Seidel at d = 16): the exact
+        # solution is fixed up to FP32 rounding, and the residual still drops
+        out32 = to_dev(torch, xs, torch.complex64)
+        H.apply(dm.OP_SMOOTH, l, to_dev(torch, b, torch.complex64), out32, dm.MIXED, arg=2)
+        assert rel_err(to_host(out32), xs) < 1e-4, ("fixed point fp32", l)
+        x32 = torch.zeros((4, n), dtype=torch.complex64, device="cuda:0")
+        H.apply(dm.OP_SMOOTH, l, to_dev(torch, b, torch.complex64), x32, dm.MIXED, arg=3)
+        r32 = b - D @ to_host(x32)
+        assert np.linalg.norm(r32) < 0.9 * np.linalg.norm(b), ("reduction fp32", l)
+        assert rel_err(to_host(x32), to_host(x0)) < 1e-4, ("fp32 vs fp64 sweeps", l)
