@@ -85,6 +85,38 @@ def copy_ceiling(torch, nbytes: int = 1 << 30, reps: int = 10) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def kernel_rates(torch, dm, ctx, H, nlev: int, b: int, reps: int = 10):
+    """Each stencil-class kernel alone at the workload's real shapes (b RHS, complex FP32),
+    reps launches after one warm-up: algorithmic bytes per launch / mean event time."""
+    out = {}
+    ctx.timing_select(None)
+    ctx.timing(True)
+    dev = "cuda:0"
+    for l in range(1, nlev):
+        n, nc = H.n(l), H.n(l + 1)
+        x = torch.randn(b, n, dtype=torch.complex64, device=dev)
+        y = torch.randn(b, n, dtype=torch.complex64, device=dev)
+        xc = torch.randn(b, nc, dtype=torch.complex64, device=dev)
+        yc = torch.empty_like(xc)
+        cases = [("wilson" if l == 1 else "coarse", dm.OP_D, x, y, 0),
+                 ("restrict", dm.OP_RESTRICT, x, yc, 0),
+                 ("prolong", dm.OP_PROLONG, xc, y, 0),
+                 ("sap" if l == 1 else "coarse_gs", dm.OP_SMOOTH, x, y, 1)]
+        for cls, op, a, o, arg in cases:
+            H.apply(op, l, a, o, dm.MIXED, arg)
+            ctx.timing_reset()
+            for _ in range(reps):
+                H.apply(op, l, a, o, dm.MIXED, arg)
+            nl, ms, by = ctx.timing_get(cls)
+            out[f"{cls}_level{l}"] = {"launches": nl, "avg_us": 1e3 * ms / max(1, nl),
+                                      "bytes_per_launch": by / max(1, nl),
+                                      "GBps": by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
+        del x, y, xc, yc
+    ctx.timing(False)
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_baseline(name: str, nsamp: int):
     """The CPU checker as it stands (direct sparse-LU solves), on the named workload's
     three-level hierarchy, drawing `nsamp` samples per level.  Setup is excluded."""
@@ -118,6 +150,8 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true", help="skip the FP64 single-RHS baseline run")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU checker baseline")
     ap.add_argument("--cpu-workload", default="schwinger128")
+    ap.add_argument("--skip-kernel-rates", action="store_true",
+                    help="skip the per-kernel runs at the real shapes after the timed steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the estimator's samples would shard across GPUs with one "
@@ -160,7 +194,7 @@ def main():
     ctx.timing(True)
     ctx.timing_reset()
     r = run(dmlmc.MIXED, W.rhs_block)
-    tb = timers(ctx, HBM_CLASSES + ("defl_gemm",))
+    tb = timers(ctx, HBM_CLASSES + ("gs_fused", "defl_gemm"))
     ctx.timing(False)
     log(f"breakdown pass: {r.seconds:.3f} s (all kernel classes bracketed by events)")
     dom = max(HBM_CLASSES, key=lambda c: tb[c]["ms"])
@@ -184,6 +218,12 @@ def main():
     ctx.timing_select(None)
     copy_gbps = copy_ceiling(torch)
     log(f"copy kernel ceiling {copy_gbps:.0f} GB/s")
+    kr = {} if args.skip_kernel_rates else kernel_rates(torch, dmlmc, ctx, H, min(L, 3), W.rhs_block)
+    for k, v in kr.items():
+        log(f"kernel {k}: {v['avg_us']:.1f} us, {v['GBps']:.0f} GB/s")
+    kr_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kr.values())
+    kr_s = sum(v["avg_us"] * 1e-6 * v["launches"] for v in kr.values())
+    stencil_real_gbps = kr_bytes / kr_s / 1e9 if kr_s > 0 else 0.0
 
     fp64 = None
     if not args.skip_fp64:
@@ -242,7 +282,10 @@ def main():
         "trace": results[-1].trace,
         "rel_err": results[-1].rel_err,
         "N": results[-1].N,
-        "stencil_hbm_GBps": stencil_gbps,
+        "stencil_hbm_GBps": stencil_real_gbps,
+        "stencil_hbm_frac": stencil_real_gbps / HBM_PEAK_GBPS,
+        "stencil_kernels": kr,
+        "stencil_hbm_GBps_in_estimate": stencil_gbps,
         "kernel_classes": tb,
         "defl_gemm_TFLOPs": gemm_tflops,
         "copy_kernel_GBps": copy_gbps,

@@ -262,7 +262,7 @@ dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p
  * When enabled, the library brackets every launch of the named kernel classes with HIP
  * events on the context stream and accumulates their durations.  Classes:
  * "wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong", "gs_dots", "gs_update",
- * "defl_gemm".  dmlmc_timing_get returns (launches, total milliseconds, bytes per
+ * "gs_fused" (the single-workgroup Arnoldi step of small levels), "defl_gemm".  dmlmc_timing_get returns (launches, total milliseconds, bytes per
  * launch summed; flops for "defl_gemm") for a class.
  * dmlmc_timing_select restricts the bracketing to a comma-separated list of classes
  * (NULL or "" = every class), so that a timed run carries events only around the kernels

@@ -339,11 +339,35 @@ __global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, in
   reduce_or_partial(acc, 1, lds, red, part, f, r);
 }
 
+// Sums v[0..15] over the 64 lanes of a wavefront by recursive halving: at each exchange a
+// lane keeps half of its values and adds the partner's copy of that half (17 shuffles
+// instead of 96).  Lane l ends with the total of value (l >> 2) & 15 in v[0].
+__device__ __forceinline__ void wave_sum16(double (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int step = 0; step < 4; ++step) {
+    const int half = 8 >> step;
+    const int mask = 32 >> step;
+    const bool hi = (lane & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i < half) {
+        const double a = v[i], b = v[half + i];
+        const double send = hi ? a : b;
+        const double recv = __shfl_xor(send, mask, 64);
+        v[i] = (hi ? b : a) + recv;
+      }
+    }
+  }
+  v[0] += __shfl_xor(v[0], 2, 64);
+  v[0] += __shfl_xor(v[0], 1, 64);
+}
+
 // Whole single-pass step for RHS blockIdx.x in one workgroup of 1024 threads; element
 // pair p of the vectors belongs to thread p % 1024 (PPT pairs per thread, n <= 2048 PPT).
 constexpr int FUSED_THREADS = 1024;
 constexpr int FUSED_PPT = 8;
-constexpr int FUSED_CHUNK = 8;  // basis vectors per reduction round
+constexpr int FUSED_CHUNK = 8;  // basis vectors per reduction round (16 doubles: wave_sum16)
 
 template <typename RW>
 __global__ __launch_bounds__(FUSED_THREADS) void gs1_fused_kernel(c64* __restrict__ U, int nb,
@@ -361,31 +385,21 @@ __global__ __launch_bounds__(FUSED_THREADS) void gs1_fused_kernel(c64* __restric
   const int64_t np = n / 2, vs = vstride / 2;
   const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * n);
   const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * n);
-  Pair<RW> wl[FUSED_PPT];
-#pragma unroll
-  for (int q = 0; q < FUSED_PPT; ++q) {
-    const int64_t p = tid + (int64_t)q * FUSED_THREADS;
-    if (p < np) {
-      wl[q] = wr[p];
-    } else {
-      wl[q].a = cmk((RW)0, (RW)0);
-      wl[q].b = wl[q].a;
-    }
-  }
-  // h_i = s_i <u_i, ws w>, FUSED_CHUNK basis vectors per reduction round
+  // h_i = s_i <u_i, ws w>, FUSED_CHUNK basis vectors per reduction round (w is re-read
+  // from L2 per round rather than held in registers)
   for (int c0 = 0; c0 < nb; c0 += FUSED_CHUNK) {
     double acc[2 * FUSED_CHUNK];
 #pragma unroll
     for (int q = 0; q < 2 * FUSED_CHUNK; ++q) acc[q] = 0.0;
+#pragma unroll 2
+    for (int q = 0; q < FUSED_PPT; ++q) {
+      const int64_t p = tid + (int64_t)q * FUSED_THREADS;
+      if (p < np) {
+        const Pair<RW> b = wr[p];
 #pragma unroll
-    for (int i = 0; i < FUSED_CHUNK; ++i) {
-      if (c0 + i < nb) {
-#pragma unroll
-        for (int q = 0; q < FUSED_PPT; ++q) {
-          const int64_t p = tid + (int64_t)q * FUSED_THREADS;
-          if (p < np) {
+        for (int i = 0; i < FUSED_CHUNK; ++i) {
+          if (c0 + i < nb) {
             const Pair<float> u = Ur[(c0 + i) * vs + p];
-            const Pair<RW> b = wl[q];
             acc[2 * i] += (double)u.a.x * b.a.x + (double)u.a.y * b.a.y + (double)u.b.x * b.b.x +
                           (double)u.b.y * b.b.y;
             acc[2 * i + 1] += (double)u.a.x * b.a.y - (double)u.a.y * b.a.x + (double)u.b.x * b.b.y -
@@ -394,11 +408,8 @@ __global__ __launch_bounds__(FUSED_THREADS) void gs1_fused_kernel(c64* __restric
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < 2 * FUSED_CHUNK; ++q) {
-      const double v = wave_sum(acc[q]);
-      if (lane == 0) lds[wv][q] = v;
-    }
+    wave_sum16(acc);
+    if ((lane & 3) == 0) lds[wv][(lane >> 2) & 15] = acc[0];
     __syncthreads();
     if (tid < 2 * FUSED_CHUNK && c0 + tid / 2 < nb) {
       double sum = 0.0;
@@ -421,7 +432,8 @@ __global__ __launch_bounds__(FUSED_THREADS) void gs1_fused_kernel(c64* __restric
   for (int q = 0; q < FUSED_PPT; ++q) {
     const int64_t p = tid + (int64_t)q * FUSED_THREADS;
     if (p < np) {
-      double v0x = ws * wl[q].a.x, v0y = ws * wl[q].a.y, v1x = ws * wl[q].b.x, v1y = ws * wl[q].b.y;
+      const Pair<RW> b = wr[p];
+      double v0x = ws * b.a.x, v0y = ws * b.a.y, v1x = ws * b.b.x, v1y = ws * b.b.y;
       for (int i = 0; i < nb; ++i) {
         const Pair<float> u = Ur[i * vs + p];
         const c128 hi = cf[i];
@@ -548,7 +560,7 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
     f.mode = FIN_CGS1;
     f.h = k.h1;
     f.scale = scale;
-    KTimer kt(ctx, "gs_dots", (double)nrhs * n * ((2 * nb + 1) * sizeof(c64) + sizeof(Cx<RW>)));
+    KTimer kt(ctx, "gs_fused", (double)nrhs * n * ((2 * nb + 1) * sizeof(c64) + sizeof(Cx<RW>)));
     hipLaunchKernelGGL((gs1_fused_kernel<RW>), dim3(nrhs), dim3(FUSED_THREADS), 0, ctx->stream, U, nb, w, n, vstride,
                        wscale, f);
     LAUNCH_CHECK();

@@ -54,28 +54,63 @@ __device__ __forceinline__ void hops(Cx<R> ux, Cx<R> uxm, Cx<R> ut, Cx<R> utm, S
   a1 = a1 + mul_i(g);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  This
+// renumbering hands every XCD a contiguous range of logical workgroups, so neighbouring
+// sites (the stencils' re-reads) are fetched through the same L2.  It is a bijection on
+// [0, gridDim.x): the largest multiple of 8 is permuted, the tail keeps its numbers.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t g = blockIdx.x, n = gridDim.x;
+  const int64_t full = n & ~(int64_t)7;
+  if (g >= full) return g;
+  return (g & 7) * (full >> 3) + (g >> 3);
+}
+
+// Thread per site, RHS [r0, r1) in sequence; the five spinors of RHS r + 1 are requested
+// before RHS r is computed, so a thread always has a full set of loads in flight.
 template <typename R, bool G5>
 __global__ __launch_bounds__(256) void wilson_kernel(const Cx<R>* __restrict__ U, const Cx<R>* __restrict__ in,
                                                      Cx<R>* __restrict__ out, int Lx, int Lt, R diag, int nrhs,
                                                      int rb, int64_t ldx, int64_t ldy) {
   const int64_t V = (int64_t)Lx * Lt;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= V) return;
   const Nbr nb = neighbours(s, Lx, Lt);
   const Cx<R> ux = U[s], ut = U[V + s], uxm = U[nb.xm], utm = U[V + nb.tm];
   const int r0 = blockIdx.y * rb;
   const int r1 = min(r0 + rb, nrhs);
   const R half = (R)0.5;
+  Spinor<R> c, fx, bx, ft, bt;
+  {
+    const Spinor<R>* p = reinterpret_cast<const Spinor<R>*>(in + r0 * ldx);
+    c = p[s];
+    fx = p[nb.xp];
+    bx = p[nb.xm];
+    ft = p[nb.tp];
+    bt = p[nb.tm];
+  }
   for (int r = r0; r < r1; ++r) {
-    const Spinor<R>* p = reinterpret_cast<const Spinor<R>*>(in + r * ldx);
-    Spinor<R> c = p[s];
+    const Spinor<R> c0 = c, fx0 = fx, bx0 = bx, ft0 = ft, bt0 = bt;
+    if (r + 1 < r1) {
+      const Spinor<R>* p = reinterpret_cast<const Spinor<R>*>(in + (r + 1) * ldx);
+      c = p[s];
+      fx = p[nb.xp];
+      bx = p[nb.xm];
+      ft = p[nb.tp];
+      bt = p[nb.tm];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // the next RHS's loads go out before this one's arithmetic
     Cx<R> a0, a1;
-    hops(ux, uxm, ut, utm, p[nb.xp], p[nb.xm], p[nb.tp], p[nb.tm], a0, a1);
+    hops(ux, uxm, ut, utm, fx0, bx0, ft0, bt0, a0, a1);
     Spinor<R> o;
-    o.s0 = diag * c.s0 - half * a0;
-    o.s1 = diag * c.s1 - half * a1;
+    o.s0 = diag * c0.s0 - half * a0;
+    o.s1 = diag * c0.s1 - half * a1;
     if (G5) o.s1 = cmk(-o.s1.x, -o.s1.y);
-    reinterpret_cast<Spinor<R>*>(out + r * ldy)[s] = o;
+    // the result is not re-read by this launch: non-temporal store
+    R* of = reinterpret_cast<R*>(out + r * ldy + 2 * s);
+    __builtin_nontemporal_store(o.s0.x, of);
+    __builtin_nontemporal_store(o.s0.y, of + 1);
+    __builtin_nontemporal_store(o.s1.x, of + 2);
+    __builtin_nontemporal_store(o.s1.y, of + 3);
   }
 }
 
@@ -126,14 +161,14 @@ __global__ __launch_bounds__(256) void sap_kernel(const Cx<R>* __restrict__ U, C
                                                   int rb, int color, int mr) {
   constexpr int BL = BSX * BST;  // lanes per block
   const int64_t V = (int64_t)Lx * Lt;
-  const int nbx = Lx / BSX, nbt = Lt / BST;
+  const int nbx = Lx / BSX, nbt = Lt / BST;  // nbx even: blocks of one colour are every other block of a row
   const int lane = threadIdx.x % BL;
-  const int blk = blockIdx.x * (blockDim.x / BL) + threadIdx.x / BL;
-  const int BXi = blk % nbx, BTi = blk / nbx;
-  const bool active = (blk < nbx * nbt) && (((BXi + BTi) & 1) == color);
+  const int64_t k = xcd_block() * (blockDim.x / BL) + threadIdx.x / BL;  // k-th block of colour `color`
+  const int64_t BTi = k / (nbx / 2);
+  const int64_t BXi = 2 * (k % (nbx / 2)) + ((BTi + color) & 1);
+  const bool active = BTi < nbt;  // uniform over the block's lanes
   const int lx = lane % BSX, lt = lane / BSX;
-  const int xs = BXi * BSX + lx, ts = BTi * BST + lt;
-  const int64_t s = active ? (int64_t)xs + (int64_t)Lx * ts : 0;
+  const int64_t s = active ? (BXi * BSX + lx) + (int64_t)Lx * (BTi * BST + lt) : 0;
   const Nbr nb = neighbours(s, Lx, Lt);
   Cx<R> ux = cmk((R)0, (R)0), ut = ux, uxm = ux, utm = ux;
   if (active) {
@@ -144,32 +179,48 @@ __global__ __launch_bounds__(256) void sap_kernel(const Cx<R>* __restrict__ U, C
   }
   // in-block neighbour lanes (masks for the block-restricted operator)
   const bool hxp = lx + 1 < BSX, hxm = lx > 0, htp = lt + 1 < BST, htm = lt > 0;
-  const int gbase = (threadIdx.x / BL) * BL;  // first lane of my block within the workgroup
-  const int wl = (threadIdx.x & 63);           // lane within wavefront
-  const int wbase = wl - lane;                 // first lane of my block within the wavefront
-  (void)gbase;
+  const int wl = (threadIdx.x & 63);  // lane within wavefront
+  const int wbase = wl - lane;        // first lane of my block within the wavefront
   const R half = (R)0.5;
   const int r0 = blockIdx.y * rb;
   const int r1 = min(r0 + rb, nrhs);
+  const int64_t ld = 2 * V;
+  // x at the site and its four neighbours and b of RHS r + 1 are requested before RHS r
+  // is worked on (inactive lanes read site 0 and discard it)
+  Spinor<R> xc, fx, bx, ft, bt, bb;
+  {
+    const Spinor<R>* xp = reinterpret_cast<const Spinor<R>*>(x + r0 * ld);
+    xc = xp[s];
+    fx = xp[nb.xp];
+    bx = xp[nb.xm];
+    ft = xp[nb.tp];
+    bt = xp[nb.tm];
+    bb = reinterpret_cast<const Spinor<R>*>(b + r0 * ld)[s];
+  }
   for (int r = r0; r < r1; ++r) {
-    Spinor<R>* xp = reinterpret_cast<Spinor<R>*>(x + r * (int64_t)(2 * V));
-    const Spinor<R>* bp = reinterpret_cast<const Spinor<R>*>(b + r * (int64_t)(2 * V));
-    Spinor<R> rho;
-    rho.s0 = rho.s1 = cmk((R)0, (R)0);
-    Spinor<R> xc = rho;
-    if (active) {
+    const Spinor<R> xc0 = xc, fx0 = fx, bx0 = bx, ft0 = ft, bt0 = bt, bb0 = bb;
+    if (r + 1 < r1) {
+      const Spinor<R>* xp = reinterpret_cast<const Spinor<R>*>(x + (r + 1) * ld);
       xc = xp[s];
+      fx = xp[nb.xp];
+      bx = xp[nb.xm];
+      ft = xp[nb.tp];
+      bt = xp[nb.tm];
+      bb = reinterpret_cast<const Spinor<R>*>(b + (r + 1) * ld)[s];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    Spinor<R> rho;
+    {
       Cx<R> a0, a1;
-      hops(ux, uxm, ut, utm, xp[nb.xp], xp[nb.xm], xp[nb.tp], xp[nb.tm], a0, a1);
-      Spinor<R> bb = bp[s];
-      rho.s0 = bb.s0 - (diag * xc.s0 - half * a0);
-      rho.s1 = bb.s1 - (diag * xc.s1 - half * a1);
+      hops(ux, uxm, ut, utm, fx0, bx0, ft0, bt0, a0, a1);
+      rho.s0 = bb0.s0 - (diag * xc0.s0 - half * a0);
+      rho.s1 = bb0.s1 - (diag * xc0.s1 - half * a1);
     }
     Spinor<R> e;
     e.s0 = e.s1 = cmk((R)0, (R)0);
     for (int it = 0; it < mr; ++it) {
       // q = D_BB rho, neighbours from lanes of the same block
-      Spinor<R> fx, bx, ft, bt;
+      Spinor<R> gfx, gbx, gft, gbt;
       const R v[4] = {rho.s0.x, rho.s0.y, rho.s1.x, rho.s1.y};
       R fxv[4], bxv[4], ftv[4], btv[4];
 #pragma unroll
@@ -180,16 +231,16 @@ __global__ __launch_bounds__(256) void sap_kernel(const Cx<R>* __restrict__ U, C
         btv[c] = __shfl(v[c], wbase + (htm ? lane - BSX : lane), 64);
       }
       const R zx = (R)0;
-      fx.s0 = hxp ? cmk(fxv[0], fxv[1]) : cmk(zx, zx);
-      fx.s1 = hxp ? cmk(fxv[2], fxv[3]) : cmk(zx, zx);
-      bx.s0 = hxm ? cmk(bxv[0], bxv[1]) : cmk(zx, zx);
-      bx.s1 = hxm ? cmk(bxv[2], bxv[3]) : cmk(zx, zx);
-      ft.s0 = htp ? cmk(ftv[0], ftv[1]) : cmk(zx, zx);
-      ft.s1 = htp ? cmk(ftv[2], ftv[3]) : cmk(zx, zx);
-      bt.s0 = htm ? cmk(btv[0], btv[1]) : cmk(zx, zx);
-      bt.s1 = htm ? cmk(btv[2], btv[3]) : cmk(zx, zx);
+      gfx.s0 = hxp ? cmk(fxv[0], fxv[1]) : cmk(zx, zx);
+      gfx.s1 = hxp ? cmk(fxv[2], fxv[3]) : cmk(zx, zx);
+      gbx.s0 = hxm ? cmk(bxv[0], bxv[1]) : cmk(zx, zx);
+      gbx.s1 = hxm ? cmk(bxv[2], bxv[3]) : cmk(zx, zx);
+      gft.s0 = htp ? cmk(ftv[0], ftv[1]) : cmk(zx, zx);
+      gft.s1 = htp ? cmk(ftv[2], ftv[3]) : cmk(zx, zx);
+      gbt.s0 = htm ? cmk(btv[0], btv[1]) : cmk(zx, zx);
+      gbt.s1 = htm ? cmk(btv[2], btv[3]) : cmk(zx, zx);
       Cx<R> a0, a1;
-      hops(ux, uxm, ut, utm, fx, bx, ft, bt, a0, a1);
+      hops(ux, uxm, ut, utm, gfx, gbx, gft, gbt, a0, a1);
       Spinor<R> q;
       q.s0 = diag * rho.s0 - half * a0;
       q.s1 = diag * rho.s1 - half * a1;
@@ -211,9 +262,10 @@ __global__ __launch_bounds__(256) void sap_kernel(const Cx<R>* __restrict__ U, C
       rho.s1 = rho.s1 - alpha * q.s1;
     }
     if (active) {
-      xc.s0 = xc.s0 + e.s0;
-      xc.s1 = xc.s1 + e.s1;
-      xp[s] = xc;
+      Spinor<R> xo;
+      xo.s0 = xc0.s0 + e.s0;
+      xo.s1 = xc0.s1 + e.s1;
+      reinterpret_cast<Spinor<R>*>(x + r * ld)[s] = xo;
     }
   }
 }
@@ -391,6 +443,16 @@ struct Quad {
   c64 v[4];
 };
 
+// Coarse blocks and interpolation blocks are streamed once per launch: non-temporal loads
+// keep them from displacing the vectors' neighbour re-reads in the caches.
+__device__ __forceinline__ Quad load_quad_nt(const c64* __restrict__ p) {
+  const float* f = reinterpret_cast<const float*>(p);
+  Quad r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) r.v[v] = cmk(__builtin_nontemporal_load(f + 2 * v), __builtin_nontemporal_load(f + 2 * v + 1));
+  return r;
+}
+
 __device__ __forceinline__ Quad load_quad(const c64* __restrict__ p) {
   const C64Pair* q = reinterpret_cast<const C64Pair*>(p);
   const C64Pair u = q[0], w = q[1];
@@ -399,13 +461,6 @@ __device__ __forceinline__ Quad load_quad(const c64* __restrict__ p) {
   r.v[1] = u.b;
   r.v[2] = w.a;
   r.v[3] = w.b;
-  return r;
-}
-
-__device__ __forceinline__ Quad zero_quad() {
-  Quad r;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) r.v[v] = cmk(0.f, 0.f);
   return r;
 }
 
@@ -420,25 +475,34 @@ __device__ __forceinline__ void store_quad(c64* __restrict__ p, f32x4 re, f32x4 
   q[1] = w;
 }
 
+// Non-temporal form for results that the same launch does not read again.
+__device__ __forceinline__ void store_quad_nt(c64* __restrict__ p, f32x4 re, f32x4 im) {
+  float* f = reinterpret_cast<float*>(p);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    __builtin_nontemporal_store(re[v], f + 2 * v);
+    __builtin_nontemporal_store(im[v], f + 2 * v + 1);
+  }
+}
+
 // D += A X for one 16 x 16 block (a: lane's A row quarter, x: lane's B quarter).
 __device__ __forceinline__ void block_mfma(f32x4& dre, f32x4& dim, const Quad& a, const Quad& x) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) cmfma(dre, dim, a.v[t], x.v[t]);
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  This
-// renumbering hands every XCD a contiguous range of logical workgroups, so neighbouring
-// sites (the stencil's re-reads) are fetched through the same L2.  It is a bijection on
-// [0, gridDim.x): the largest multiple of 8 is permuted, the tail keeps its numbers.
-__device__ __forceinline__ int64_t xcd_block() {
-  const int64_t g = blockIdx.x, n = gridDim.x;
-  const int64_t full = n & ~(int64_t)7;
-  if (g >= full) return g;
-  return (g & 7) * (full >> 3) + (g >> 3);
+
+__device__ __forceinline__ Quad select_quad(bool keep, const Quad& q) {
+  Quad r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) r.v[v] = keep ? q.v[v] : cmk(0.f, 0.f);
+  return r;
 }
 
 // y_s = sum_dir A[s][dir] x_{s+dir} (optionally Gamma5 y), one site per wavefront, all
-// RHS in tiles of 16 processed two at a time (block operands loaded once per pair).
+// RHS in pairs of 16-wide tiles.  Every load of a tile pair is issued before the first
+// product (rows beyond nrhs load a valid row and are zeroed), so the wavefront has all
+// its memory requests in flight at once.
 template <bool G5>
 __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ in,
                                                             c64* __restrict__ out, int Lx, int Lt, int nrhs,
@@ -453,21 +517,24 @@ __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restric
   const float sg = (G5 && kq >= 2) ? -1.f : 1.f;
   for (int r0 = 0; r0 < nrhs; r0 += 32) {
     const int ra = r0 + row, rb = r0 + 16 + row;
-    const bool va = ra < nrhs, vb = rb < nrhs, two = r0 + 16 < nrhs;
+    const bool va = ra < nrhs, vb = rb < nrhs;
+    const int64_t oa = (int64_t)min(ra, nrhs - 1) * ldx + 4 * kq, ob = (int64_t)min(rb, nrhs - 1) * ldx + 4 * kq;
+    Quad a[5], xa[5], xb[5];
+#pragma unroll
+    for (int dir = 0; dir < 5; ++dir) {
+      a[dir] = load_quad(A + (s * 5 + dir) * 256 + row * 16 + 4 * kq);
+      xa[dir] = load_quad(in + oa + sites[dir] * 16);
+      xb[dir] = load_quad(in + ob + sites[dir] * 16);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
     f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
 #pragma unroll
     for (int dir = 0; dir < 5; ++dir) {
-      const Quad a = load_quad(A + (s * 5 + dir) * 256 + row * 16 + 4 * kq);
-      const int64_t off = sites[dir] * 16 + 4 * kq;
-      const Quad xa = va ? load_quad(in + (int64_t)ra * ldx + off) : zero_quad();
-      block_mfma(are, aim, a, xa);
-      if (two) {
-        const Quad xb = vb ? load_quad(in + (int64_t)rb * ldx + off) : zero_quad();
-        block_mfma(bre, bim, a, xb);
-      }
+      block_mfma(are, aim, a[dir], select_quad(va, xa[dir]));
+      block_mfma(bre, bim, a[dir], select_quad(vb, xb[dir]));
     }
     if (va) store_quad(out + (int64_t)ra * ldy + s * 16 + 4 * kq, are, aim, sg);
-    if (two && vb) store_quad(out + (int64_t)rb * ldy + s * 16 + 4 * kq, bre, bim, sg);
+    if (vb) store_quad(out + (int64_t)rb * ldy + s * 16 + 4 * kq, bre, bim, sg);
   }
 }
 
@@ -489,37 +556,38 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const c64* __rest
   const int row = lane & 15, kq = lane >> 4;
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[4] = {nb.xp, nb.xm, nb.tp, nb.tm};
+  const int64_t own = s * 16 + 4 * kq;
   for (int r0 = 0; r0 < nrhs; r0 += 32) {
     const int ra = r0 + row, rb = r0 + 16 + row;
-    const bool va = ra < nrhs, vb = rb < nrhs, two = r0 + 16 < nrhs;
+    const bool va = ra < nrhs, vb = rb < nrhs;
+    const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq, ob = (int64_t)min(rb, nrhs - 1) * ld + 4 * kq;
+    Quad a[4], xa[4], xb[4];
+#pragma unroll
+    for (int dir = 0; dir < 4; ++dir) {
+      a[dir] = load_quad(A + (s * 5 + dir + 1) * 256 + row * 16 + 4 * kq);
+      xa[dir] = load_quad(x + oa + sites[dir] * 16);
+      xb[dir] = load_quad(x + ob + sites[dir] * 16);
+    }
+    const Quad ai = load_quad(Ainv + s * 256 + row * 16 + 4 * kq);
+    Quad qa = load_quad(b + oa - 4 * kq + own);
+    Quad qb = load_quad(b + ob - 4 * kq + own);
+    __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
     f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
 #pragma unroll
     for (int dir = 0; dir < 4; ++dir) {
-      const Quad a = load_quad(A + (s * 5 + dir + 1) * 256 + row * 16 + 4 * kq);
-      const int64_t off = sites[dir] * 16 + 4 * kq;
-      const Quad xa = va ? load_quad(x + (int64_t)ra * ld + off) : zero_quad();
-      block_mfma(are, aim, a, xa);
-      if (two) {
-        const Quad xb = vb ? load_quad(x + (int64_t)rb * ld + off) : zero_quad();
-        block_mfma(bre, bim, a, xb);
-      }
+      block_mfma(are, aim, a[dir], select_quad(va, xa[dir]));
+      block_mfma(bre, bim, a[dir], select_quad(vb, xb[dir]));
     }
-    const int64_t own = s * 16 + 4 * kq;
-    const Quad ai = load_quad(Ainv + s * 256 + row * 16 + 4 * kq);
-    Quad q = va ? load_quad(b + (int64_t)ra * ld + own) : zero_quad();
 #pragma unroll
-    for (int v = 0; v < 4; ++v) q.v[v] = cmk(q.v[v].x - are[v], q.v[v].y - aim[v]);
-    f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere;
-    block_mfma(ere, eim, ai, q);
+    for (int v = 0; v < 4; ++v) {
+      qa.v[v] = cmk(qa.v[v].x - are[v], qa.v[v].y - aim[v]);
+      qb.v[v] = cmk(qb.v[v].x - bre[v], qb.v[v].y - bim[v]);
+    }
+    f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere, fre = ere, fim = ere;
+    block_mfma(ere, eim, ai, select_quad(va, qa));
+    block_mfma(fre, fim, ai, select_quad(vb, qb));
     if (va) store_quad(x + (int64_t)ra * ld + own, ere, eim, 1.f);
-    if (two) {
-      Quad qb = vb ? load_quad(b + (int64_t)rb * ld + own) : zero_quad();
-#pragma unroll
-      for (int v = 0; v < 4; ++v) qb.v[v] = cmk(qb.v[v].x - bre[v], qb.v[v].y - bim[v]);
-      f32x4 fre = {0.f, 0.f, 0.f, 0.f}, fim = fre;
-      block_mfma(fre, fim, ai, qb);
-      if (vb) store_quad(x + (int64_t)rb * ld + own, fre, fim, 1.f);
-    }
+    if (vb) store_quad(x + (int64_t)rb * ld + own, fre, fim, 1.f);
   }
 }
 
@@ -546,7 +614,9 @@ struct AggMap {
   }
 };
 
-// One wavefront per (aggregate, group of mtw 16-entry tiles), all RHS, two RHS tiles at a time.
+// One wavefront per (aggregate, group of mtw <= 4 16-entry tiles), all RHS, two RHS tiles
+// at a time; the group's interpolation quads (and, when adding, the old fine values) are
+// all requested before the first product.
 __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restrict__ P, const c64* __restrict__ ec,
                                                              c64* __restrict__ xf, AggMap g, int64_t Vc, int mtw,
                                                              int nrhs, int add) {
@@ -561,56 +631,72 @@ __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restri
   const int64_t ldc = Vc * 16;
   // coarse dof 4 kq + t has chirality kq / 2 and test vector 4 (kq % 2) + t
   const int cj = kq >> 1, k0 = 4 * (kq & 1);
-  for (int r0 = 0; r0 < nrhs; r0 += 32) {
-    const int ra = r0 + row, rb = r0 + 16 + row;
-    const bool va = ra < nrhs, vb = rb < nrhs, two = r0 + 16 < nrhs;
-    const Quad ea = va ? load_quad(ec + (int64_t)ra * ldc + cs * 16 + 4 * kq) : zero_quad();
-    const Quad eb = (two && vb) ? load_quad(ec + (int64_t)rb * ldc + cs * 16 + 4 * kq) : zero_quad();
-    for (int mt = grp * mtw; mt < (grp + 1) * mtw; ++mt) {
+  Quad a[4];
+  int64_t fo[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    fo[u] = 0;
+    if (u < mtw) {  // wave-uniform
+      const int mt = grp * mtw + u;
       int ce;
       const int64_t pr = g.prow(cs, 16 * mt + row, ce);
-      const Quad a = (ce == cj) ? load_quad(P + pr + k0) : zero_quad();
-      const int64_t fo = g.fine_offset(cs, 16 * mt + 4 * kq);
-      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
-      block_mfma(are, aim, a, ea);
-      if (va) {
-        c64* o = xf + (int64_t)ra * nf + fo;
+      a[u] = select_quad(ce == cj, load_quad_nt(P + pr + k0));
+      fo[u] = g.fine_offset(cs, 16 * mt + 4 * kq);
+    }
+  }
+  for (int r0 = 0; r0 < nrhs; r0 += 32) {
+    const int ra = r0 + row, rb = r0 + 16 + row;
+    const bool va = ra < nrhs, vb = rb < nrhs;
+    const int64_t oa = (int64_t)min(ra, nrhs - 1) * nf, ob = (int64_t)min(rb, nrhs - 1) * nf;
+    // rows beyond nrhs load a valid row and are zeroed (no divergent loads)
+    const Quad ea = select_quad(va, load_quad(ec + (int64_t)min(ra, nrhs - 1) * ldc + cs * 16 + 4 * kq));
+    const Quad eb = select_quad(vb, load_quad(ec + (int64_t)min(rb, nrhs - 1) * ldc + cs * 16 + 4 * kq));
+    Quad xa[4], xb[4];
+    if (add) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u < mtw) {
+          xa[u] = load_quad(xf + oa + fo[u]);
+          xb[u] = load_quad(xf + ob + fo[u]);
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u < mtw) {  // wave-uniform
+        f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
+        block_mfma(are, aim, a[u], ea);
+        block_mfma(bre, bim, a[u], eb);
         if (add) {
-          const Quad x = load_quad(o);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            are[v] += x.v[v].x;
-            aim[v] += x.v[v].y;
+            are[v] += xa[u].v[v].x;
+            aim[v] += xa[u].v[v].y;
+            bre[v] += xb[u].v[v].x;
+            bim[v] += xb[u].v[v].y;
           }
         }
-        store_quad(o, are, aim, 1.f);
-      }
-      if (two) {
-        f32x4 bre = {0.f, 0.f, 0.f, 0.f}, bim = bre;
-        block_mfma(bre, bim, a, eb);
-        if (vb) {
-          c64* o = xf + (int64_t)rb * nf + fo;
-          if (add) {
-            const Quad x = load_quad(o);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              bre[v] += x.v[v].x;
-              bim[v] += x.v[v].y;
-            }
-          }
-          store_quad(o, bre, bim, 1.f);
-        }
+        if (va) store_quad(xf + oa + fo[u], are, aim, 1.f);
+        if (vb) store_quad(xf + ob + fo[u], bre, bim, 1.f);
       }
     }
   }
 }
 
-// One wavefront per aggregate, all its 16-entry tiles accumulated, two RHS tiles at a time.
+// WPA wavefronts per aggregate (WPA = min(4, E / 16)), 4 / WPA aggregates per workgroup:
+// the aggregate's 16-entry tiles are dealt round-robin to its wavefronts, each of which
+// requests the loads of up to four tiles before multiplying; the partial 16 x 32 results
+// of the wavefronts meet in LDS.  Every wavefront reaches the barriers.
 __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restrict__ P, const c64* __restrict__ xf,
-                                                              c64* __restrict__ yc, AggMap g, int64_t Vc, int nrhs) {
+                                                              c64* __restrict__ yc, AggMap g, int64_t Vc, int nrhs,
+                                                              int wpa) {
+  __shared__ f32x4 part[4][4][64];  // [wave][are, aim, bre, bim][lane]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t cs = xcd_block() * 4 + w;
-  if (cs >= Vc) return;  // wave-uniform
+  const int64_t cs_raw = xcd_block() * (4 / wpa) + w / wpa;
+  const bool valid = cs_raw < Vc;
+  const int64_t cs = valid ? cs_raw : Vc - 1;
+  const int sub = w % wpa;
   const int row = lane & 15, kq = lane >> 4;
   const int64_t nf = (int64_t)g.Lxf * (Vc / g.Lxc) * g.at * g.df;
   const int64_t ldc = Vc * 16;
@@ -619,27 +705,52 @@ __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restr
   const int ntile = g.E / 16;
   for (int r0 = 0; r0 < nrhs; r0 += 32) {
     const int ra = r0 + row, rb = r0 + 16 + row;
-    const bool va = ra < nrhs, vb = rb < nrhs, two = r0 + 16 < nrhs;
+    const bool va = ra < nrhs, vb = rb < nrhs;
     f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
-    for (int kt = 0; kt < ntile; ++kt) {
-      Quad a;
+    const int64_t oa = (int64_t)min(ra, nrhs - 1) * nf, ob = (int64_t)min(rb, nrhs - 1) * nf;
+    for (int kt0 = sub; kt0 < ntile; kt0 += 4 * wpa) {
+      Quad a[4], xa[4], xb[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        int ce;
-        const int64_t pr = g.prow(cs, 16 * kt + 4 * kq + t, ce);
-        const c64 pv = (ce == cj) ? P[pr + kj] : cmk(0.f, 0.f);
-        a.v[t] = cmk(pv.x, -pv.y);
+      for (int u = 0; u < 4; ++u) {
+        const int kt = kt0 + u * wpa;
+        if (kt >= ntile) continue;  // wave-uniform
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          int ce;
+          const int64_t pr = g.prow(cs, 16 * kt + 4 * kq + t, ce);
+          const float* pf = reinterpret_cast<const float*>(P + pr + kj);
+          const c64 pv = cmk(__builtin_nontemporal_load(pf), __builtin_nontemporal_load(pf + 1));
+          a[u].v[t] = ce == cj ? cmk(pv.x, -pv.y) : cmk(0.f, 0.f);
+        }
+        const int64_t fo = g.fine_offset(cs, 16 * kt + 4 * kq);
+        xa[u] = load_quad(xf + oa + fo);
+        xb[u] = load_quad(xf + ob + fo);
       }
-      const int64_t fo = g.fine_offset(cs, 16 * kt + 4 * kq);
-      const Quad xa = va ? load_quad(xf + (int64_t)ra * nf + fo) : zero_quad();
-      block_mfma(are, aim, a, xa);
-      if (two) {
-        const Quad xb = vb ? load_quad(xf + (int64_t)rb * nf + fo) : zero_quad();
-        block_mfma(bre, bim, a, xb);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (kt0 + u * wpa < ntile) {  // wave-uniform
+          block_mfma(are, aim, a[u], select_quad(va, xa[u]));
+          block_mfma(bre, bim, a[u], select_quad(vb, xb[u]));
+        }
       }
     }
-    if (va) store_quad(yc + (int64_t)ra * ldc + cs * 16 + 4 * kq, are, aim, 1.f);
-    if (two && vb) store_quad(yc + (int64_t)rb * ldc + cs * 16 + 4 * kq, bre, bim, 1.f);
+    part[w][0][lane] = are;
+    part[w][1][lane] = aim;
+    part[w][2][lane] = bre;
+    part[w][3][lane] = bim;
+    __syncthreads();
+    if (sub == 0 && valid) {
+      for (int q = 1; q < wpa; ++q) {
+        are += part[w + q][0][lane];
+        aim += part[w + q][1][lane];
+        bre += part[w + q][2][lane];
+        bim += part[w + q][3][lane];
+      }
+      if (va) store_quad_nt(yc + (int64_t)ra * ldc + cs * 16 + 4 * kq, are, aim);
+      if (vb) store_quad_nt(yc + (int64_t)rb * ldc + cs * 16 + 4 * kq, bre, bim);
+    }
+    __syncthreads();
   }
 }
 
@@ -676,7 +787,8 @@ template <typename R>
 void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx, int64_t ldy,
                    bool gamma5_left) {
   const int64_t V = L.sites();
-  const int rb = rhs_block_for(V, nrhs);
+  // at most 8 RHS per thread: more workgroups in flight; links are re-read nrhs / 8 times
+  const int rb = std::min(8, rhs_block_for(V, nrhs));
   dim3 grid((unsigned)ceil_div(V, 256), (unsigned)ceil_div(nrhs, rb));
   const Cx<R>* U = std::is_same<R, float>::value ? (const Cx<R>*)L.U32.p : (const Cx<R>*)L.U64.p;
   KTimer kt(ctx, "wilson", (double)nrhs * V * 4 * sizeof(Cx<R>) + (double)V * 2 * sizeof(Cx<R>));
@@ -735,18 +847,19 @@ template <typename R>
 void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color, int mr_iters) {
   const Cx<R>* U = std::is_same<R, float>::value ? (const Cx<R>*)L.U32.p : (const Cx<R>*)L.U64.p;
   const int64_t V = L.sites();
-  const int rb = rhs_block_for(V, nrhs);
+  const int rb = std::min(4, rhs_block_for(V, nrhs));  // 4 RHS per thread: more workgroups in flight
   KTimer kt(ctx, "sap", (double)nrhs * V * 2 * sizeof(Cx<R>) * 2.5 + (double)V * sizeof(Cx<R>));
   // 4x4 blocks when the block checkerboard has even extents (no two neighbouring blocks
   // share a colour, also across the periodic boundary), else 2x2 blocks (the fine extents
   // are multiples of 4, so 2x2 block counts are even).
+  REQUIRE(L.Lx % 4 == 0 && L.Lt % 4 == 0, "SAP needs fine extents divisible by 4");
   if (L.Lx % 8 == 0 && L.Lt % 8 == 0) {
-    const int nblk = (L.Lx / 4) * (L.Lt / 4);
+    const int nblk = (L.Lx / 4) * (L.Lt / 4) / 2;  // blocks of one colour
     dim3 grid((unsigned)ceil_div(nblk, 16), (unsigned)ceil_div(nrhs, rb));
     hipLaunchKernelGGL((sap_kernel<R, 4, 4>), grid, dim3(256), 0, ctx->stream, U, x, b, L.Lx, L.Lt,
                        (R)(L.m0 + 2.0), nrhs, rb, color, mr_iters);
   } else {
-    const int nblk = (L.Lx / 2) * (L.Lt / 2);
+    const int nblk = (L.Lx / 2) * (L.Lt / 2) / 2;
     dim3 grid((unsigned)ceil_div(nblk, 64), (unsigned)ceil_div(nrhs, rb));
     hipLaunchKernelGGL((sap_kernel<R, 2, 2>), grid, dim3(256), 0, ctx->stream, U, x, b, L.Lx, L.Lt,
                        (R)(L.m0 + 2.0), nrhs, rb, color, mr_iters);
@@ -795,8 +908,10 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
             (double)nrhs * (L.n() + threads) * sizeof(Cx<R>) + (double)L.n() * L.N * sizeof(Cx<R>));
   if (std::is_same<R, float>::value && transfer16_ok(L)) {
     REQUIRE(((uintptr_t)xf | (uintptr_t)yc) % 16 == 0, "matrix-core restriction needs 16-byte aligned vectors");
-    hipLaunchKernelGGL(restrict16_mfma_kernel, dim3((unsigned)ceil_div(Vc, 4)), dim3(256), 0, ctx->stream,
-                       (const c64*)P, (const c64*)xf, (c64*)yc, agg_map(L), Vc, nrhs);
+    const AggMap g = agg_map(L);
+    const int wpa = g.E / 16 >= 4 ? 4 : 1;  // wavefronts per aggregate
+    hipLaunchKernelGGL(restrict16_mfma_kernel, dim3((unsigned)ceil_div(Vc, 4 / wpa)), dim3(256), 0, ctx->stream,
+                       (const c64*)P, (const c64*)xf, (c64*)yc, g, Vc, nrhs, wpa);
     LAUNCH_CHECK();
     return;
   }

@@ -1,0 +1,198 @@
+"""Parity at the full 1024 x 1024 workload, in the launch configuration the benchmark
+times (four levels, 32 RHS per block, complex FP32 bulk inside FP64 refinement) (GPU).
+
+The checker cannot build the 1024^2 hierarchy (its test-vector setup needs direct
+solves with 2M unknowns), so at this size the comparisons are of two kinds:
+
+* against the checker directly: noise bit-exact, the fine operator on sampled RHS, and
+  fine-level solves whose residuals the checker recomputes with its own matvec;
+* identities that hold at any size: P^H P = I and Gamma5 P = P Gamma5 (eq. 14) for the
+  device-built interpolators, the Galerkin identity <P y, D P x> = <y, D_2 x> with the
+  checker's fine D, eigenpair residuals and orthonormality of the deflation space, and
+  the composition of the sample values from independently checked pieces.
+"""
+import numpy as np
+import pytest
+
+from oracle import noise as onoise, wilson as ow
+from paper_2211_15383_amd.inputs import WORKLOADS, load_m0
+
+from _helpers import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+NAME = "schwinger1024"
+B = 32  # RHS block of the timed configuration
+
+
+@pytest.fixture(scope="module")
+def full(gpu):
+    torch, dm, ctx = gpu
+    W = WORKLOADS[NAME]
+    m0 = load_m0(NAME)
+    theta = W.theta()
+    print(f"[fullsize] building {NAME} hierarchy and deflation", flush=True)
+    H = dm.Hierarchy(ctx, theta, m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed)
+    D = dm.Deflation(H, W.nlevels, W.k_defl, eig_rtol=1e-9)
+    Dfine = ow.dirac_operator(theta, m0)
+    return W, m0, H, D, Dfine
+
+
+def _g5(n: int, dofs: int) -> np.ndarray:
+    half = dofs // 2
+    return np.tile(np.concatenate([np.ones(half), -np.ones(half)]), n // dofs)
+
+
+def test_full_noise_bit_exact(gpu, full):
+    torch, dm, ctx = gpu
+    W, m0, H, D, Dfine = full
+    for level in (1, W.nlevels):
+        n = H.n(level)
+        x = ctx.z2_noise(n, W.noise_seed, level, 0, B, dm.MIXED).cpu().numpy()
+        rows = (0, 13, B - 1) if level == 1 else range(B)
+        for r in rows:
+            assert np.array_equal(x[r].real, onoise.z2_noise(W.noise_seed, level, r, n)), (level, r)
+
+
+def test_full_fine_stencil(gpu, full):
+    torch, dm, ctx = gpu
+    W, m0, H, D, Dfine = full
+    n = H.n(1)
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    x = torch.randn(B, n, dtype=torch.complex64, device="cuda:0", generator=g)
+    y = torch.empty_like(x)
+    H.apply(dm.OP_D, 1, x, y, dm.MIXED)
+    for r in (0, 7, B - 1):
+        xr = x[r].cpu().numpy().astype(np.complex128)
+        assert rel_err(y[r].cpu().numpy(), Dfine @ xr) < 1e-6, r
+    x64 = x[:4].to(torch.complex128)
+    y64 = torch.empty_like(x64)
+    H.apply(dm.OP_D, 1, x64, y64, dm.FP64)
+    assert rel_err(to_host(y64), Dfine @ to_host(x64)) < 1e-13
+
+
+def test_full_interpolators(gpu, full):
+    """P^H P = I and Gamma5 P = P Gamma5 at every coarsening step (FP64 and FP32)."""
+    torch, dm, ctx = gpu
+    W, m0, H, D, Dfine = full
+    g = torch.Generator(device="cuda:0").manual_seed(6)
+    for l in range(1, W.nlevels):
+        nf, nc = H.n(l), H.n(l + 1)
+        df, dc = H.level_info(l)[2], H.level_info(l + 1)[2]
+        xc = torch.randn(B, nc, dtype=torch.complex128, device="cuda:0", generator=g)
+        for prec, dt, tol in ((dm.FP64, torch.complex128, 1e-12), (dm.MIXED, torch.complex64, 1e-5)):
+            xin = xc.to(dt)
+            yf = torch.empty((B, nf), dtype=dt, device="cuda:0")
+            H.apply(dm.OP_PROLONG, l, xin, yf, prec)
+            back = torch.empty((B, nc), dtype=dt, device="cuda:0")
+            H.apply(dm.OP_RESTRICT, l, yf, back, prec)
+            assert rel_err(to_host(back), to_host(xin)) < tol, ("P^H P", l, prec)
+        g5c = torch.from_numpy(_g5(nc, dc)).to("cuda:0")
+        g5f = torch.from_numpy(_g5(nf, df)).to("cuda:0")
+        a = torch.empty((B, nf), dtype=torch.complex128, device="cuda:0")
+        b = torch.empty_like(a)
+        H.apply(dm.OP_PROLONG, l, (xc * g5c).contiguous(), a, dm.FP64)
+        H.apply(dm.OP_PROLONG, l, xc, b, dm.FP64)
+        assert rel_err(to_host(a), to_host(b * g5f)) < 1e-13, ("Gamma5", l)
+
+
+def test_full_galerkin_identity(gpu, full):
+    """<P y, D P x> = <y, D_2 x> with the checker's fine D; deeper levels with the device's
+    FP64 operators on both sides."""
+    torch, dm, ctx = gpu
+    W, m0, H, D, Dfine = full
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    for l in range(1, W.nlevels):
+        nf, nc = H.n(l), H.n(l + 1)
+        x = torch.randn(4, nc, dtype=torch.complex128, device="cuda:0", generator=g)
+        y = torch.randn(4, nc, dtype=torch.complex128, device="cuda:0", generator=g)
+        px = torch.empty((4, nf), dtype=torch.complex128, device="cuda:0")
+        py = torch.empty_like(px)
+        H.apply(dm.OP_PROLONG, l, x, px, dm.FP64)
+        H.apply(dm.OP_PROLONG, l, y, py, dm.FP64)
+        if l == 1:
+            dpx = Dfine @ to_host(px)
+        else:
+            t = torch.empty_like(px)
+            H.apply(dm.OP_D, l, px, t, dm.FP64)
+            dpx = to_host(t)
+        lhs = np.einsum("ij,ij->j", to_host(py).conj(), dpx)
+        dcx = torch.empty_like(x)
+        H.apply(dm.OP_D, l + 1, x, dcx, dm.FP64)
+        rhs = np.einsum("ij,ij->j", to_host(y).conj(), to_host(dcx))
+        assert np.abs(lhs - rhs).max() / np.abs(rhs).max() < 1e-11, l
+
+
+def test_full_fine_solve_and_first_sample_term(gpu, full):
+    """Mixed-precision fine-level solves of the first block of level-1 noise: residuals by
+    the checker's matvec; then every level-1 sample of an MLMC run equals x^H D_1^-1 x
+    (these solves) minus y^H D_2^-1 y (a device solve of y = P^H x)."""
+    torch, dm, ctx = gpu
+    W, m0, H, D, Dfine = full
+    n = H.n(1)
+    Bm = np.column_stack([onoise.z2_noise(W.noise_seed, 1, i, n) for i in range(B)]).astype(np.complex128)
+    H.set_deflation(D)  # the V-cycles of an MLMC run use the deflated coarsest solve
+    try:
+        X, st = H.solve(1, to_dev(torch, Bm), prec=dm.MIXED, rtol=W.rtol)
+        Y = torch.empty((B, H.n(2)), dtype=torch.complex128, device="cuda:0")
+        H.apply(dm.OP_RESTRICT, 1, to_dev(torch, Bm), Y, dm.FP64)
+        Z, _ = H.solve(2, Y, prec=dm.MIXED, rtol=W.rtol)
+    finally:
+        H.set_deflation(None)
+    Xh = to_host(X)
+    res = np.linalg.norm(Bm - Dfine @ Xh, axis=0) / np.linalg.norm(Bm, axis=0)
+    assert res.max() <= W.rtol * 1.0001, res.max()
+    t1 = np.einsum("ij,ij->j", Bm.conj(), Xh)
+    t2 = np.einsum("ij,ij->j", to_host(Y).conj(), to_host(Z))
+    L = W.nlevels
+    r = dm.mlmc_trace(H, D, W.eps, W.noise_seed, [B] + [1] * (L - 1), B, prec=dm.MIXED, rtol=W.rtol,
+                      fixed_counts=True, max_samples=[B] * L, keep_samples=True)
+    s = r.samples[0][:B]
+    err = np.abs(s - (t1 - t2)) / (np.abs(t1) + np.abs(t2))
+    assert err.max() < 1e-7, err.max()
+
+
+def test_full_deflation(gpu, full):
+    """Eigenpairs of Q_L = Gamma5 D_L (device FP64 operator), orthonormal X, and
+    tr(D^-1 Pi) = sum x^H Gamma5 x / lambda recomputed from the exported pairs."""
+    torch, dm, ctx = gpu
+    W, m0, H, D, Dfine = full
+    L = W.nlevels
+    X, lam = D.export()
+    k, n = X.shape
+    assert k == W.k_defl
+    Xt = torch.from_numpy(X).to("cuda:0")
+    QX = torch.empty_like(Xt)
+    H.apply(dm.OP_GAMMA5_D, L, Xt, QX, dm.FP64)
+    QXh = QX.cpu().numpy()
+    # ||Q|| from power iteration on the Hermitian Q (a lower bound, hence the factor 2)
+    v = torch.randn(1, n, dtype=torch.complex128, device="cuda:0", generator=torch.Generator(device="cuda:0").manual_seed(3))
+    w = torch.empty_like(v)
+    qn = 0.0
+    for _ in range(40):
+        v = v / torch.linalg.vector_norm(v)
+        H.apply(dm.OP_GAMMA5_D, L, v, w, dm.FP64)
+        qn = float(torch.linalg.vector_norm(w))
+        v = w.clone()
+    res = np.linalg.norm(QXh - lam[:, None] * X, axis=1)
+    assert res.max() < 2e-9 * qn, (res.max(), qn)
+    G = X.conj() @ X.T
+    assert np.abs(G - np.eye(k)).max() < 1e-10
+    g5 = _g5(n, 16)
+    tr = float(np.sum(np.real(np.einsum("ij,ij->i", X.conj(), g5[None, :] * X)) / lam))
+    assert abs(tr - D.tr_defl) < 1e-10 * abs(D.tr_defl)
+
+
+def test_full_mixed_matches_fp64(gpu, full):
+    """Same noise indices, mixed precision vs the FP64 solver: per-sample agreement within
+    1e-6 of each level's sample scale, and the same trace estimate."""
+    torch, dm, ctx = gpu
+    W, m0, H, D, Dfine = full
+    L = W.nlevels
+    kw = dict(fixed_counts=True, max_samples=[B] * L, keep_samples=True, rtol=W.rtol)
+    rm = dm.mlmc_trace(H, D, W.eps, W.noise_seed, [B] * L, B, prec=dm.MIXED, **kw)
+    rf = dm.mlmc_trace(H, D, W.eps, W.noise_seed, [B] * L, B, prec=dm.FP64, **kw)
+    for l in range(L):
+        sm, sf = rm.samples[l][:B], rf.samples[l][:B]
+        assert np.abs(sm - sf).max() / np.abs(sf).max() < 1e-6, l
+    assert abs(rm.trace - rf.trace) / abs(rf.trace) < 1e-8
