@@ -181,6 +181,8 @@ dmlmc_status dmlmc_solve_multi_rhs(dmlmc_ctx *ctx, const dmlmc_hier *h, int leve
  * |estimate|.  Sample counts start at n0[l] (rounded up to rhs_block) and follow the
  * multilevel allocation N_l = ceil(eps^-2 T^-2 sqrt(V_l / C_l) sum_j sqrt(V_j C_j))
  * (C_l: a fixed per-level work proxy) until the error is <= eps, unless fixed_counts.
+ * rhs_block = 0 takes the block size chosen by dmlmc_tune_rhs_block for this hierarchy
+ * (ESTATE if it was never tuned).
  * samples_out[l-1], when not NULL, receives max_samples[l-1] complex128 sample values
  * (host).  Errors: EINVAL, ENOCONV (a solve failed; result holds the samples so far). */
 typedef struct {
@@ -194,10 +196,19 @@ typedef struct {
   int fixed_counts;
   int maxiter;
   double *samples_out[8];
+  /* skip[l-1] != 0 leaves hierarchy level l out of the telescoping sum, so that a term
+   * joins level l-1 to level l+1 through the composite P_{l-1} P_l (eq. 12; levels 1 and
+   * L are always kept).  Results, n0, max_samples and samples_out stay indexed by the
+   * level a term starts at; skipped levels report N = 0. */
+  int skip[8];
+  /* term_defl[a-1]: exact deflation of the difference term that starts at level a
+   * (dmlmc_deflate_difference for that term), or NULL; its trace term is added to the
+   * estimate and to tr_defl of the result. */
+  const dmlmc_defl *term_defl[8];
 } dmlmc_mlmc_params;
 
 typedef struct {
-  double trace, trace_imag, rel_err;
+  double trace, trace_imag, rel_err;   /* tr_defl below is included in trace */
   int64_t N[8];
   double mean_re[8], mean_im[8], var[8];
   double cost_s[8];       /* wall seconds spent per level */
@@ -208,6 +219,41 @@ typedef struct {
 
 dmlmc_status dmlmc_mlmc_trace(dmlmc_ctx *ctx, const dmlmc_hier *h, const dmlmc_defl *coarsest,
                               const dmlmc_mlmc_params *p, dmlmc_trace_result *out);
+
+/* ---------------------------------------------------------------- difference-level deflation
+ * Exact deflation of the term (a, b) of the telescoping sum (Sec. 4.2):
+ * M_ab = D_a^-1 - P_ab D_b^-1 P_ab^H with P_ab = P_a ... P_{b-1} (b = a + 1, or further
+ * when the levels in between are skipped, eq. 12).  The k eigenpairs of largest |lambda|
+ * (ties: lambda descending) of the Hermitian J_ab = M_ab Gamma5 = Q_a^-1 - P_ab Q_b^-1 P_ab^H
+ * (eqs. 15-16) give the k largest singular triplets of M_ab, with right singular vectors
+ * V = Gamma5 X.  Samples of the term then project x - V V^H x, and the estimate adds
+ * tr(M_ab V V^H) = sum_i lambda_i x_i^H Gamma5 x_i (returned in *corr_out and kept as
+ * tr_defl of the handle).  Each application of J solves with D_a and D_b in precision
+ * prec to relative residual solve_rtol; the block Davidson eigensolver stops when
+ * max_i ||J x_i - lambda_i x_i|| <= eig_rtol max_i |lambda_i| (ENOCONV after 400 steps,
+ * handle still returned).  The V-cycles inside use the coarsest deflation attached with
+ * dmlmc_set_deflation, if any.  import_X (host [k][n_a] complex128, orthonormal) and
+ * import_lambda (host [k]) replace the eigensolver.  Errors: EINVAL (1 <= a < b <= L,
+ * 1 <= k, 4 k <= n_a), ENOCONV, ENOMEM, EHIP.  The handle is freed by
+ * dmlmc_free_deflation. */
+dmlmc_status dmlmc_deflate_difference(dmlmc_ctx *ctx, dmlmc_hier *h, int a, int b, int k, double eig_rtol,
+                                      double solve_rtol, dmlmc_precision prec, const void *import_X,
+                                      const double *import_lambda, dmlmc_defl **out, double *corr_out);
+
+/* ---------------------------------------------------------------- RHS block autotuner
+ * Batching is this library's own design choice (the method is indifferent to how many
+ * noise vectors one launch carries), so the block size is measured, not derived: for
+ * each of the ncand candidate sizes, one block of samples of every level is drawn and
+ * solved (twice; the second, warm pass is timed) exactly as dmlmc_mlmc_trace would with
+ * precision prec and tolerance rtol, using sample indices from 2^62 on, so no estimate's
+ * samples are touched.  The candidate with the least wall time per sample summed over
+ * the levels is stored in the hierarchy (used by dmlmc_mlmc_trace with rhs_block = 0)
+ * and returned in *best; sec_per_sample (nullable, host [ncand]) receives the sums.
+ * candidates: host [ncand], each in 1..512, ncand in 1..16.  coarsest: as for
+ * dmlmc_mlmc_trace.  Errors: EINVAL, ENOCONV (a solve failed). */
+dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_defl *coarsest,
+                                  const int *candidates, int ncand, dmlmc_precision prec, double rtol,
+                                  uint64_t noise_seed, int *best, double *sec_per_sample);
 
 /* ---------------------------------------------------------------- single operators
  * Applies one operator of level `level` to nrhs device vectors (for parity checks and
@@ -250,10 +296,13 @@ dmlmc_status dmlmc_set_deflation(dmlmc_hier *h, const dmlmc_defl *d);
  * Parameters of the solver that change iteration counts and speed but not the solution
  * (every solve still stops at its FP64 residual tolerance): SAP local minimal-residual
  * iterations, pre/post smoothing sweeps of the V-cycle, fixed GMRES iterations of the
- * coarsest solve without / with an attached coarsest deflation, and the FGMRES restart
- * length (at most 31).  Values < 0 keep the current setting. */
+ * coarsest solve without / with an attached coarsest deflation, the FGMRES restart
+ * length (at most 31), and use_graphs: 1 (default) replays each complex-FP32 FGMRES
+ * iteration (preconditioner, operator, Gram-Schmidt) as a recorded HIP graph after its
+ * first two runs with the same shapes, 0 launches every kernel directly (results are
+ * bitwise the same).  Values < 0 keep the current setting. */
 typedef struct {
-  int sap_mr_iters, nu_pre, nu_post, coarsest_iters, coarsest_iters_defl, restart;
+  int sap_mr_iters, nu_pre, nu_post, coarsest_iters, coarsest_iters_defl, restart, use_graphs;
 } dmlmc_solver_params;
 dmlmc_status dmlmc_set_solver_params(dmlmc_hier *h, const dmlmc_solver_params *p);
 dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p);

@@ -372,7 +372,7 @@ dmlmc_status dmlmc_mlmc_trace(dmlmc_ctx* ctx, const dmlmc_hier* h, const dmlmc_d
     check_hier(ctx, h);
     REQUIRE(p != nullptr && out != nullptr, "NULL pointer");
     const int L = (int)h->lv.size();
-    REQUIRE(p->rhs_block >= 1 && p->rhs_block <= 512, "rhs_block must be in 1..512");
+    REQUIRE(p->rhs_block >= 0 && p->rhs_block <= 512, "rhs_block must be in 0..512 (0: tuned)");
     REQUIRE(p->eps > 0.0 || p->fixed_counts, "eps must be positive");
     REQUIRE(p->rtol > 0.0, "rtol must be positive");
     REQUIRE(p->prec == DMLMC_FP64 || p->prec == DMLMC_MIXED, "unknown precision");
@@ -382,10 +382,88 @@ dmlmc_status dmlmc_mlmc_trace(dmlmc_ctx* ctx, const dmlmc_hier* h, const dmlmc_d
     }
     if (coarsest) {
       if (coarsest->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
-      REQUIRE(coarsest->level == L, "deflation must be of the coarsest level");
+      REQUIRE(coarsest->level == L && coarsest->kind == 0, "deflation must be of the coarsest level");
     }
+    REQUIRE(!p->skip[0] && !p->skip[L - 1], "the finest and the coarsest level cannot be skipped");
+    for (int l = 1; l < L; ++l) {
+      const dmlmc_defl* t = p->term_defl[l - 1];
+      if (!t) continue;
+      if (t->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
+      REQUIRE(!p->skip[l - 1], "a term deflation is given for a skipped level");
+      int nx = l + 1;
+      while (nx < L && p->skip[nx - 1]) ++nx;
+      REQUIRE(t->kind == 1 && t->level == l && t->level_b == nx,
+              "term deflation does not match the term (a, b) of the telescoping sum");
+    }
+    REQUIRE(p->term_defl[L - 1] == nullptr, "the coarsest term is deflated through the coarsest argument");
     std::memset(out, 0, sizeof(*out));
     run_mlmc(const_cast<dmlmc_hier*>(h), coarsest, p, out);
+  });
+}
+
+dmlmc_status dmlmc_deflate_difference(dmlmc_ctx* ctx, dmlmc_hier* h, int a, int b, int k, double eig_rtol,
+                                      double solve_rtol, dmlmc_precision prec, const void* import_X,
+                                      const double* import_lambda, dmlmc_defl** out, double* corr_out) {
+  if (!ctx) return DMLMC_EINVAL;
+  dmlmc_status conv = DMLMC_OK;
+  dmlmc_status st = guarded(ctx, [&]() {
+    REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    check_hier(ctx, h);
+    const int L = (int)h->lv.size();
+    REQUIRE(a >= 1 && a < b && b <= L, "need 1 <= a < b <= L");
+    const int64_t na = h->lv[a - 1].n();
+    REQUIRE(k >= 1 && (int64_t)k * 4 <= na, "k must be in 1..n_a/4");
+    REQUIRE((import_X == nullptr) == (import_lambda == nullptr), "import_X and import_lambda go together");
+    REQUIRE(import_X != nullptr || (eig_rtol > 0.0 && solve_rtol > 0.0), "tolerances must be positive");
+    REQUIRE(prec == DMLMC_FP64 || prec == DMLMC_MIXED, "unknown precision");
+    std::unique_ptr<dmlmc_defl> D(new dmlmc_defl());
+    D->ctx = ctx;
+    D->level = a;
+    D->level_b = b;
+    D->kind = 1;
+    D->k = k;
+    D->n = na;
+    D->X64.alloc(sizeof(c128) * (size_t)k * na);
+    if (import_X) {
+      HIPCHK(hipMemcpy(D->X64.p, import_X, sizeof(c128) * (size_t)k * na, hipMemcpyHostToDevice));
+      D->lambda.assign(import_lambda, import_lambda + k);
+      for (double v : D->lambda) REQUIRE(std::isfinite(v), "imported eigenvalue is not finite");
+    } else {
+      EigResult r = eig_difference(h, a, b, k, eig_rtol, solve_rtol, prec, D->X64.as<c128>());
+      D->lambda = r.lambda;
+      D->eig_iters = r.iters;
+      D->eig_residual = r.max_residual;
+      if (!r.converged) conv = DMLMC_ENOCONV;
+    }
+    defl_finish(h, D.get());
+    if (corr_out) *corr_out = D->tr_defl;
+    *out = D.release();
+  });
+  if (st == DMLMC_OK && conv != DMLMC_OK) {
+    ctx->err = "eigensolver stopped at its iteration limit";
+    return conv;
+  }
+  return st;
+}
+
+dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx* ctx, dmlmc_hier* h, const dmlmc_defl* coarsest, const int* candidates,
+                                  int ncand, dmlmc_precision prec, double rtol, uint64_t noise_seed, int* best,
+                                  double* sec_per_sample) {
+  if (!ctx) return DMLMC_EINVAL;
+  return guarded(ctx, [&]() {
+    check_hier(ctx, h);
+    REQUIRE(candidates != nullptr && best != nullptr, "NULL pointer");
+    REQUIRE(ncand >= 1 && ncand <= 16, "ncand must be in 1..16");
+    for (int c = 0; c < ncand; ++c) REQUIRE(candidates[c] >= 1 && candidates[c] <= 512, "candidates must be in 1..512");
+    REQUIRE(rtol > 0.0, "rtol must be positive");
+    REQUIRE(prec == DMLMC_FP64 || prec == DMLMC_MIXED, "unknown precision");
+    const int L = (int)h->lv.size();
+    if (coarsest) {
+      if (coarsest->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
+      REQUIRE(coarsest->level == L, "deflation must be of the coarsest level");
+    }
+    *best = tune_rhs_block(h, coarsest, candidates, ncand, prec, rtol, noise_seed, sec_per_sample);
   });
 }
 
@@ -393,7 +471,7 @@ dmlmc_status dmlmc_set_deflation(dmlmc_hier* h, const dmlmc_defl* d) {
   if (!h) return DMLMC_EINVAL;
   if (d && d->ctx != h->ctx) return DMLMC_ESTATE;
   h->attached = d;
-  h->coarse_defl = (d && d->level == (int)h->lv.size()) ? d : nullptr;
+  h->coarse_defl = (d && d->kind == 0 && d->level == (int)h->lv.size()) ? d : nullptr;
   return DMLMC_OK;
 }
 
@@ -402,7 +480,8 @@ dmlmc_status dmlmc_set_solver_params(dmlmc_hier* h, const dmlmc_solver_params* p
   auto ok = [](int v, int lo, int hi) { return v < 0 || (v >= lo && v <= hi); };
   const int maxb = gs_max_basis() - 1;
   if (!ok(p->sap_mr_iters, 0, 64) || !ok(p->nu_pre, 0, 16) || !ok(p->nu_post, 0, 16) ||
-      !ok(p->coarsest_iters, 1, maxb) || !ok(p->coarsest_iters_defl, 1, maxb) || !ok(p->restart, 2, maxb))
+      !ok(p->coarsest_iters, 1, maxb) || !ok(p->coarsest_iters_defl, 1, maxb) || !ok(p->restart, 2, maxb) ||
+      !ok(p->use_graphs, 0, 1))
     return DMLMC_EINVAL;
   if (p->nu_pre == 0 && p->nu_post == 0) return DMLMC_EINVAL;
   if (p->sap_mr_iters >= 0) h->sap_mr_iters = p->sap_mr_iters;
@@ -411,6 +490,7 @@ dmlmc_status dmlmc_set_solver_params(dmlmc_hier* h, const dmlmc_solver_params* p
   if (p->coarsest_iters >= 0) h->coarsest_iters = p->coarsest_iters;
   if (p->coarsest_iters_defl >= 0) h->coarsest_iters_defl = p->coarsest_iters_defl;
   if (p->restart >= 0) h->restart = p->restart;
+  if (p->use_graphs >= 0) h->use_graphs = p->use_graphs != 0;
   return DMLMC_OK;
 }
 
@@ -422,6 +502,7 @@ dmlmc_status dmlmc_get_solver_params(const dmlmc_hier* h, dmlmc_solver_params* p
   p->coarsest_iters = h->coarsest_iters;
   p->coarsest_iters_defl = h->coarsest_iters_defl;
   p->restart = h->restart;
+  p->use_graphs = h->use_graphs ? 1 : 0;
   return DMLMC_OK;
 }
 

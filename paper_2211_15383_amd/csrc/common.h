@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -94,6 +95,10 @@ struct DmlmcError : std::runtime_error {
 #define LAUNCH_CHECK() HIPCHK(hipGetLastError())
 
 // ------------------------------------------------------------------ device memory
+// Bumped by every device allocation and free: a recorded HIP graph made before a bump may
+// hold pointers to memory that has moved, and is re-recorded.
+inline std::atomic<uint64_t> g_dev_epoch{0};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -112,10 +117,11 @@ struct DevBuf {
     if (b == 0) return;
     HIPCHK(hipMalloc(&p, b));
     bytes = b;
+    ++g_dev_epoch;
   }
   // grows (never shrinks); contents are not preserved
   void ensure(size_t b) { if (b > bytes) alloc(b); }
-  void release() { if (p) { (void)hipFree(p); p = nullptr; bytes = 0; } }
+  void release() { if (p) { (void)hipFree(p); p = nullptr; bytes = 0; ++g_dev_epoch; } }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
@@ -190,6 +196,17 @@ struct dmlmc_hier {
   // deflation of the coarsest level used inside V-cycles (exact solve on its span, GMRES
   // on the rest); set for the duration of an estimate, or by dmlmc_set_deflation
   const dmlmc_defl* coarse_defl = nullptr;
+  int tuned_block = 0;  // RHS block chosen by the autotuner (0: not tuned)
+  // recorded FGMRES iterations (preconditioner + operator + Gram-Schmidt) of the
+  // complex-FP32 cycles, keyed by everything their launches depend on
+  bool use_graphs = true;
+  struct GraphRec {
+    hipGraphExec_t exec = nullptr;
+    uint64_t epoch = 0;
+  };
+  std::map<std::vector<int64_t>, GraphRec> graphs;
+  std::set<std::vector<int64_t>> graph_seen;
+  int64_t graph_launches = 0;
   int coarsest_iters_defl = 8;
   // solver knobs (not part of the math; iteration counts only)
   int sap_mr_iters = 2;
@@ -203,6 +220,10 @@ struct dmlmc_hier {
 struct dmlmc_defl {
   dmlmc_ctx* ctx = nullptr;
   int level = 0, k = 0;
+  // kind 0: eigenpairs of Q_L = Gamma5 D_L (coarsest term; tr_defl = sum x^H Gamma5 x / lambda);
+  // kind 1: eigenpairs of J = Q_a^-1 - P_ab Q_b^-1 P_ab^H of the term (a = level, b = level_b)
+  // (tr_defl = sum lambda x^H Gamma5 x, the trace of the term on the deflated space)
+  int kind = 0, level_b = 0;
   int64_t n = 0;
   DevBuf X64;     // eigenvectors of Q, [k][n]
   DevBuf W64, W32;// Gamma5 X, [k][n]

@@ -13,7 +13,16 @@ struct EigResult {
 
 // k eigenpairs of Q = Gamma5 D_level with the smallest |lambda|; X written to Xout [k][n].
 EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout);
-// W = Gamma5 X (FP64 and FP32 copies) and tr(D^-1 Pi) from D->X64 and D->lambda.
+// k eigenpairs of J = Q_a^-1 - P_ab Q_b^-1 P_ab^H (P_ab = P_a ... P_{b-1}) with the largest
+// |lambda| (ties: lambda descending), by block Davidson with exact residual expansion;
+// the solves inside J use solve_level (precision prec, tolerance solve_rtol).  X written
+// to Xout [k][n_a].
+EigResult eig_difference(dmlmc_hier* H, int a, int b, int k, double tol, double solve_rtol, dmlmc_precision prec,
+                         c128* Xout);
+// W = J V for nv vectors (device [nv][n_a], FP64)
+void apply_J(dmlmc_hier* H, int a, int b, const c128* V, c128* W, int nv, dmlmc_precision prec, double rtol);
+// W = Gamma5 X (FP64 and FP32 copies) and the trace term from D->X64 and D->lambda (kind 0:
+// sum x^H Gamma5 x / lambda; kind 1: sum lambda x^H Gamma5 x).
 void defl_finish(dmlmc_hier* H, dmlmc_defl* D);
 // C[r][i] = <w_i, x_r> and X <- X - W C
 void defl_coeffs_fp64(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, int b, int64_t ldx, c128* C);

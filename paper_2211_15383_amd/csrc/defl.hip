@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "defl.h"
+#include "tsgemm.h"
 #include "eigh_host.h"
 #include "setup.h"
 #include "solver.h"
@@ -245,11 +246,11 @@ void applyQ(dmlmc_ctx* ctx, const Level& L, const c128* x, c128* y, int nv) {
   apply_op<double>(ctx, L, x, y, nv, /*gamma5_left=*/true);
 }
 
-// G[r][i] = <Y_i, Z_r> (ns x nv) -> host, row-major host matrix M[i][r]
+// M[i][r] = <Y_i, Z_r> (nsY x nv) -> host, row-major
 std::vector<std::complex<double>> gram(dmlmc_hier* H, const c128* Y, int nsY, const c128* Z, int nv, int64_t n) {
   dmlmc_ctx* ctx = H->ctx;
   c128* G = (c128*)hier_buf(H, "eg_G", 0, sizeof(c128) * (size_t)nsY * nv);
-  launch_multidot<double>(ctx, Y, nsY, Z, n, nv, n, n, G, nsY, 0);
+  ts_gram(ctx, Y, nsY, Z, nv, n, G, hier_devbuf(H, "eg_part", 0));
   std::vector<c128> h((size_t)nsY * nv);
   HIPCHK(hipMemcpyAsync(h.data(), G, sizeof(c128) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -259,7 +260,7 @@ std::vector<std::complex<double>> gram(dmlmc_hier* H, const c128* Y, int nsY, co
   return M;
 }
 
-// out_r = sum_i S[i][r] Y_i (S host ns x nv row-major); out must not alias Y
+// out_r = sum_i S[i][r] Y_i (S host nsY x nv row-major); out must not alias Y
 void rotate(dmlmc_hier* H, const c128* Y, int nsY, const std::vector<std::complex<double>>& S, int nv, c128* out,
             int64_t n) {
   dmlmc_ctx* ctx = H->ctx;
@@ -268,9 +269,7 @@ void rotate(dmlmc_hier* H, const c128* Y, int nsY, const std::vector<std::comple
     for (int i = 0; i < nsY; ++i) h[(size_t)r * nsY + i] = cmk(S[(size_t)i * nv + r].real(), S[(size_t)i * nv + r].imag());
   c128* hd = (c128*)hier_buf(H, "eg_S", 0, sizeof(c128) * h.size());
   HIPCHK(hipMemcpyAsync(hd, h.data(), sizeof(c128) * h.size(), hipMemcpyHostToDevice, ctx->stream));
-  launch_fill_zero<c128>(ctx, out, (size_t)nv * n);
-  // out_r -= (-1) * sum_i h[r][i] Y_i
-  launch_multiaxpy<double>(ctx, Y, nsY, out, n, nv, n, n, hd, nsY, 0, -1.0);
+  ts_rotate(ctx, Y, nsY, hd, nv, n, out);
   HIPCHK(hipStreamSynchronize(ctx->stream));
 }
 
@@ -436,6 +435,163 @@ void defl_finish(dmlmc_hier* H, dmlmc_defl* D) {
   HIPCHK(hipMemcpyAsync(h.data(), dd, sizeof(c128) * D->k, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   double tr = 0.0;
-  for (int i = 0; i < D->k; ++i) tr += h[i].x / D->lambda[i];
+  for (int i = 0; i < D->k; ++i) tr += D->kind == 1 ? h[i].x * D->lambda[i] : h[i].x / D->lambda[i];
   D->tr_defl = tr;
+}
+
+// ------------------------------------------------------------------ difference levels
+void apply_J(dmlmc_hier* H, int a, int b, const c128* V, c128* W, int nv, dmlmc_precision prec, double rtol) {
+  dmlmc_ctx* ctx = H->ctx;
+  const Level& La = H->lv[a - 1];
+  const Level& Lb = H->lv[b - 1];
+  const int64_t na = La.n(), nbn = Lb.n();
+  constexpr int CH = 32;  // vectors per multi-RHS solve
+  for (int c0 = 0; c0 < nv; c0 += CH) {
+    const int m = std::min(CH, nv - c0);
+    const c128* v = V + (int64_t)c0 * na;
+    c128* w = W + (int64_t)c0 * na;
+    c128* t1 = (c128*)hier_buf(H, "jq_t1", a, sizeof(c128) * (size_t)m * na);
+    // Q_a^-1 v = D_a^-1 Gamma5 v
+    hipLaunchKernelGGL(gamma5_kernel, dim3((unsigned)ceil_div(na * m, 256)), dim3(256), 0, ctx->stream, v, t1, na,
+                       La.dofs, m);
+    LAUNCH_CHECK();
+    SolveResult r1 = solve_level(H, a, t1, w, m, prec, rtol, 5000);
+    if (!r1.converged) throw DmlmcError(DMLMC_ENOCONV, "a solve inside the difference operator did not converge");
+    // P_ab Q_b^-1 P_ab^H v
+    const c128* cur = v;
+    for (int l = a; l < b; ++l) {
+      c128* nxt = (c128*)hier_buf(H, "jq_r", l + 1, sizeof(c128) * (size_t)m * H->lv[l].n());
+      launch_restrict<double>(ctx, H->lv[l - 1], cur, nxt, m);
+      cur = nxt;
+    }
+    c128* t2 = (c128*)hier_buf(H, "jq_t2", b, sizeof(c128) * (size_t)m * nbn);
+    c128* z2 = (c128*)hier_buf(H, "jq_z2", b, sizeof(c128) * (size_t)m * nbn);
+    hipLaunchKernelGGL(gamma5_kernel, dim3((unsigned)ceil_div(nbn * m, 256)), dim3(256), 0, ctx->stream, cur, t2, nbn,
+                       Lb.dofs, m);
+    LAUNCH_CHECK();
+    SolveResult r2 = solve_level(H, b, t2, z2, m, prec, rtol, 5000);
+    if (!r2.converged) throw DmlmcError(DMLMC_ENOCONV, "a solve inside the difference operator did not converge");
+    cur = z2;
+    for (int l = b - 1; l >= a; --l) {
+      c128* nxt = l == a ? t1 : (c128*)hier_buf(H, "jq_p", l, sizeof(c128) * (size_t)m * H->lv[l - 1].n());
+      launch_prolong<double>(ctx, H->lv[l - 1], cur, nxt, m, false);
+      cur = nxt;
+    }
+    // w = Q_a^-1 v - P Q_b^-1 P^H v: t1 = w - t1, then w = t1
+    launch_xmy<double>(ctx, w, t1, na, m, na, na);
+    HIPCHK(hipMemcpyAsync(w, t1, sizeof(c128) * (size_t)m * na, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+}
+
+namespace {
+
+// indices of the first `count` values ordered by |theta| descending, then theta descending
+std::vector<int> largest_first(const std::vector<double>& th, int count) {
+  std::vector<int> o(th.size());
+  for (size_t i = 0; i < th.size(); ++i) o[i] = (int)i;
+  std::sort(o.begin(), o.end(), [&](int i, int j) {
+    const double ai = std::fabs(th[i]), aj = std::fabs(th[j]);
+    return ai > aj || (ai == aj && th[i] > th[j]);
+  });
+  o.resize(count);
+  return o;
+}
+
+}  // namespace
+
+EigResult eig_difference(dmlmc_hier* H, int a, int b, int k, double tol, double solve_rtol, dmlmc_precision prec,
+                         c128* Xout) {
+  dmlmc_ctx* ctx = H->ctx;
+  const int64_t n = H->lv[a - 1].n();
+  // the top of the spectrum of J is flat (many |lambda| close to the largest), so the
+  // retained subspace carries 32 (or k) vectors beyond the wanted ones
+  const int ns = (int)std::min<int64_t>(n / 2 - k, k + std::max(32, k));
+  REQUIRE(ns >= k, "deflation subspace too large for the level");
+  // block Davidson: the basis grows by the residual block of the k wanted Ritz pairs
+  // (orthogonalised against it) until it holds ns + 8 k vectors, then restarts from the
+  // ns leading Ritz vectors
+  const int cap = (int)std::min<int64_t>(n / 2, ns + 8 * k);
+  EigResult res;
+  c128* Y = (c128*)hier_buf(H, "ed_Y", 0, sizeof(c128) * (size_t)cap * n);
+  c128* Z = (c128*)hier_buf(H, "ed_Z", 0, sizeof(c128) * (size_t)cap * n);
+  c128* T = (c128*)hier_buf(H, "ed_T", 0, sizeof(c128) * (size_t)cap * n);
+  c128* U = (c128*)hier_buf(H, "ed_U", 0, sizeof(c128) * (size_t)cap * n);
+  c128* Rb = (c128*)hier_buf(H, "ed_R", 0, sizeof(c128) * (size_t)k * n);
+  c128* Rt = (c128*)hier_buf(H, "ed_Rt", 0, sizeof(c128) * (size_t)k * n);
+  c128* C = (c128*)hier_buf(H, "ed_C", 0, sizeof(c128) * (size_t)cap * k);
+  launch_z4(ctx, Y, n, 0x5eed5eedull, a + 96, 0, ns);
+  if (!cholqr2(H, Y, T, ns, n)) throw DmlmcError(DMLMC_ENUMERIC, "eigensolver: start block is rank-deficient");
+  apply_J(H, a, b, Y, Z, ns, prec, solve_rtol);
+  int cur = ns;
+  const int maxit = 400;
+  std::vector<double> th, thk(k);
+  std::vector<std::complex<double>> S;
+  double* thd = (double*)hier_buf(H, "ed_th", 0, sizeof(double) * k);
+  double* nrd = (double*)hier_buf(H, "ed_nr", 0, sizeof(double) * k);
+  auto columns = [&](const std::vector<int>& ord, int cnt) {
+    std::vector<std::complex<double>> Sc((size_t)cur * cnt);
+    for (int c = 0; c < cnt; ++c)
+      for (int i = 0; i < cur; ++i) Sc[(size_t)i * cnt + c] = S[(size_t)i * cur + ord[c]];
+    return Sc;
+  };
+  int it = 0;
+  for (;; ++it) {
+    // Rayleigh-Ritz on span(Y): J is Hermitian, so the projected matrix is symmetrised
+    std::vector<std::complex<double>> G = gram(H, Y, cur, Z, cur, n);
+    for (int i = 0; i < cur; ++i)
+      for (int r = i; r < cur; ++r) {
+        const std::complex<double> v = 0.5 * (G[(size_t)i * cur + r] + std::conj(G[(size_t)r * cur + i]));
+        G[(size_t)i * cur + r] = v;
+        G[(size_t)r * cur + i] = std::conj(v);
+      }
+    eigh_jacobi(cur, G, th, S);
+    const std::vector<int> ord = largest_first(th, std::min(cur, ns));
+    for (int c = 0; c < k; ++c) thk[c] = th[ord[c]];
+    // the k wanted Ritz vectors (T) and J applied to them (U); residuals U - theta T -> Rb
+    const std::vector<std::complex<double>> Sk = columns(ord, k);
+    rotate(H, Y, cur, Sk, k, T, n);
+    rotate(H, Z, cur, Sk, k, U, n);
+    HIPCHK(hipMemcpyAsync(Rb, U, sizeof(c128) * (size_t)k * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(thd, thk.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(ritz_res_kernel, dim3((unsigned)ceil_div(n * k, 256)), dim3(256), 0, ctx->stream, Rb, T, thd, n,
+                       k);
+    LAUNCH_CHECK();
+    launch_norms2<double>(ctx, Rb, n, k, n, nrd);
+    std::vector<double> rn(k);
+    HIPCHK(hipMemcpyAsync(rn.data(), nrd, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double scale = std::fabs(thk[0]);
+    double worst = 0.0;
+    for (int i = 0; i < k; ++i) worst = std::max(worst, std::sqrt(rn[i]));
+    res.max_residual = scale > 0.0 ? worst / scale : worst;
+    if (res.max_residual <= tol || it + 1 >= maxit) break;
+    if (cur + k > cap) {
+      // restart from the ns leading Ritz vectors
+      const std::vector<std::complex<double>> Sn = columns(ord, ns);
+      rotate(H, Y, cur, Sn, ns, T, n);
+      rotate(H, Z, cur, Sn, ns, U, n);
+      std::swap(Y, T);
+      std::swap(Z, U);
+      cur = ns;
+    }
+    // expansion by the residual block, orthogonalised against the basis twice and within itself
+    for (int pass = 0; pass < 2; ++pass) {
+      ts_gram(ctx, Y, cur, Rb, k, n, C, hier_devbuf(H, "eg_part", 0));  // C[r][i] = <Y_i, R_r>
+      ts_rotate(ctx, Y, cur, C, k, n, Rt);                                 // Rt_r = sum_i C[r][i] Y_i
+      launch_xmy<double>(ctx, Rb, Rt, n, k, n, n);                         // Rt = R - Rt
+      std::swap(Rb, Rt);
+    }
+    c128* R = Rb;
+    c128* tmp = Rt;
+    if (!cholqr2(H, R, tmp, k, n)) orthonormalise(H, R, k, n);
+    HIPCHK(hipMemcpyAsync(Y + (int64_t)cur * n, R, sizeof(c128) * (size_t)k * n, hipMemcpyDeviceToDevice, ctx->stream));
+    apply_J(H, a, b, Y + (int64_t)cur * n, Z + (int64_t)cur * n, k, prec, solve_rtol);
+    cur += k;
+  }
+  res.iters = it + 1;
+  res.converged = res.max_residual <= tol;
+  res.lambda.assign(thk.begin(), thk.end());
+  HIPCHK(hipMemcpyAsync(Xout, T, sizeof(c128) * (size_t)k * n, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return res;
 }

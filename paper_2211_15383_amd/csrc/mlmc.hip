@@ -26,9 +26,13 @@ double now_s() {
 
 }  // namespace
 
-// Sample values of indices [i0, i0 + b) of level l, appended to out.
+// Sample values of indices [i0, i0 + b) of the term that starts at level l, appended to
+// out.  l < L: the difference term (l, lb) with lb the next level kept (l + 1, or further
+// when levels are skipped, eq. 12), deflated by tdefl when given (Sec. 4.2); l = L: the
+// coarsest term, deflated by defl.
 static int sample_block(dmlmc_hier* H, const dmlmc_defl* defl, int l, int64_t i0, int b,
-                        const dmlmc_mlmc_params* p, std::vector<std::complex<double>>& out) {
+                        const dmlmc_mlmc_params* p, std::vector<std::complex<double>>& out, int lb = 0,
+                        const dmlmc_defl* tdefl = nullptr) {
   dmlmc_ctx* ctx = H->ctx;
   const int L = (int)H->lv.size();
   const Level& F = H->lv[l - 1];
@@ -40,14 +44,33 @@ static int sample_block(dmlmc_hier* H, const dmlmc_defl* defl, int l, int64_t i0
   int iters = 0;
   const int maxit = p->maxiter > 0 ? p->maxiter : 2000;
   if (l < L) {
-    const Level& C = H->lv[l];
-    const int64_t nc = C.n();
-    c128* Y = (c128*)hier_buf(H, "ml_Y", l + 1, sizeof(c128) * (size_t)b * nc);
-    c128* Zc = (c128*)hier_buf(H, "ml_Zc", l + 1, sizeof(c128) * (size_t)b * nc);
+    if (lb == 0) lb = l + 1;
+    const int64_t nc = H->lv[lb - 1].n();
+    // x~ = x - V V^H x for a deflated term
+    const c128* Xr = X;
+    if (tdefl) {
+      c128* Xt = (c128*)hier_buf(H, "ml_Xt", l, sizeof(c128) * (size_t)b * n);
+      HIPCHK(hipMemcpyAsync(Xt, X, sizeof(c128) * (size_t)b * n, hipMemcpyDeviceToDevice, ctx->stream));
+      defl_apply(H, tdefl, Xt, b, n, p->prec);
+      Xr = Xt;
+    }
+    // y = P^H x and y~ = P^H x~ through the levels between l and lb
+    auto restrict_to = [&](const c128* src, const char* tag) -> c128* {
+      const c128* cur = src;
+      c128* nxt = nullptr;
+      for (int m = l; m < lb; ++m) {
+        nxt = (c128*)hier_buf(H, m + 1 == lb ? tag : "ml_Rm", m + 1, sizeof(c128) * (size_t)b * H->lv[m].n());
+        launch_restrict<double>(ctx, H->lv[m - 1], cur, nxt, b);
+        cur = nxt;
+      }
+      return nxt;
+    };
+    c128* Zc = (c128*)hier_buf(H, "ml_Zc", lb, sizeof(c128) * (size_t)b * nc);
     c128* s2 = (c128*)hier_buf(H, "ml_s2", l, sizeof(c128) * b);
-    SolveResult r1 = solve_level(H, l, X, Z, b, p->prec, p->rtol, maxit);
-    launch_restrict<double>(ctx, F, X, Y, b);
-    SolveResult r2 = solve_level(H, l + 1, Y, Zc, b, p->prec, p->rtol, maxit);
+    SolveResult r1 = solve_level(H, l, Xr, Z, b, p->prec, p->rtol, maxit);
+    c128* Y = restrict_to(X, "ml_Y");
+    const c128* Yr = tdefl ? restrict_to(Xr, "ml_Yt") : Y;
+    SolveResult r2 = solve_level(H, lb, Yr, Zc, b, p->prec, p->rtol, maxit);
     if (!r1.converged || !r2.converged)
       throw DmlmcError(DMLMC_ENOCONV, "sample solve did not converge at level " + std::to_string(l));
     iters = r1.iters + r2.iters;
@@ -83,30 +106,47 @@ void run_mlmc(dmlmc_hier* H, const dmlmc_defl* defl, const dmlmc_mlmc_params* p,
     ~Restore() { H->coarse_defl = prev; }
   } restore{H, H->coarse_defl};
   if (defl) H->coarse_defl = defl;
-  const int blk = p->rhs_block;
+  const int blk = p->rhs_block > 0 ? p->rhs_block : H->tuned_block;
+  if (blk < 1) throw DmlmcError(DMLMC_ESTATE, "rhs_block = 0 but the hierarchy has no tuned block size");
   const double t0 = now_s();
+  // the levels kept in the telescoping sum; next[l] = the level a term starting at l joins
+  std::vector<int> next(L + 1, 0);
+  std::vector<bool> kept(L + 1, false);
+  {
+    int prev = 0;
+    for (int l = 1; l <= L; ++l) {
+      if (l > 1 && l < L && p->skip[l - 1]) continue;
+      kept[l] = true;
+      if (prev) next[prev] = l;
+      prev = l;
+    }
+  }
   std::vector<std::vector<std::complex<double>>> S(L);
-  std::vector<int64_t> target(L), cap(L);
-  std::vector<double> cost(L), level_time(L, 0.0);
+  std::vector<int64_t> target(L, 0), cap(L, 0);
+  std::vector<double> cost(L, 0.0), level_time(L, 0.0);
   std::vector<int64_t> iters(L, 0);
   auto roundup = [&](int64_t m) { return ((m + blk - 1) / blk) * blk; };
+  double tr_defl = defl ? defl->tr_defl : 0.0;
   for (int l = 1; l <= L; ++l) {
-    cost[l - 1] = level_work(H, l) + (l < L ? level_work(H, l + 1) : 0.0);
+    if (!kept[l]) continue;
+    cost[l - 1] = level_work(H, l) + (l < L ? level_work(H, next[l]) : 0.0);
     target[l - 1] = roundup(std::max(1, p->n0[l - 1]));
     cap[l - 1] = p->max_samples[l - 1] > 0 ? p->max_samples[l - 1] : ((int64_t)1 << 40);
+    if (l < L && p->term_defl[l - 1]) tr_defl += p->term_defl[l - 1]->tr_defl;
   }
-  const double tr_defl = defl ? defl->tr_defl : 0.0;
   double T = 0.0, Ti = 0.0, err = INFINITY;
   std::vector<double> var(L, 0.0);
   std::vector<std::complex<double>> mean(L);
   while (true) {
     for (int l = 1; l <= L; ++l) {
+      if (!kept[l]) continue;
       auto& s = S[l - 1];
       while ((int64_t)s.size() < std::min(target[l - 1], cap[l - 1])) {
         const int64_t i0 = (int64_t)s.size();
         const int b = (int)std::min<int64_t>(blk, std::min(target[l - 1], cap[l - 1]) - i0);
         const double ts = now_s();
-        iters[l - 1] += sample_block(H, defl, l, i0, b, p, s);
+        iters[l - 1] += sample_block(H, defl, l, i0, b, p, s, l < L ? next[l] : 0,
+                                     l < L ? p->term_defl[l - 1] : nullptr);
         level_time[l - 1] += now_s() - ts;
       }
     }
@@ -115,6 +155,7 @@ void run_mlmc(dmlmc_hier* H, const dmlmc_defl* defl, const dmlmc_mlmc_params* p,
     Ti = 0.0;
     double vn = 0.0;
     for (int l = 0; l < L; ++l) {
+      if (!kept[l + 1]) continue;
       const auto& s = S[l];
       std::complex<double> m(0.0, 0.0);
       for (auto v : s) m += v;
@@ -131,9 +172,11 @@ void run_mlmc(dmlmc_hier* H, const dmlmc_defl* defl, const dmlmc_mlmc_params* p,
     if (p->fixed_counts || err <= p->eps) break;
     // multilevel allocation
     double sum = 0.0;
-    for (int l = 0; l < L; ++l) sum += std::sqrt(var[l] * cost[l]);
+    for (int l = 0; l < L; ++l)
+      if (kept[l + 1]) sum += std::sqrt(var[l] * cost[l]);
     bool grew = false;
     for (int l = 0; l < L; ++l) {
+      if (!kept[l + 1]) continue;
       const double want = std::ceil(std::sqrt(var[l] / cost[l]) * sum / (p->eps * p->eps * T * T));
       int64_t t = roundup(std::max<int64_t>((int64_t)want, (int64_t)S[l].size()));
       t = std::min(t, cap[l]);
@@ -164,4 +207,45 @@ void run_mlmc(dmlmc_hier* H, const dmlmc_defl* defl, const dmlmc_mlmc_params* p,
     }
   }
   res->t_trace_s = now_s() - t0;
+}
+
+int tune_rhs_block(dmlmc_hier* H, const dmlmc_defl* defl, const int* cand, int ncand, dmlmc_precision prec,
+                   double rtol, uint64_t noise_seed, double* sec_per_sample) {
+  const int L = (int)H->lv.size();
+  struct Restore {
+    dmlmc_hier* H;
+    const dmlmc_defl* prev;
+    ~Restore() { H->coarse_defl = prev; }
+  } restore{H, H->coarse_defl};
+  if (defl) H->coarse_defl = defl;
+  dmlmc_mlmc_params p{};
+  p.noise_seed = noise_seed;
+  p.prec = prec;
+  p.rtol = rtol;
+  p.maxiter = 2000;
+  const int64_t base = (int64_t)1 << 62;  // sample indices no estimate uses
+  int best = cand[0];
+  double best_t = INFINITY;
+  std::vector<std::complex<double>> sink;
+  for (int c = 0; c < ncand; ++c) {
+    const int b = cand[c];
+    double t = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      t = 0.0;
+      for (int l = 1; l <= L; ++l) {
+        sink.clear();
+        HIPCHK(hipStreamSynchronize(H->ctx->stream));
+        const double t0 = now_s();
+        sample_block(H, defl, l, base + (int64_t)pass * 512, b, &p, sink);
+        t += (now_s() - t0) / b;
+      }
+    }
+    if (sec_per_sample) sec_per_sample[c] = t;
+    if (t < best_t) {
+      best_t = t;
+      best = b;
+    }
+  }
+  H->tuned_block = best;
+  return best;
 }

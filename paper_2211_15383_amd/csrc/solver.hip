@@ -97,7 +97,65 @@ DevBuf& hier_devbuf(dmlmc_hier* H, const char* name, int level) {
   return H->ws[level]->bufs[name];
 }
 
-dmlmc_hier::~dmlmc_hier() {}
+dmlmc_hier::~dmlmc_hier() {
+  for (auto& kv : graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+}
+
+// Runs body on the context stream through a recorded HIP graph: the first call with a
+// key runs it directly (so that every workspace buffer it needs exists), the second
+// records and launches it, later ones replay the recording.  A recording is dropped when
+// any device buffer was allocated or freed since it was made (its pointers may be stale);
+// a recording during which that happens is discarded and the body run directly.  Timing
+// runs (events around launches) never record.
+template <typename F>
+static void run_graphed(dmlmc_hier* H, const std::vector<int64_t>& key, F&& body) {
+  dmlmc_ctx* ctx = H->ctx;
+  if (!H->use_graphs || ctx->timing) {
+    body();
+    return;
+  }
+  const uint64_t now = g_dev_epoch.load();
+  auto it = H->graphs.find(key);
+  if (it != H->graphs.end()) {
+    if (it->second.epoch == now) {
+      HIPCHK(hipGraphLaunch(it->second.exec, ctx->stream));
+      ++H->graph_launches;
+      return;
+    }
+    (void)hipGraphExecDestroy(it->second.exec);
+    H->graphs.erase(it);
+    H->graph_seen.erase(key);
+  }
+  if (!H->graph_seen.count(key)) {
+    H->graph_seen.insert(key);
+    body();
+    return;
+  }
+  HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+  hipGraph_t g = nullptr;
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(ctx->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(ctx->stream, &g));
+  if (g_dev_epoch.load() != now) {
+    (void)hipGraphDestroy(g);
+    H->graph_seen.erase(key);
+    body();
+    return;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) throw DmlmcError(DMLMC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  H->graphs[key] = {exec, now};
+  HIPCHK(hipGraphLaunch(exec, ctx->stream));
+  ++H->graph_launches;
+}
 
 KrylovArrays krylov_arrays(dmlmc_hier* H, const char* prefix, int level, int m, int nrhs) {
   KrylovArrays k;
@@ -292,10 +350,14 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, 
   for (int j = 0; j < m; ++j) {
     Cx<RP>* zj = Z + j * vstride;
     if (f32) {
-      launch_scale_vec(ctx, U + j * vstride, scale + (int64_t)j * nrhs, (c64*)vin, n, nrhs);
-      vcycle<RP>(H, l, vin, zj, nrhs);
-      apply_op<RP>(ctx, L, zj, wr, nrhs);
-      arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k);
+      const std::vector<int64_t> key = {l, nrhs, j, m, (int64_t)(uintptr_t)H->coarse_defl, H->coarsest_iters,
+                                        H->coarsest_iters_defl, H->nu_pre, H->nu_post, H->sap_mr_iters};
+      run_graphed(H, key, [&]() {
+        launch_scale_vec(ctx, U + j * vstride, scale + (int64_t)j * nrhs, (c64*)vin, n, nrhs);
+        vcycle<RP>(H, l, vin, zj, nrhs);
+        apply_op<RP>(ctx, L, zj, wr, nrhs);
+        arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k);
+      });
     } else {
       vcycle<RP>(H, l, (const Cx<RP>*)(V + j * vstride), zj, nrhs);
       apply_op<RP>(ctx, L, zj, (Cx<RP>*)w, nrhs);

@@ -24,10 +24,10 @@ OP_D, OP_RESTRICT, OP_PROLONG, OP_SMOOTH, OP_VCYCLE, OP_DEFL_C, OP_DEFL_P, OP_GA
 
 EXPORTED = [
     "dmlmc_create", "dmlmc_destroy", "dmlmc_last_error", "dmlmc_version", "dmlmc_build_hierarchy",
-    "dmlmc_free_hierarchy", "dmlmc_level_info", "dmlmc_export_level", "dmlmc_deflate",
+    "dmlmc_free_hierarchy", "dmlmc_level_info", "dmlmc_export_level", "dmlmc_deflate", "dmlmc_deflate_difference",
     "dmlmc_free_deflation", "dmlmc_deflation_info", "dmlmc_export_deflation", "dmlmc_solve_multi_rhs", "dmlmc_mlmc_trace",
     "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_set_solver_params",
-    "dmlmc_get_solver_params", "dmlmc_timing_enable", "dmlmc_timing_select",
+    "dmlmc_get_solver_params", "dmlmc_timing_enable", "dmlmc_timing_select", "dmlmc_tune_rhs_block",
     "dmlmc_timing_reset", "dmlmc_timing_get",
 ]
 
@@ -54,13 +54,14 @@ class SolveStats(C.Structure):
 
 class SolverParams(C.Structure):
     _fields_ = [("sap_mr_iters", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarsest_iters", C.c_int),
-                ("coarsest_iters_defl", C.c_int), ("restart", C.c_int)]
+                ("coarsest_iters_defl", C.c_int), ("restart", C.c_int), ("use_graphs", C.c_int)]
 
 
 class MLMCParams(C.Structure):
     _fields_ = [("eps", C.c_double), ("noise_seed", C.c_uint64), ("n0", C.c_int * 8),
                 ("max_samples", C.c_int64 * 8), ("rhs_block", C.c_int), ("prec", C.c_int), ("rtol", C.c_double),
-                ("fixed_counts", C.c_int), ("maxiter", C.c_int), ("samples_out", C.POINTER(C.c_double) * 8)]
+                ("fixed_counts", C.c_int), ("maxiter", C.c_int), ("samples_out", C.POINTER(C.c_double) * 8),
+                ("skip", C.c_int * 8), ("term_defl", C.c_void_p * 8)]
 
 
 class TraceResult(C.Structure):
@@ -85,6 +86,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_level_info": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "dmlmc_export_level": (i32, [vp, vp, i32, vp, vp, vp]),
         "dmlmc_deflate": (i32, [vp, vp, i32, i32, dbl, vp, C.POINTER(dbl), C.POINTER(vp), C.POINTER(dbl)]),
+        "dmlmc_deflate_difference": (i32, [vp, vp, i32, i32, i32, dbl, dbl, i32, vp, C.POINTER(dbl), C.POINTER(vp),
+                                           C.POINTER(dbl)]),
         "dmlmc_free_deflation": (None, [vp]),
         "dmlmc_deflation_info": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(dbl)]),
         "dmlmc_export_deflation": (i32, [vp, vp, vp, C.POINTER(dbl)]),
@@ -98,6 +101,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_timing_enable": (i32, [vp, i32]),
         "dmlmc_timing_reset": (i32, [vp]),
         "dmlmc_timing_select": (i32, [vp, C.c_char_p]),
+        "dmlmc_tune_rhs_block": (i32, [vp, vp, vp, C.POINTER(i32), i32, i32, dbl, C.c_uint64, C.POINTER(i32),
+                                       C.POINTER(dbl)]),
         "dmlmc_timing_get": (i32, [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
@@ -289,7 +294,7 @@ class Hierarchy:
 
     def solver_params(self, **kw):
         """Sets the given solver parameters (see dmlmc_solver_params); returns all of them."""
-        p = SolverParams(-1, -1, -1, -1, -1, -1)
+        p = SolverParams(-1, -1, -1, -1, -1, -1, -1)
         for key, v in kw.items():
             setattr(p, key, int(v))
         st = lib().dmlmc_set_solver_params(self.h, C.byref(p))
@@ -299,6 +304,17 @@ class Hierarchy:
         lib().dmlmc_get_solver_params(self.h, C.byref(q))
         return {f: getattr(q, f) for f, _ in SolverParams._fields_}
 
+    def tune_rhs_block(self, defl: Optional["Deflation"], candidates=(16, 32, 64), prec: int = FP64,
+                       rtol: float = 1e-10, noise_seed: int = 0):
+        """Times one block of samples per level for each candidate block size (see
+        dmlmc_tune_rhs_block); returns (best, {candidate: seconds per sample})."""
+        cand = (C.c_int32 * len(candidates))(*candidates)
+        secs = (C.c_double * len(candidates))()
+        best = C.c_int32()
+        self.ctx.check(lib().dmlmc_tune_rhs_block(self.ctx.h, self.h, defl.h if defl is not None else None, cand,
+                                                  len(candidates), prec, rtol, noise_seed, C.byref(best), secs))
+        return best.value, {c: secs[i] for i, c in enumerate(candidates)}
+
     def set_deflation(self, d: Optional["Deflation"]):
         st = lib().dmlmc_set_deflation(self.h, d.h if d is not None else None)
         if st != OK:
@@ -306,10 +322,12 @@ class Hierarchy:
 
 
 class Deflation:
-    """Exact deflation of one level (normally the coarsest)."""
+    """Exact deflation of the coarsest term (dmlmc_deflate) or, with `level_b`, of the
+    difference term (level, level_b) (dmlmc_deflate_difference)."""
 
     def __init__(self, hier: Hierarchy, level: int, k: int, eig_rtol: float = 1e-12,
-                 import_X: Optional[np.ndarray] = None, import_lambda: Optional[np.ndarray] = None):
+                 import_X: Optional[np.ndarray] = None, import_lambda: Optional[np.ndarray] = None,
+                 level_b: int = 0, solve_rtol: float = 1e-12, prec: int = MIXED):
         self.hier = hier
         ctx = hier.ctx
         handle = C.c_void_p()
@@ -322,7 +340,12 @@ class Deflation:
             keep += [Xc, lam]
             pX = Xc.ctypes.data
             plam = lam.ctypes.data_as(C.POINTER(C.c_double))
-        st = lib().dmlmc_deflate(ctx.h, hier.h, level, k, eig_rtol, pX, plam, C.byref(handle), C.byref(tr))
+        if level_b:
+            st = lib().dmlmc_deflate_difference(ctx.h, hier.h, level, level_b, k, eig_rtol, solve_rtol, prec, pX, plam,
+                                                C.byref(handle), C.byref(tr))
+        else:
+            st = lib().dmlmc_deflate(ctx.h, hier.h, level, k, eig_rtol, pX, plam, C.byref(handle), C.byref(tr))
+        self.level_b = level_b
         self.status = st
         if st not in (OK, ENOCONV):
             raise DmlmcError(st, lib().dmlmc_last_error(ctx.h).decode())
@@ -377,7 +400,10 @@ class TraceEstimate:
 def mlmc_trace(hier: Hierarchy, defl: Optional[Deflation], eps: float, noise_seed: int, n0: Sequence[int],
                rhs_block: int, prec: int = FP64, rtol: float = 1e-10, fixed_counts: bool = False,
                max_samples: Optional[Sequence[int]] = None, keep_samples: bool = False,
-               maxiter: int = 2000) -> TraceEstimate:
+               maxiter: int = 2000, skip: Sequence[int] = (),
+               term_defl: Optional[Sequence[Optional[Deflation]]] = None) -> TraceEstimate:
+    """skip: hierarchy levels left out of the telescoping sum (eq. 12); term_defl[a-1]:
+    deflation of the difference term starting at level a, or None."""
     L = hier.nlevels
     p = MLMCParams()
     p.eps = eps
@@ -390,6 +416,11 @@ def mlmc_trace(hier: Hierarchy, defl: Optional[Deflation], eps: float, noise_see
     p.rtol = rtol
     p.fixed_counts = 1 if fixed_counts else 0
     p.maxiter = maxiter
+    for l in skip:
+        p.skip[l - 1] = 1
+    if term_defl is not None:
+        for l, d in enumerate(term_defl):
+            p.term_defl[l] = d.h.value if d is not None else None
     bufs = []
     if keep_samples:
         if max_samples is None:

@@ -1,0 +1,63 @@
+"""The RHS-block autotuner (GPU): it measures every candidate, records the fastest in the
+hierarchy, and an estimate with rhs_block = 0 then draws exactly the samples of an
+estimate with that block size given explicitly (sample values are independent of the
+block size, so both agree with the checker's samples as well)."""
+import numpy as np
+import pytest
+
+from oracle import mlmc as omlmc
+
+from _helpers import oracle_deflation, oracle_hierarchy
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tuned_block_estimate(gpu):
+    torch, dm, ctx = gpu
+    name = "schwinger128"
+    W, m0, lv = oracle_hierarchy(name)
+    H = dm.Hierarchy(ctx, W.theta(), m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                     import_tv=[l.V for l in lv[:-1]])
+    ref = oracle_deflation(name, W.k_defl)
+    d = dm.Deflation(H, len(lv), W.k_defl, import_X=ref.X, import_lambda=ref.lam)
+    L = len(lv)
+    with pytest.raises(dm.DmlmcError):
+        dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [4] * L, 0, prec=dm.MIXED, fixed_counts=True)
+    cands = (8, 16, 32)
+    best, secs = H.tune_rhs_block(d, cands, prec=dm.MIXED, rtol=W.rtol, noise_seed=W.noise_seed)
+    assert best in cands
+    assert all(v > 0 for v in secs.values())
+    assert secs[best] == min(secs.values())
+    kw = dict(prec=dm.MIXED, rtol=W.rtol, fixed_counts=True, max_samples=[40] * L, keep_samples=True)
+    r0 = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [20] * L, 0, **kw)
+    r1 = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [20] * L, best, **kw)
+    assert r0.N == r1.N and all(n % best == 0 for n in r0.N)
+    for l in range(L):
+        assert np.array_equal(r0.samples[l], r1.samples[l])
+    solver = omlmc.DirectSolver(lv)
+    for i in (0, 7):
+        s, t1, t2 = omlmc.difference_sample(lv, solver, W.noise_seed, 1, i)
+        assert abs(r0.samples[0][i] - s) / (abs(t1) + abs(t2)) < 1e-6
+
+
+def test_recorded_iterations_match_direct_launches(gpu):
+    """FGMRES iterations replayed from recorded HIP graphs give bitwise the samples of
+    direct launches, over several estimates (record, then replays with eager work and
+    host synchronisation in between)."""
+    torch, dm, ctx = gpu
+    name = "schwinger128"
+    W, m0, lv = oracle_hierarchy(name)
+    H = dm.Hierarchy(ctx, W.theta(), m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                     import_tv=[l.V for l in lv[:-1]])
+    ref = oracle_deflation(name, W.k_defl)
+    d = dm.Deflation(H, len(lv), W.k_defl, import_X=ref.X, import_lambda=ref.lam)
+    L = len(lv)
+    kw = dict(prec=dm.MIXED, rtol=W.rtol, fixed_counts=True, max_samples=[32] * L, keep_samples=True)
+    assert H.solver_params(use_graphs=0)["use_graphs"] == 0
+    direct = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [32] * L, 16, **kw)
+    assert H.solver_params(use_graphs=1)["use_graphs"] == 1
+    for rep in range(3):
+        g = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [32] * L, 16, **kw)
+        for l in range(L):
+            assert np.array_equal(g.samples[l], direct.samples[l]), (rep, l)
+        assert g.trace == direct.trace
