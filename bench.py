@@ -117,6 +117,49 @@ def kernel_rates(torch, dm, ctx, H, nlev: int, b: int, reps: int = 10):
     return out
 
 
+def method_comparison(torch, dm, ctx, name: str, eps: float, kdiff: int):
+    """The variants of the paper's Table 1 on one synthetic workload (mixed precision,
+    coarsest term always deflated): plain MGMLMC; level 2 skipped (eq. 12); and each of
+    those with the first difference term exactly deflated by its kdiff largest singular
+    triplets (Sec. 4.2).  Returns setup and estimate seconds per variant."""
+    from paper_2211_15383_amd.inputs import WORKLOADS, load_m0
+
+    W = WORKLOADS[name]
+    L = W.nlevels
+    H = dm.Hierarchy(ctx, W.theta(), load_m0(name), W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed)
+    t0 = time.perf_counter()
+    Dc = dm.Deflation(H, L, W.k_defl, eig_rtol=1e-9)
+    t_coarse = time.perf_counter() - t0
+    H.set_deflation(Dc)  # the difference-level eigensolves use the deflated coarsest solve
+    out = {"workload": name, "eps": eps, "k_coarsest": W.k_defl, "k_difference": kdiff,
+           "coarsest_eigensolve_s": t_coarse, "variants": {}}
+    for skip in ((), (2,)):
+        b = 3 if skip else 2
+        for defl in (False, True):
+            label = ("skip2" if skip else "all_levels") + ("+diff_defl" if defl else "")
+            td = 0.0
+            term = [None] * L
+            if defl:
+                t0 = time.perf_counter()
+                dd = dm.Deflation(H, 1, kdiff, eig_rtol=1e-9, level_b=b, solve_rtol=1e-12, prec=dm.MIXED)
+                td = time.perf_counter() - t0
+                term[0] = dd
+            dm.mlmc_trace(H, Dc, eps, W.noise_seed, [W.n0] * L, W.rhs_block, prec=dm.MIXED, rtol=W.rtol,
+                          skip=skip, term_defl=term)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = dm.mlmc_trace(H, Dc, eps, W.noise_seed, [W.n0] * L, W.rhs_block, prec=dm.MIXED, rtol=W.rtol,
+                              skip=skip, term_defl=term)
+            torch.cuda.synchronize()
+            te = time.perf_counter() - t0
+            out["variants"][label] = {"trace_s": te, "difference_eigensolve_s": td, "trace": r.trace,
+                                      "rel_err": r.rel_err, "N": r.N, "var": r.var}
+            log(f"method {label}: {te:.3f} s (+{td:.2f} s eigensolve) trace {r.trace:.4f} rel_err "
+                f"{r.rel_err:.2e} N {r.N}")
+    H.set_deflation(None)
+    return out
+
+
 def cpu_baseline(name: str, nsamp: int):
     """The CPU checker as it stands (direct sparse-LU solves), on the named workload's
     three-level hierarchy, drawing `nsamp` samples per level.  Setup is excluded."""
@@ -152,6 +195,10 @@ def main():
     ap.add_argument("--cpu-workload", default="schwinger128")
     ap.add_argument("--skip-kernel-rates", action="store_true",
                     help="skip the per-kernel runs at the real shapes after the timed steps")
+    ap.add_argument("--methods", default=None, metavar="WORKLOAD",
+                    help="also time plain / skipped-level / difference-deflated MGMLMC on WORKLOAD")
+    ap.add_argument("--methods-eps", type=float, default=1e-3)
+    ap.add_argument("--methods-k", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the estimator's samples would shard across GPUs with one "
@@ -248,6 +295,10 @@ def main():
     g = tb["defl_gemm"]
     gemm_tflops = g["bytes"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
 
+    methods = None
+    if args.methods:
+        methods = method_comparison(torch, dmlmc, ctx, args.methods, args.methods_eps, args.methods_k)
+
     cpu = None
     if not args.skip_cpu:
         nsamp = W.n0
@@ -295,6 +346,8 @@ def main():
                      "algorithmic_bytes_per_launch": avg_bytes, "traffic_summary": traffic_src},
         "cpu_baseline": cpu,
     }
+    if methods is not None:
+        out["methods"] = methods
     print(json.dumps(out), flush=True)
 
 
