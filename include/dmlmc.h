@@ -233,12 +233,18 @@ dmlmc_status dmlmc_mlmc_trace(dmlmc_ctx *ctx, const dmlmc_hier *h, const dmlmc_d
  * max_i ||J x_i - lambda_i x_i|| <= eig_rtol max_i |lambda_i| (ENOCONV after 400 steps,
  * handle still returned).  The V-cycles inside use the coarsest deflation attached with
  * dmlmc_set_deflation, if any.  import_X (host [k][n_a] complex128, orthonormal) and
- * import_lambda (host [k]) replace the eigensolver.  Errors: EINVAL (1 <= a < b <= L,
- * 1 <= k, 4 k <= n_a), ENOCONV, ENOMEM, EHIP.  The handle is freed by
- * dmlmc_free_deflation. */
+ * import_lambda (host [k]) replace the eigensolver.
+ * Inexact deflation (Sec. 3.2, here for M_ab): with corr_rtol > 0 the small term is not
+ * taken from the eigenpairs but evaluated for the vectors at hand,
+ * Re sum_i x_i^H Gamma5 (J_ab x_i), with k more applications of J solved to corr_rtol; the
+ * split then holds for approximate vectors (a loose eig_rtol / solve_rtol, e.g. 1e-1 /
+ * 1e-3).  corr_rtol <= 0: sum_i lambda_i x_i^H Gamma5 x_i (exact eigenpairs).
+ * Errors: EINVAL (1 <= a < b <= L, 1 <= k, 4 k <= n_a), ENOCONV, ENOMEM, EHIP.  The handle
+ * is freed by dmlmc_free_deflation. */
 dmlmc_status dmlmc_deflate_difference(dmlmc_ctx *ctx, dmlmc_hier *h, int a, int b, int k, double eig_rtol,
                                       double solve_rtol, dmlmc_precision prec, const void *import_X,
-                                      const double *import_lambda, dmlmc_defl **out, double *corr_out);
+                                      const double *import_lambda, double corr_rtol, dmlmc_defl **out,
+                                      double *corr_out);
 
 /* ---------------------------------------------------------------- RHS block autotuner
  * Batching is this library's own design choice (the method is indifferent to how many

@@ -22,6 +22,12 @@ because M_ab v_i = X Lambda X^H x_i = lambda_i x_i.  A deflated sample of the te
 s = x^H M_ab (x - V V^H x) = x^H D_a^-1 xt - y^H D_b^-1 yt with xt = x - V V^H x,
 y = P_ab^H x, yt = P_ab^H xt; x is the real Z2 vector of sample i of level a.
 
+Inexact deflation (Sec. 3.2 for D; here for M_ab): with approximate eigenvectors X (any
+orthonormal k columns) the split still holds with Pi = V V^H, V = Gamma5 X, but the small
+term must be evaluated, tr(M_ab Pi) = sum_i v_i^H M_ab v_i = sum_i x_i^H Gamma5 J_ab x_i,
+at the price of k extra applications of J (the "k extra inversions" of the text); its real
+part enters the estimate.
+
 Eigensolvers: dense numpy.linalg.eigh of J (small levels) or scipy's ARPACK (eigsh,
 largest magnitude) on J as a linear operator whose solves are sparse LU.
 """
@@ -134,3 +140,18 @@ def pair_sample(levels, solver: DirectSolver, seed: int, a: int, b: int, i: int,
     x = noise.z2_noise(seed, a, i, levels[a - 1].n)
     t1, t2 = pair_terms(levels, solver, a, b, x, dd)
     return complex(t1 - t2), complex(t1), complex(t2)
+
+
+def inexact_deflation(levels, a: int, b: int, X: np.ndarray, solver: Optional[DirectSolver] = None,
+                      dense: bool = False) -> DiffDeflation:
+    """Deflation of term (a, b) by given orthonormal columns X: lam are the Rayleigh quotients
+    x_i^H J x_i, corr = Re sum_i x_i^H Gamma5 J x_i (k applications of J)."""
+    if dense:
+        JX = J_dense(levels, a, b) @ X
+    else:
+        JX = J_operator(levels, solver or DirectSolver(levels), a, b).matmat(X)
+    g5 = levels[a - 1].gamma5
+    V = np.asarray(g5 @ X)
+    lam = np.real(np.einsum("ik,ik->k", X.conj(), JX))
+    corr = float(np.real(np.sum(np.einsum("ik,ik->k", V.conj(), JX))))
+    return DiffDeflation(a=a, b=b, X=X, lam=lam, V=V, corr=corr)

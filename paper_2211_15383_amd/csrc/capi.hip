@@ -403,7 +403,8 @@ dmlmc_status dmlmc_mlmc_trace(dmlmc_ctx* ctx, const dmlmc_hier* h, const dmlmc_d
 
 dmlmc_status dmlmc_deflate_difference(dmlmc_ctx* ctx, dmlmc_hier* h, int a, int b, int k, double eig_rtol,
                                       double solve_rtol, dmlmc_precision prec, const void* import_X,
-                                      const double* import_lambda, dmlmc_defl** out, double* corr_out) {
+                                      const double* import_lambda, double corr_rtol, dmlmc_defl** out,
+                                      double* corr_out) {
   if (!ctx) return DMLMC_EINVAL;
   dmlmc_status conv = DMLMC_OK;
   dmlmc_status st = guarded(ctx, [&]() {
@@ -437,6 +438,7 @@ dmlmc_status dmlmc_deflate_difference(dmlmc_ctx* ctx, dmlmc_hier* h, int a, int 
       if (!r.converged) conv = DMLMC_ENOCONV;
     }
     defl_finish(h, D.get());
+    if (corr_rtol > 0.0) D->tr_defl = difference_trace_term(h, D.get(), prec, corr_rtol);
     if (corr_out) *corr_out = D->tr_defl;
     *out = D.release();
   });

@@ -19,6 +19,9 @@ EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout);
 // to Xout [k][n_a].
 EigResult eig_difference(dmlmc_hier* H, int a, int b, int k, double tol, double solve_rtol, dmlmc_precision prec,
                          c128* Xout);
+// Re sum_i x_i^H Gamma5 (J x_i) for the deflation's vectors, J applied with solves to rtol
+// (the small trace term of an inexact deflation).
+double difference_trace_term(dmlmc_hier* H, const dmlmc_defl* D, dmlmc_precision prec, double rtol);
 // W = J V for nv vectors (device [nv][n_a], FP64)
 void apply_J(dmlmc_hier* H, int a, int b, const c128* V, c128* W, int nv, dmlmc_precision prec, double rtol);
 // W = Gamma5 X (FP64 and FP32 copies) and the trace term from D->X64 and D->lambda (kind 0:

@@ -483,6 +483,21 @@ void apply_J(dmlmc_hier* H, int a, int b, const c128* V, c128* W, int nv, dmlmc_
   }
 }
 
+double difference_trace_term(dmlmc_hier* H, const dmlmc_defl* D, dmlmc_precision prec, double rtol) {
+  dmlmc_ctx* ctx = H->ctx;
+  const int64_t n = D->n;
+  c128* JX = (c128*)hier_buf(H, "ed_JX", 0, sizeof(c128) * (size_t)D->k * n);
+  apply_J(H, D->level, D->level_b, D->X64.as<c128>(), JX, D->k, prec, rtol);
+  c128* dd = (c128*)hier_buf(H, "ed_dd", 0, sizeof(c128) * D->k);
+  launch_dots<double, double>(ctx, D->W64.as<c128>(), JX, n, D->k, n, n, dd);  // <Gamma5 x_i, J x_i>
+  std::vector<c128> h(D->k);
+  HIPCHK(hipMemcpyAsync(h.data(), dd, sizeof(c128) * D->k, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double tr = 0.0;
+  for (int i = 0; i < D->k; ++i) tr += h[i].x;
+  return tr;
+}
+
 namespace {
 
 // indices of the first `count` values ordered by |theta| descending, then theta descending

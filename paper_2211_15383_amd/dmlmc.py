@@ -86,8 +86,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_level_info": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "dmlmc_export_level": (i32, [vp, vp, i32, vp, vp, vp]),
         "dmlmc_deflate": (i32, [vp, vp, i32, i32, dbl, vp, C.POINTER(dbl), C.POINTER(vp), C.POINTER(dbl)]),
-        "dmlmc_deflate_difference": (i32, [vp, vp, i32, i32, i32, dbl, dbl, i32, vp, C.POINTER(dbl), C.POINTER(vp),
-                                           C.POINTER(dbl)]),
+        "dmlmc_deflate_difference": (i32, [vp, vp, i32, i32, i32, dbl, dbl, i32, vp, C.POINTER(dbl), dbl,
+                                           C.POINTER(vp), C.POINTER(dbl)]),
         "dmlmc_free_deflation": (None, [vp]),
         "dmlmc_deflation_info": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(dbl)]),
         "dmlmc_export_deflation": (i32, [vp, vp, vp, C.POINTER(dbl)]),
@@ -327,7 +327,7 @@ class Deflation:
 
     def __init__(self, hier: Hierarchy, level: int, k: int, eig_rtol: float = 1e-12,
                  import_X: Optional[np.ndarray] = None, import_lambda: Optional[np.ndarray] = None,
-                 level_b: int = 0, solve_rtol: float = 1e-12, prec: int = MIXED):
+                 level_b: int = 0, solve_rtol: float = 1e-12, prec: int = MIXED, corr_rtol: float = 0.0):
         self.hier = hier
         ctx = hier.ctx
         handle = C.c_void_p()
@@ -342,7 +342,7 @@ class Deflation:
             plam = lam.ctypes.data_as(C.POINTER(C.c_double))
         if level_b:
             st = lib().dmlmc_deflate_difference(ctx.h, hier.h, level, level_b, k, eig_rtol, solve_rtol, prec, pX, plam,
-                                                C.byref(handle), C.byref(tr))
+                                                corr_rtol, C.byref(handle), C.byref(tr))
         else:
             st = lib().dmlmc_deflate(ctx.h, hier.h, level, k, eig_rtol, pX, plam, C.byref(handle), C.byref(tr))
         self.level_b = level_b

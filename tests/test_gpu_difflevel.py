@@ -91,3 +91,31 @@ def test_deflated_and_skipped_samples(gpu, prec_name, rtol, tol, skip):
     for i in range(nsamp):
         s = omlmc.coarsest_sample(lv, solver, cref, W.noise_seed, i)
         assert abs(got[i] - s) / abs(s) < tol, (L, i)
+
+
+@pytest.mark.parametrize("prec_name,srtol,tol", [("fp64", 1e-13, 1e-10), ("mixed", 1e-12, 1e-6)])
+def test_inexact_difference_deflation(gpu, prec_name, srtol, tol):
+    """Approximate vectors with the evaluated small term Re sum x^H Gamma5 J x (inexact
+    deflation): imported perturbed vectors, and a loose device eigensolve (1e-1, solves to
+    1e-3) followed by the accurate small term; samples against the checker."""
+    torch, dm, ctx = gpu
+    prec = dm.FP64 if prec_name == "fp64" else dm.MIXED
+    W, lv, H = _gpu_hier(gpu, "rect24x16")
+    exact = dl.deflate_difference(lv, 1, 2, 4)
+    rng = np.random.default_rng(3)
+    Xp = np.linalg.qr(exact.X + 1e-2 * (rng.normal(size=exact.X.shape) + 1j * rng.normal(size=exact.X.shape)))[0]
+    ref = dl.inexact_deflation(lv, 1, 2, Xp, dense=True)
+    d = dm.Deflation(H, 1, 4, level_b=2, import_X=Xp, import_lambda=ref.lam, prec=prec, corr_rtol=srtol)
+    assert abs(d.tr_defl - ref.corr) < 10 * tol * abs(ref.corr), (d.tr_defl, ref.corr)
+    loose = dm.Deflation(H, 1, 4, eig_rtol=1e-1, level_b=2, solve_rtol=1e-3, prec=dm.MIXED, corr_rtol=1e-12)
+    X2, _ = loose.export()
+    ref2 = dl.inexact_deflation(lv, 1, 2, X2.T, dense=True)
+    assert abs(loose.tr_defl - ref2.corr) < 1e-7 * abs(ref2.corr)
+    L = len(lv)
+    nsamp = 8
+    res = dm.mlmc_trace(H, None, 1e-2, W.noise_seed, [nsamp] * L, 4, prec=prec, rtol=srtol if prec == dm.FP64 else 1e-10,
+                        fixed_counts=True, max_samples=[nsamp] * L, keep_samples=True, term_defl=[d] + [None] * (L - 1))
+    solver = omlmc.DirectSolver(lv)
+    for i in range(nsamp):
+        s, t1, t2 = dl.pair_sample(lv, solver, W.noise_seed, 1, 2, i, ref)
+        assert abs(res.samples[0][i] - s) / (abs(t1) + abs(t2)) < tol, (i, res.samples[0][i], s)

@@ -10,6 +10,8 @@ Through routes independent of the checker's formulas:
 * brute force over all 2^16 Z2 vectors: the deflated samples average to tr(M_ab (I - Pi))
   and their variance is eq. (2) on M_ab (I - Pi), which is below that of M_ab;
 * ARPACK on J as an operator agrees with dense eigh;
+* inexact deflation: for any orthonormal X the split holds with the evaluated small term
+  Re tr(M_ab V V^H) (dense trace) and reduces to the eigenpair formula for exact vectors;
 * skipping a level: the composite P_13 = P_1 P_2 maps level 3 to level 1, the split of
   eq. 12 telescopes to tr(D^-1) and the per-sample sum with coupled noise reproduces
   x^H D^-1 x.
@@ -123,3 +125,26 @@ def test_skip_level_split():
     y = P13.conj().T @ x
     total = t1 - t2 + np.vdot(y, solver.solve(3, y))
     assert abs(total - np.vdot(x, solver.solve(1, x))) < 1e-11 * abs(t1)
+
+
+def test_inexact_deflation_split():
+    lv = _rect()
+    a, b = 1, 2
+    M = dl.M_dense(lv, a, b)
+    n = M.shape[0]
+    rng = np.random.default_rng(3)
+    exact = dl.deflate_difference(lv, a, b, 4)
+    # approximate vectors: exact ones perturbed, re-orthonormalised
+    Xp = np.linalg.qr(exact.X + 1e-2 * (rng.normal(size=exact.X.shape) + 1j * rng.normal(size=exact.X.shape)))[0]
+    for X in (Xp, np.linalg.qr(rng.normal(size=(n, 3)) + 1j * rng.normal(size=(n, 3)))[0]):
+        d = dl.inexact_deflation(lv, a, b, X, dense=True)
+        Pi = d.V @ d.V.conj().T
+        small = np.trace(M @ Pi)
+        assert abs(d.corr - small.real) < 1e-10 * np.abs(M).sum()
+        assert abs(np.trace(M @ (np.eye(n) - Pi)) + small - np.trace(M)) < 1e-10 * np.abs(M).sum()
+        solver = mlmc.DirectSolver(lv)
+        ds = dl.inexact_deflation(lv, a, b, X, solver=solver)
+        assert abs(ds.corr - d.corr) < 1e-10 * abs(d.corr)
+    de = dl.inexact_deflation(lv, a, b, exact.X, dense=True)
+    assert abs(de.corr - exact.corr) < 1e-10 * abs(exact.corr)
+    assert np.abs(de.lam - exact.lam).max() < 1e-10 * np.abs(exact.lam).max()
