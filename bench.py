@@ -53,17 +53,20 @@ def source_digest(cls: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def recorded_traffic(cls: str):
+def recorded_traffic(cls: str, algorithmic_per_launch: float):
     """HBM bytes per launch of a kernel class from a committed rocprofv3 --pmc summary
     (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size), if it was measured on
-    the current source of that kernel; else (None, None)."""
+    the current source of that kernel and on the same launch mix (algorithmic bytes per
+    launch within 0.5 %); else (None, None)."""
     want = source_digest(cls)
-    pat = re.compile(r"^traffic: class=(\S+) source_sha256=(\S+) bytes_per_launch=(\S+)")
+    pat = re.compile(r"^traffic: class=(\S+) source_sha256=(\S+) bytes_per_launch=(\S+) "
+                     r"algorithmic_bytes_per_launch=(\S+)")
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
         with open(path) as f:
             for line in f:
                 m = pat.match(line.strip())
-                if m and m.group(1) == cls and m.group(2) == want:
+                if (m and m.group(1) == cls and m.group(2) == want
+                        and abs(float(m.group(4)) - algorithmic_per_launch) <= 5e-3 * algorithmic_per_launch):
                     return float(m.group(3)), os.path.basename(path)
     return None, None
 
@@ -226,6 +229,11 @@ def main():
     torch.cuda.synchronize()
     t_eig = time.perf_counter() - t0
     log(f"deflation k={W.k_defl} in {t_eig:.2f} s, tr_defl {D.tr_defl:.6f}, {D.info()}")
+    t0 = time.perf_counter()
+    H.coarsest_direct(D)  # explicit coarsest inverse for the complex-FP32 coarsest solves
+    torch.cuda.synchronize()
+    t_inv = time.perf_counter() - t0
+    log(f"coarsest inverse (n = {H.n(L)}) in {t_inv:.2f} s")
 
     n0 = [W.n0] * L
 
@@ -241,7 +249,7 @@ def main():
     ctx.timing(True)
     ctx.timing_reset()
     r = run(dmlmc.MIXED, W.rhs_block)
-    tb = timers(ctx, HBM_CLASSES + ("gs_fused", "defl_gemm"))
+    tb = timers(ctx, HBM_CLASSES + ("gs_fused", "defl_gemm", "coarse_direct"))
     ctx.timing(False)
     log(f"breakdown pass: {r.seconds:.3f} s (all kernel classes bracketed by events)")
     dom = max(HBM_CLASSES, key=lambda c: tb[c]["ms"])
@@ -288,12 +296,14 @@ def main():
     avg_ms = d["ms"] / max(1, d["launches"])
     avg_bytes = d["bytes"] / max(1, d["launches"])
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic, traffic_src = recorded_traffic(dom)
+    traffic, traffic_src = recorded_traffic(dom, avg_bytes)
     st_bytes = sum(tb[c]["bytes"] for c in STENCIL_CLASSES)
     st_ms = sum(tb[c]["ms"] for c in STENCIL_CLASSES)
     stencil_gbps = st_bytes / (st_ms * 1e-3) / 1e9 if st_ms > 0 else 0.0
     g = tb["defl_gemm"]
     gemm_tflops = g["bytes"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    cdm = tb["coarse_direct"]
+    direct_tflops = cdm["bytes"] / (cdm["ms"] * 1e-3) / 1e12 if cdm["ms"] > 0 else 0.0
 
     methods = None
     if args.methods:
@@ -324,9 +334,11 @@ def main():
         "dtype": "c64+f64",
         "data": "synthetic",
         "config": {"workload": f"{W.name}: {W.Lx}x{W.Lt} Wilson-Schwinger, 4 levels (4x4,4x4,2x2 aggregates, "
-                               f"8 tv/chirality), k={W.k_defl} coarsest deflation, eps={W.eps}, rtol={W.rtol}, "
+                               f"8 tv/chirality), k={W.k_defl} coarsest deflation, direct coarsest solve, "
+                               f"eps={W.eps}, rtol={W.rtol}, "
                                f"{W.n0} initial samples/level, RHS block {W.rhs_block}",
-                   "m0": m0, "setup_hierarchy_s": t_hier, "setup_eigensolve_s": t_eig},
+                   "m0": m0, "setup_hierarchy_s": t_hier, "setup_eigensolve_s": t_eig,
+                   "setup_coarsest_inverse_s": t_inv, "coarsest_solve": "explicit inverse (complex FP32)"},
         "fp64_single_rhs_s": fp64["seconds"] if fp64 else None,
         "speedup_vs_fp64": (fp64["seconds"] / t_mixed) if fp64 else None,
         "fp64_run": fp64,
@@ -339,6 +351,8 @@ def main():
         "stencil_hbm_GBps_in_estimate": stencil_gbps,
         "kernel_classes": tb,
         "defl_gemm_TFLOPs": gemm_tflops,
+        "coarse_direct_TFLOPs": direct_tflops,
+        "coarse_direct_frac_fp32_mfma": direct_tflops / FP32_MFMA_PEAK_TFLOPS,
         "copy_kernel_GBps": copy_gbps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,

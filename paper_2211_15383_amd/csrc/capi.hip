@@ -4,6 +4,7 @@
 #include <cstdio>
 
 #include "defl.h"
+#include "dense.h"
 #include "mlmc.h"
 #include "setup.h"
 #include "solver.h"
@@ -447,6 +448,26 @@ dmlmc_status dmlmc_deflate_difference(dmlmc_ctx* ctx, dmlmc_hier* h, int a, int 
     return conv;
   }
   return st;
+}
+
+dmlmc_status dmlmc_coarsest_direct(dmlmc_ctx* ctx, dmlmc_hier* h, const dmlmc_defl* coarsest, int enable) {
+  if (!ctx) return DMLMC_EINVAL;
+  return guarded(ctx, [&]() {
+    check_hier(ctx, h);
+    REQUIRE(enable == 0 || enable == 1, "enable must be 0 or 1");
+    if (coarsest) {
+      if (coarsest->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
+      REQUIRE(coarsest->kind == 0 && coarsest->level == (int)h->lv.size(), "deflation must be of the coarsest level");
+    }
+    if (!enable) {
+      h->coarse_direct_on = false;
+      h->coarse_dinv.release();
+      h->coarse_dinv_n = 0;
+      return;
+    }
+    if (h->coarse_dinv_n == 0) build_coarse_direct(h, coarsest);
+    h->coarse_direct_on = true;
+  });
 }
 
 dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx* ctx, dmlmc_hier* h, const dmlmc_defl* coarsest, const int* candidates,

@@ -197,6 +197,10 @@ struct dmlmc_hier {
   // on the rest); set for the duration of an estimate, or by dmlmc_set_deflation
   const dmlmc_defl* coarse_defl = nullptr;
   int tuned_block = 0;  // RHS block chosen by the autotuner (0: not tuned)
+  // explicit coarsest inverse (complex FP32 [n][n]) for the complex-FP32 coarsest solves
+  DevBuf coarse_dinv;
+  int64_t coarse_dinv_n = 0;
+  bool coarse_direct_on = false;
   // recorded FGMRES iterations (preconditioner + operator + Gram-Schmidt) of the
   // complex-FP32 cycles, keyed by everything their launches depend on
   bool use_graphs = true;

@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "defl.h"
+#include "dense.h"
 #include "solver.h"
 
 namespace {
@@ -217,6 +218,10 @@ void coarsest_gmres(dmlmc_hier* H, int l, const Cx<R>* b_in, Cx<R>* x, int nrhs)
   const Level& L = H->lv[l - 1];
   const int64_t n = L.n();
   const bool f32 = std::is_same<R, float>::value;
+  if (f32 && H->coarse_direct_on && H->coarse_dinv_n == n) {
+    apply_coarse_direct(H, (const c64*)b_in, (c64*)x, nrhs);
+    return;
+  }
   const dmlmc_defl* D = H->coarse_defl;
   const bool use_defl = D != nullptr && D->level == l;
   const int m = std::max(1, use_defl ? H->coarsest_iters_defl : H->coarsest_iters);

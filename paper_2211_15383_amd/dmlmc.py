@@ -28,6 +28,7 @@ EXPORTED = [
     "dmlmc_free_deflation", "dmlmc_deflation_info", "dmlmc_export_deflation", "dmlmc_solve_multi_rhs", "dmlmc_mlmc_trace",
     "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_set_solver_params",
     "dmlmc_get_solver_params", "dmlmc_timing_enable", "dmlmc_timing_select", "dmlmc_tune_rhs_block",
+    "dmlmc_coarsest_direct",
     "dmlmc_timing_reset", "dmlmc_timing_get",
 ]
 
@@ -101,6 +102,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_timing_enable": (i32, [vp, i32]),
         "dmlmc_timing_reset": (i32, [vp]),
         "dmlmc_timing_select": (i32, [vp, C.c_char_p]),
+        "dmlmc_coarsest_direct": (i32, [vp, vp, vp, i32]),
         "dmlmc_tune_rhs_block": (i32, [vp, vp, vp, C.POINTER(i32), i32, i32, dbl, C.c_uint64, C.POINTER(i32),
                                        C.POINTER(dbl)]),
         "dmlmc_timing_get": (i32, [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
@@ -314,6 +316,12 @@ class Hierarchy:
         self.ctx.check(lib().dmlmc_tune_rhs_block(self.ctx.h, self.h, defl.h if defl is not None else None, cand,
                                                   len(candidates), prec, rtol, noise_seed, C.byref(best), secs))
         return best.value, {c: secs[i] for i, c in enumerate(candidates)}
+
+    def coarsest_direct(self, defl: Optional["Deflation"] = None, enable: bool = True):
+        """Explicit-inverse coarsest solve on (computed on first use) or off (see
+        dmlmc_coarsest_direct)."""
+        self.ctx.check(lib().dmlmc_coarsest_direct(self.ctx.h, self.h, defl.h if defl is not None else None,
+                                                   1 if enable else 0))
 
     def set_deflation(self, d: Optional["Deflation"]):
         st = lib().dmlmc_set_deflation(self.h, d.h if d is not None else None)

@@ -1,5 +1,6 @@
 """Parity at the full 1024 x 1024 workload, in the launch configuration the benchmark
-times (four levels, 32 RHS per block, complex FP32 bulk inside FP64 refinement) (GPU).
+times (four levels, 32 RHS per block, complex FP32 bulk inside FP64 refinement, explicit
+coarsest inverse) (GPU).
 
 The checker cannot build the 1024^2 hierarchy (its test-vector setup needs direct
 solves with 2M unknowns), so at this size the comparisons are of two kinds:
@@ -34,6 +35,7 @@ def full(gpu):
     print(f"[fullsize] building {NAME} hierarchy and deflation", flush=True)
     H = dm.Hierarchy(ctx, theta, m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed)
     D = dm.Deflation(H, W.nlevels, W.k_defl, eig_rtol=1e-9)
+    H.coarsest_direct(D)  # as the benchmark runs it
     Dfine = ow.dirac_operator(theta, m0)
     return W, m0, H, D, Dfine
 

@@ -115,3 +115,43 @@ def test_sample_parity(gpu, name, prec_name, rtol, tol):
                 s = omlmc.coarsest_sample(lv, solver, ref, W.noise_seed, i)
                 scale = abs(s)
             assert abs(got[i] - s) / scale < tol, (l, i, got[i], s)
+
+
+def test_direct_coarsest_solve(gpu):
+    """Explicit-inverse coarsest solve: the V-cycle of the coarsest level is D_L^-1 to FP32
+    accuracy, solves still reach their FP64 tolerance (in a few iterations at the coarsest
+    level), and samples match the checker's."""
+    torch, dm, ctx = gpu
+    name = "schwinger128"
+    W, lv, H = _gpu_hier(gpu, name)
+    L = len(lv)
+    ref = oracle_deflation(name, W.k_defl)
+    d = dm.Deflation(H, L, W.k_defl, import_X=ref.X, import_lambda=ref.lam)
+    H.coarsest_direct(d)
+    D = lv[-1].D
+    n = D.shape[0]
+    b = random_vectors(n, 5, 77)
+    x = torch.empty((5, n), dtype=torch.complex64, device="cuda:0")
+    H.apply(dm.OP_VCYCLE, L, to_dev(torch, b, torch.complex64), x, dm.MIXED)
+    xs = spla.splu(D.tocsc()).solve(b)
+    assert rel_err(to_host(x), xs) < 1e-4
+    X, st = H.solve(L, to_dev(torch, b), prec=dm.MIXED, rtol=1e-10)
+    res = np.linalg.norm(b - D @ to_host(X), axis=0) / np.linalg.norm(b, axis=0)
+    assert res.max() <= 1e-10 * 1.0001 and st.iters <= 10, (res.max(), st.iters)
+    nsamp = 10
+    r = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [nsamp] * L, 5, prec=dm.MIXED, rtol=1e-10, fixed_counts=True,
+                      max_samples=[nsamp] * L, keep_samples=True)
+    solver = omlmc.DirectSolver(lv)
+    for l in range(1, L + 1):
+        for i in range(nsamp):
+            if l < L:
+                s, t1, t2 = omlmc.difference_sample(lv, solver, W.noise_seed, l, i)
+                scale = abs(t1) + abs(t2)
+            else:
+                s = omlmc.coarsest_sample(lv, solver, ref, W.noise_seed, i)
+                scale = abs(s)
+            assert abs(r.samples[l - 1][i] - s) / scale < 1e-6, (l, i)
+    H.coarsest_direct(enable=False)
+    X2, st2 = H.solve(L, to_dev(torch, b), prec=dm.MIXED, rtol=1e-10)
+    res2 = np.linalg.norm(b - D @ to_host(X2), axis=0) / np.linalg.norm(b, axis=0)
+    assert res2.max() <= 1e-10 * 1.0001
