@@ -27,12 +27,14 @@ sys.path.insert(0, ROOT)
 METRIC = "time to 1e-2 rel. trace error, mixed+batched vs FP64 (s); stencil HBM GB/s"
 HBM_PEAK_GBPS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-HBM_CLASSES = ("wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong", "gs_dots", "gs_update")
+HBM_CLASSES = ("wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong", "gs_dots", "gs_update",
+               "coarse_direct16")
 STENCIL_CLASSES = ("wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong")
 # source file of each timed kernel class (a recorded HBM traffic figure is only valid for the
 # source it was measured on)
 CLASS_SOURCE = {"wilson": "stencil.hip", "coarse": "stencil.hip", "sap": "stencil.hip", "coarse_gs": "stencil.hip",
-                "restrict": "stencil.hip", "prolong": "stencil.hip", "gs_dots": "gram.hip", "gs_update": "gram.hip"}
+                "restrict": "stencil.hip", "prolong": "stencil.hip", "gs_dots": "gram.hip", "gs_update": "gram.hip",
+                "coarse_direct16": "dense.hip"}
 
 
 def log(msg):
@@ -193,6 +195,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="schwinger1024")
+    ap.add_argument("--direct", choices=("fp16", "fp32", "off"), default="fp16",
+                    help="coarsest solve inside the complex-FP32 V-cycles: explicit inverse applied in "
+                         "FP16 or FP32, or the iterative deflated GMRES")
     ap.add_argument("--skip-fp64", action="store_true", help="skip the FP64 single-RHS baseline run")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU checker baseline")
     ap.add_argument("--cpu-workload", default="schwinger128")
@@ -230,10 +235,12 @@ def main():
     t_eig = time.perf_counter() - t0
     log(f"deflation k={W.k_defl} in {t_eig:.2f} s, tr_defl {D.tr_defl:.6f}, {D.info()}")
     t0 = time.perf_counter()
-    H.coarsest_direct(D)  # explicit coarsest inverse for the complex-FP32 coarsest solves
+    direct_mode = {"fp16": dmlmc.DIRECT_FP16, "fp32": dmlmc.DIRECT_FP32, "off": dmlmc.DIRECT_OFF}[args.direct]
+    if direct_mode != dmlmc.DIRECT_OFF:  # explicit coarsest inverse for the complex-FP32 coarsest solves
+        H.coarsest_direct(D, direct_mode)
     torch.cuda.synchronize()
     t_inv = time.perf_counter() - t0
-    log(f"coarsest inverse (n = {H.n(L)}) in {t_inv:.2f} s")
+    log(f"coarsest inverse (n = {H.n(L)}, {args.direct}) in {t_inv:.2f} s")
 
     n0 = [W.n0] * L
 
@@ -303,7 +310,9 @@ def main():
     g = tb["defl_gemm"]
     gemm_tflops = g["bytes"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     cdm = tb["coarse_direct"]
-    direct_tflops = cdm["bytes"] / (cdm["ms"] * 1e-3) / 1e12 if cdm["ms"] > 0 else 0.0
+    direct_tflops = cdm["bytes"] / (cdm["ms"] * 1e-3) / 1e12 if cdm["ms"] > 0 else None
+    c16 = tb["coarse_direct16"]
+    direct16_gbps = c16["bytes"] / (c16["ms"] * 1e-3) / 1e9 if c16["ms"] > 0 else None
 
     methods = None
     if args.methods:
@@ -320,6 +329,9 @@ def main():
                          f"checker's reach"}
         log(f"cpu baseline {sec:.2f} s")
 
+    coarsest = {"fp16": "explicit inverse applied in complex FP16 (FP32 accumulation)",
+                "fp32": "explicit inverse applied in complex FP32",
+                "off": "deflated fixed-count GMRES"}[args.direct]
     out = {
         "metric": METRIC,
         "value": t_mixed,
@@ -334,11 +346,11 @@ def main():
         "dtype": "c64+f64",
         "data": "synthetic",
         "config": {"workload": f"{W.name}: {W.Lx}x{W.Lt} Wilson-Schwinger, 4 levels (4x4,4x4,2x2 aggregates, "
-                               f"8 tv/chirality), k={W.k_defl} coarsest deflation, direct coarsest solve, "
+                               f"8 tv/chirality), k={W.k_defl} coarsest deflation, coarsest solve {coarsest}, "
                                f"eps={W.eps}, rtol={W.rtol}, "
                                f"{W.n0} initial samples/level, RHS block {W.rhs_block}",
                    "m0": m0, "setup_hierarchy_s": t_hier, "setup_eigensolve_s": t_eig,
-                   "setup_coarsest_inverse_s": t_inv, "coarsest_solve": "explicit inverse (complex FP32)"},
+                   "setup_coarsest_inverse_s": t_inv, "coarsest_solve": coarsest},
         "fp64_single_rhs_s": fp64["seconds"] if fp64 else None,
         "speedup_vs_fp64": (fp64["seconds"] / t_mixed) if fp64 else None,
         "fp64_run": fp64,
@@ -352,7 +364,9 @@ def main():
         "kernel_classes": tb,
         "defl_gemm_TFLOPs": gemm_tflops,
         "coarse_direct_TFLOPs": direct_tflops,
-        "coarse_direct_frac_fp32_mfma": direct_tflops / FP32_MFMA_PEAK_TFLOPS,
+        "coarse_direct_frac_fp32_mfma": direct_tflops / FP32_MFMA_PEAK_TFLOPS if direct_tflops else None,
+        "coarse_direct16_GBps": direct16_gbps,
+        "coarse_direct16_frac_hbm": direct16_gbps / HBM_PEAK_GBPS if direct16_gbps else None,
         "copy_kernel_GBps": copy_gbps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,

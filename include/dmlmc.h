@@ -247,16 +247,22 @@ dmlmc_status dmlmc_deflate_difference(dmlmc_ctx *ctx, dmlmc_hier *h, int a, int 
                                       double *corr_out);
 
 /* ---------------------------------------------------------------- direct coarsest solve
- * enable = 1: the complex-FP32 coarsest solves (inside every mixed-precision V-cycle, and
- * so the preconditioner of solves at the coarsest level) apply the explicit inverse
+ * enable = 1 or 2: the complex-FP32 coarsest solves (inside every mixed-precision V-cycle,
+ * and so the preconditioner of solves at the coarsest level) apply the explicit inverse
  * D_L^-1 instead of the fixed-count GMRES; the paper's coarsest level is likewise solved
  * directly.  The inverse is computed once, column by column from multi-RHS solves of
  * D_L X = I refined in FP64 to 1e-10 (coarsest, if given, deflates their V-cycles), and
- * kept in complex FP32: n_L^2 * 8 bytes (2.1 GB at n_L = 16384).  Every solve still stops
- * at its FP64 residual tolerance.  enable = 0 returns to the iterative coarsest solve and
- * frees the inverse.  Needs a coarse coarsest level with 16 dofs per site and
- * n_L <= 65536, n_L a multiple of 128 (EINVAL otherwise); ENOCONV if a column solve
- * fails.  The FP64 solver path is unaffected. */
+ * kept in complex FP32: n_L^2 * 8 bytes (2.1 GB at n_L = 16384).
+ *   enable = 1: applied in FP32 on the matrix cores (exact to FP32 rounding);
+ *   enable = 2: applied from a complex-FP16 copy (n_L^2 * 4 more bytes, made on first
+ *               use; one power-of-two scale for the matrix and one per RHS, FP32
+ *               accumulation): each coarsest solve is then accurate to ~1e-3 relative,
+ *               half the bytes and half the matrix-core instructions of enable = 1.
+ * Every solve still stops at its FP64 residual tolerance, so the precision changes
+ * iteration counts only.  enable = 0 returns to the iterative coarsest solve and frees
+ * both inverses.  Needs a coarse coarsest level with 16 dofs per site and
+ * n_L <= 65536, n_L a multiple of 256 (EINVAL otherwise); ENOCONV if a column solve
+ * fails, ENUMERIC if the inverse holds NaN/Inf.  The FP64 solver path is unaffected. */
 dmlmc_status dmlmc_coarsest_direct(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_defl *coarsest, int enable);
 
 /* ---------------------------------------------------------------- RHS block autotuner
@@ -330,9 +336,11 @@ dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p
  * When enabled, the library brackets every launch of the named kernel classes with HIP
  * events on the context stream and accumulates their durations.  Classes:
  * "wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong", "gs_dots", "gs_update",
- * "gs_fused" (the single-workgroup Arnoldi step of small levels), "defl_gemm", and
- * "coarse_direct" (the explicit-inverse coarsest solve; flops).  dmlmc_timing_get returns (launches, total milliseconds, bytes per
- * launch summed; flops for "defl_gemm") for a class.
+ * "gs_fused" (the single-workgroup Arnoldi step of small levels), "defl_gemm",
+ * "coarse_direct" (the FP32 explicit-inverse coarsest solve) and "coarse_direct16" (its
+ * FP16 form: RHS scaling, product and reduction as one timed unit).
+ * dmlmc_timing_get returns (launches, total milliseconds, work summed over launches) for
+ * a class: algorithmic bytes, except flops for "defl_gemm" and "coarse_direct".
  * dmlmc_timing_select restricts the bracketing to a comma-separated list of classes
  * (NULL or "" = every class), so that a timed run carries events only around the kernels
  * it measures.  Unknown names are accepted and simply never match. */

@@ -454,19 +454,21 @@ dmlmc_status dmlmc_coarsest_direct(dmlmc_ctx* ctx, dmlmc_hier* h, const dmlmc_de
   if (!ctx) return DMLMC_EINVAL;
   return guarded(ctx, [&]() {
     check_hier(ctx, h);
-    REQUIRE(enable == 0 || enable == 1, "enable must be 0 or 1");
+    REQUIRE(enable >= 0 && enable <= 2, "enable must be 0, 1 or 2");
     if (coarsest) {
       if (coarsest->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
       REQUIRE(coarsest->kind == 0 && coarsest->level == (int)h->lv.size(), "deflation must be of the coarsest level");
     }
     if (!enable) {
-      h->coarse_direct_on = false;
+      h->coarse_direct_mode = 0;
       h->coarse_dinv.release();
+      h->coarse_dinv16.release();
       h->coarse_dinv_n = 0;
       return;
     }
     if (h->coarse_dinv_n == 0) build_coarse_direct(h, coarsest);
-    h->coarse_direct_on = true;
+    if (enable == 2 && h->coarse_dinv16.p == nullptr) build_coarse_direct16(h);
+    h->coarse_direct_mode = enable;
   });
 }
 

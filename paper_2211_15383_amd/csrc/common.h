@@ -197,10 +197,14 @@ struct dmlmc_hier {
   // on the rest); set for the duration of an estimate, or by dmlmc_set_deflation
   const dmlmc_defl* coarse_defl = nullptr;
   int tuned_block = 0;  // RHS block chosen by the autotuner (0: not tuned)
-  // explicit coarsest inverse (complex FP32 [n][n]) for the complex-FP32 coarsest solves
+  // explicit coarsest inverse for the complex-FP32 coarsest solves: complex FP32 [n][n],
+  // and its complex-FP16 copy (scaled by 2^-e so that every component is below 1;
+  // coarse_dinv16_unscale = 2^e); mode 0 off, 1 FP32 inverse, 2 FP16 inverse
   DevBuf coarse_dinv;
+  DevBuf coarse_dinv16;
   int64_t coarse_dinv_n = 0;
-  bool coarse_direct_on = false;
+  float coarse_dinv16_unscale = 1.f;
+  int coarse_direct_mode = 0;
   // recorded FGMRES iterations (preconditioner + operator + Gram-Schmidt) of the
   // complex-FP32 cycles, keyed by everything their launches depend on
   bool use_graphs = true;

@@ -2,14 +2,29 @@
 //
 // Setup: the columns of D_L^-1 come from multi-RHS solves of D_L X = I (blocks of unit
 // vectors, FP64 refinement to 1e-10); the inverse is kept in complex FP32, row-major
-// [n][n].  Apply: Y = D_L^-1 B for a block of RHS on the matrix cores, the same operand
-// layout as the coarse stencil (lane (row, kq) takes the quads Dinv[i0 + row][j0 + 4kq ..]
-// and B[r0 + row][j0 + 4kq ..], and receives Y[r0 + row][i0 + 4kq + v]); the contraction
-// is split over KS waves whose partial tiles are summed by a second kernel in a fixed
-// order.  At n = 16384 and 32 RHS one apply is 69 GFLOP over a 2.1 GB operand: matrix-core
-// bound (~0.44 ms at the FP32 peak), comparable to the iterative coarsest solve it
-// replaces, and exact to FP32 rounding.
+// [n][n], and on request also in complex FP16 (one power-of-two scale for the whole
+// matrix, so that no component exceeds 1).
+//
+// FP32 apply: Y = D_L^-1 B for a block of RHS on the matrix cores, the same operand layout
+// as the coarse stencil (lane (row, kq) takes the quads Dinv[i0 + row][j0 + 4kq ..] and
+// B[r0 + row][j0 + 4kq ..], and receives Y[r0 + row][i0 + 4kq + v]); the contraction is
+// split over KS waves whose partial tiles are summed by a second kernel in a fixed order.
+// At n = 16384 and 32 RHS one apply is 69 GFLOP over a 2.1 GB operand: matrix-core bound
+// (~0.44 ms at the FP32 peak), exact to FP32 rounding.
+//
+// FP16 apply: the same product with v_mfma_f32_16x16x32_f16 (FP32 accumulation).  A
+// complex FP16 entry is one 32-bit word (real part in the low half); a lane's eight
+// consecutive words of a Dinv row are two K = 32 operands as stored, and the matching
+// RHS words become (re, -im) pairs for the real part and (im, re) pairs for the imaginary
+// part of the product, two instructions per complex product instead of four.  Each RHS is
+// first scaled by a power of two into [-1, 1] and rounded to FP16 (relative rounding
+// 2^-11); the reduction undoes both scales.  The operand is half the bytes and the
+// instruction count half of the FP32 form, so the apply is HBM-bound (1.07 GB at
+// n = 16384).  It is a preconditioner: every solve still stops at its FP64 tolerance.
 #include "dense.h"
+
+#include <cmath>
+
 #include "solver.h"
 
 namespace {
@@ -108,6 +123,142 @@ __global__ void dense_reduce_kernel(const c64* __restrict__ part, int KS, int64_
   Y[e] = cmk(sx, sy);
 }
 
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ half8 as_half8(u32x4 v) { return __builtin_bit_cast(half8, v); }
+
+__device__ __forceinline__ uint32_t pack_half2(float re, float im) {
+  const _Float16 a = (_Float16)re, b = (_Float16)im;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+// grid: (n / (16 TI) / 4 workgroups) x KS; wave (group, ks) accumulates the TI row tiles
+// Dinv[i0 + 16 t .. + 16) times B over columns [ks n / KS, (ks + 1) n / KS), 32 columns
+// per step: lane (row, g) holds words j0 + 32 q + 8 g .. + 7 of its Dinv rows and of its
+// RHS rows, as two K = 32 operands (words 0..3 and 4..7).
+template <int TI>
+__global__ __launch_bounds__(256) void dense16_apply_kernel(const uint32_t* __restrict__ Dinv,
+                                                            const uint32_t* __restrict__ B, c64* __restrict__ part,
+                                                            int64_t n, int nrhs, int KS) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t grp = (int64_t)blockIdx.x * 4 + w;
+  if (grp * 16 * TI >= n) return;  // wave-uniform
+  const int ks = blockIdx.y;
+  const int64_t i0 = grp * 16 * TI;
+  const int64_t kc = n / KS;
+  const int64_t j0 = ks * kc;
+  const int row = lane & 15, g = lane >> 4;
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  for (int r0 = 0; r0 < nrhs; r0 += 32) {
+    const int ra = r0 + row, rb = r0 + 16 + row;
+    const bool va = ra < nrhs, vb = rb < nrhs;
+    const u32x4* Ba = reinterpret_cast<const u32x4*>(B + (int64_t)min(ra, nrhs - 1) * n + j0 + 8 * g);
+    const u32x4* Bb = reinterpret_cast<const u32x4*>(B + (int64_t)min(rb, nrhs - 1) * n + j0 + 8 * g);
+    const u32x4* Ar[TI];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) Ar[t] = reinterpret_cast<const u32x4*>(Dinv + (i0 + 16 * t + row) * n + j0 + 8 * g);
+    f32x4 are[TI], aim[TI], bre[TI], bim[TI];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) are[t] = aim[t] = bre[t] = bim[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int steps = (int)(kc / 32);
+    for (int q = 0; q < steps; ++q) {
+      u32x4 xa[2], xb[2], a[TI][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        xa[u] = Ba[8 * q + u];
+        xb[u] = Bb[8 * q + u];
+#pragma unroll
+        for (int t = 0; t < TI; ++t) a[t][u] = Ar[t][8 * q + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        // rows beyond nrhs read a valid row and contribute zeros
+        const u32x4 pa = va ? xa[u] : zero, pb = vb ? xb[u] : zero;
+        const half8 a_re = as_half8(pa ^ 0x80000000u), a_im = as_half8((pa >> 16) | (pa << 16));
+        const half8 b_re = as_half8(pb ^ 0x80000000u), b_im = as_half8((pb >> 16) | (pb << 16));
+#pragma unroll
+        for (int t = 0; t < TI; ++t) {
+          const half8 m = as_half8(a[t][u]);
+          are[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(m, a_re, are[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(m, a_im, aim[t], 0, 0, 0);
+          bre[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(m, b_re, bre[t], 0, 0, 0);
+          bim[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(m, b_im, bim[t], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      c64* pa = part + ((int64_t)ks * nrhs + min(ra, nrhs - 1)) * n + i0 + 16 * t + 4 * g;
+      c64* pb = part + ((int64_t)ks * nrhs + min(rb, nrhs - 1)) * n + i0 + 16 * t + 4 * g;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (va) pa[v] = cmk(are[t][v], aim[t][v]);
+        if (vb) pb[v] = cmk(bre[t][v], bim[t][v]);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ float block_max_1024(float m, float* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  float r = 0.f;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = fmaxf(r, red[i]);
+  return r;
+}
+
+// one workgroup per RHS r: s = 2^-e with max |component| < 2^e, B16[r] = FP16(s B[r]),
+// rs[r] = unscale / s (s = 1 for a zero or non-finite RHS, whose NaN/Inf then propagate)
+__global__ __launch_bounds__(1024) void dense16_rhs_kernel(const c64* __restrict__ B, int64_t n, float unscale,
+                                                           uint32_t* __restrict__ B16, float* __restrict__ rs) {
+  __shared__ float red[16];
+  const int64_t r = blockIdx.x;
+  const c64* b = B + r * n;
+  float m = 0.f;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fmaxf(fabsf(b[i].x), fabsf(b[i].y)));
+  m = block_max_1024(m, red);
+  int e = 0;
+  if (m > 0.f && isfinite(m)) frexpf(m, &e);  // m = f 2^e, 0.5 <= f < 1
+  e = min(max(e, -100), 100);                 // scales stay normal FP32 numbers
+  const float s = ldexpf(1.f, -e);
+  if (threadIdx.x == 0) rs[r] = unscale * ldexpf(1.f, e);
+  uint32_t* o = B16 + r * n;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) o[i] = pack_half2(s * b[i].x, s * b[i].y);
+}
+
+__global__ void dense16_reduce_kernel(const c64* __restrict__ part, int KS, int64_t n, int64_t m,
+                                      const float* __restrict__ rs, c64* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  float sx = 0.f, sy = 0.f;
+  for (int k = 0; k < KS; ++k) {
+    const c64 v = part[(int64_t)k * m + e];
+    sx += v.x;
+    sy += v.y;
+  }
+  const float f = rs[e / n];
+  Y[e] = cmk(f * sx, f * sy);
+}
+
+// per-block maximum |component| of the FP32 inverse
+__global__ __launch_bounds__(1024) void absmax_partial_kernel(const c64* __restrict__ A, int64_t m,
+                                                              float* __restrict__ part) {
+  __shared__ float red[16];
+  float v = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    v = fmaxf(v, fmaxf(fabsf(A[i].x), fabsf(A[i].y)));
+  v = block_max_1024(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void to_half_kernel(const c64* __restrict__ A, int64_t m, float s, uint32_t* __restrict__ A16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    A16[i] = pack_half2(s * A[i].x, s * A[i].y);
+}
+
 // E[r][i] = 1 if i == c0 + r else 0 (unit vectors of columns c0 .. c0 + nb - 1)
 __global__ void unit_block_kernel(c128* __restrict__ E, int64_t n, int64_t c0, int nb) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -137,7 +288,9 @@ __global__ void store_columns_kernel(const c128* __restrict__ X, int64_t n, int6
 }
 
 constexpr int KSPLIT = 16;
-constexpr int TILES = 2;  // row tiles of 16 per wavefront
+constexpr int TILES = 2;     // row tiles of 16 per wavefront
+constexpr int KSPLIT16 = 4;  // FP16 form: contraction split and row tiles per wavefront
+constexpr int TILES16 = 4;
 
 }  // namespace
 
@@ -148,18 +301,19 @@ void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl) {
   const int64_t n = C.n();
   REQUIRE(!C.fine && C.dofs == 16, "the direct coarsest solve needs a coarse level with 16 dofs per site");
   REQUIRE(n <= 65536, "the coarsest level is too large for an explicit inverse (n > 65536)");
-  REQUIRE(n % (16 * KSPLIT) == 0 && n % (16 * TILES) == 0, "the coarsest dimension must be a multiple of 256");
+  REQUIRE(n % (16 * KSPLIT) == 0 && n % (16 * TILES) == 0 && n % (32 * KSPLIT16) == 0 && n % (16 * TILES16) == 0,
+          "the coarsest dimension must be a multiple of 256");
   struct Restore {
     dmlmc_hier* H;
     const dmlmc_defl* prev;
-    bool prevd;
+    int prevd;
     ~Restore() {
       H->coarse_defl = prev;
-      H->coarse_direct_on = prevd;
+      H->coarse_direct_mode = prevd;
     }
-  } restore{H, H->coarse_defl, H->coarse_direct_on};
+  } restore{H, H->coarse_defl, H->coarse_direct_mode};
   if (defl) H->coarse_defl = defl;
-  H->coarse_direct_on = false;  // the columns are computed with the iterative coarsest solve
+  H->coarse_direct_mode = 0;  // the columns are computed with the iterative coarsest solve
   H->coarse_dinv.alloc(sizeof(c64) * (size_t)n * n);
   constexpr int NB = 512;
   c128* E = (c128*)hier_buf(H, "cd_E", L, sizeof(c128) * (size_t)NB * n);
@@ -176,7 +330,38 @@ void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl) {
     LAUNCH_CHECK();
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  H->coarse_dinv16.release();
   H->coarse_dinv_n = n;
+}
+
+void build_coarse_direct16(dmlmc_hier* H) {
+  dmlmc_ctx* ctx = H->ctx;
+  const int64_t n = H->coarse_dinv_n;
+  REQUIRE(n > 0, "the FP32 coarsest inverse must be built first");
+  const int64_t m = n * n;
+  constexpr int NBLK = 1024;
+  DevBuf part;
+  part.alloc(sizeof(float) * NBLK);
+  hipLaunchKernelGGL(absmax_partial_kernel, dim3(NBLK), dim3(1024), 0, ctx->stream, H->coarse_dinv.as<c64>(), m,
+                     part.as<float>());
+  LAUNCH_CHECK();
+  std::vector<float> h(NBLK);
+  HIPCHK(hipMemcpyAsync(h.data(), part.p, sizeof(float) * NBLK, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  float amax = 0.f;
+  for (float v : h) {
+    if (!std::isfinite(v)) throw DmlmcError(DMLMC_ENUMERIC, "NaN/Inf in the coarsest inverse");
+    amax = std::max(amax, v);
+  }
+  int e = 0;
+  if (amax > 0.f) std::frexp(amax, &e);  // amax < 2^e
+  e = std::min(std::max(e, -100), 100);
+  H->coarse_dinv16.alloc(sizeof(uint32_t) * (size_t)m);
+  hipLaunchKernelGGL(to_half_kernel, dim3(8192), dim3(256), 0, ctx->stream, H->coarse_dinv.as<c64>(), m,
+                     std::ldexp(1.f, -e), H->coarse_dinv16.as<uint32_t>());
+  LAUNCH_CHECK();
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  H->coarse_dinv16_unscale = std::ldexp(1.f, e);
 }
 
 void apply_coarse_direct(dmlmc_hier* H, const c64* B, c64* Y, int nrhs) {
@@ -184,6 +369,24 @@ void apply_coarse_direct(dmlmc_hier* H, const c64* B, c64* Y, int nrhs) {
   const int64_t n = H->coarse_dinv_n;
   REQUIRE(((uintptr_t)B | (uintptr_t)Y) % 16 == 0, "direct coarsest solve needs 16-byte aligned vectors");
   const int64_t m = (int64_t)nrhs * n;
+  if (H->coarse_direct_mode == 2) {
+    REQUIRE(H->coarse_dinv16.p != nullptr, "the FP16 coarsest inverse is not built");
+    const int L = (int)H->lv.size();
+    uint32_t* B16 = (uint32_t*)hier_buf(H, "cd_B16", L, sizeof(uint32_t) * (size_t)m);
+    float* rs = (float*)hier_buf(H, "cd_rs", L, sizeof(float) * (size_t)nrhs);
+    c64* part = (c64*)hier_buf(H, "cd_part16", L, sizeof(c64) * (size_t)KSPLIT16 * m);
+    KTimer kt(ctx, "coarse_direct16", 4.0 * n * n + 16.0 * m);
+    hipLaunchKernelGGL(dense16_rhs_kernel, dim3((unsigned)nrhs), dim3(1024), 0, ctx->stream, B, n,
+                       H->coarse_dinv16_unscale, B16, rs);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(dense16_apply_kernel<TILES16>, dim3((unsigned)ceil_div(n / (16 * TILES16), 4), KSPLIT16),
+                       dim3(256), 0, ctx->stream, H->coarse_dinv16.as<uint32_t>(), B16, part, n, nrhs, KSPLIT16);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(dense16_reduce_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, ctx->stream, part,
+                       KSPLIT16, n, m, rs, Y);
+    LAUNCH_CHECK();
+    return;
+  }
   c64* part = (c64*)hier_buf(H, "cd_part", (int)H->lv.size(), sizeof(c64) * (size_t)KSPLIT * m);
   KTimer kt(ctx, "coarse_direct", 8.0 * n * n * nrhs);
   hipLaunchKernelGGL(dense_apply_kernel<TILES>, dim3((unsigned)ceil_div(n / (16 * TILES), 4), KSPLIT), dim3(256), 0,

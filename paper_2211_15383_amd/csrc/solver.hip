@@ -218,7 +218,7 @@ void coarsest_gmres(dmlmc_hier* H, int l, const Cx<R>* b_in, Cx<R>* x, int nrhs)
   const Level& L = H->lv[l - 1];
   const int64_t n = L.n();
   const bool f32 = std::is_same<R, float>::value;
-  if (f32 && H->coarse_direct_on && H->coarse_dinv_n == n) {
+  if (f32 && H->coarse_direct_mode != 0 && H->coarse_dinv_n == n) {
     apply_coarse_direct(H, (const c64*)b_in, (c64*)x, nrhs);
     return;
   }
@@ -356,7 +356,8 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, 
     Cx<RP>* zj = Z + j * vstride;
     if (f32) {
       const std::vector<int64_t> key = {l, nrhs, j, m, (int64_t)(uintptr_t)H->coarse_defl, H->coarsest_iters,
-                                        H->coarsest_iters_defl, H->nu_pre, H->nu_post, H->sap_mr_iters};
+                                        H->coarsest_iters_defl, H->nu_pre, H->nu_post, H->sap_mr_iters,
+                                        H->coarse_direct_mode};
       run_graphed(H, key, [&]() {
         launch_scale_vec(ctx, U + j * vstride, scale + (int64_t)j * nrhs, (c64*)vin, n, nrhs);
         vcycle<RP>(H, l, vin, zj, nrhs);

@@ -35,7 +35,7 @@ def full(gpu):
     print(f"[fullsize] building {NAME} hierarchy and deflation", flush=True)
     H = dm.Hierarchy(ctx, theta, m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed)
     D = dm.Deflation(H, W.nlevels, W.k_defl, eig_rtol=1e-9)
-    H.coarsest_direct(D)  # as the benchmark runs it
+    H.coarsest_direct(D, dm.DIRECT_FP16)  # as the benchmark runs it
     Dfine = ow.dirac_operator(theta, m0)
     return W, m0, H, D, Dfine
 

@@ -117,27 +117,30 @@ def test_sample_parity(gpu, name, prec_name, rtol, tol):
             assert abs(got[i] - s) / scale < tol, (l, i, got[i], s)
 
 
-def test_direct_coarsest_solve(gpu):
-    """Explicit-inverse coarsest solve: the V-cycle of the coarsest level is D_L^-1 to FP32
-    accuracy, solves still reach their FP64 tolerance (in a few iterations at the coarsest
-    level), and samples match the checker's."""
+@pytest.mark.parametrize("mode_name,vtol,maxit", [("fp32", 1e-4, 10), ("fp16", 5e-3, 16)])
+def test_direct_coarsest_solve(gpu, mode_name, vtol, maxit):
+    """Explicit-inverse coarsest solve, applied in complex FP32 or FP16: the V-cycle of the
+    coarsest level is D_L^-1 to that precision (FP16: 2^-11 rounding of the inverse and of
+    the scaled RHS, FP32 accumulation), solves still reach their FP64 tolerance (in a few
+    iterations at the coarsest level), and samples match the checker's."""
     torch, dm, ctx = gpu
+    mode = dm.DIRECT_FP32 if mode_name == "fp32" else dm.DIRECT_FP16
     name = "schwinger128"
     W, lv, H = _gpu_hier(gpu, name)
     L = len(lv)
     ref = oracle_deflation(name, W.k_defl)
     d = dm.Deflation(H, L, W.k_defl, import_X=ref.X, import_lambda=ref.lam)
-    H.coarsest_direct(d)
+    H.coarsest_direct(d, mode)
     D = lv[-1].D
     n = D.shape[0]
     b = random_vectors(n, 5, 77)
     x = torch.empty((5, n), dtype=torch.complex64, device="cuda:0")
     H.apply(dm.OP_VCYCLE, L, to_dev(torch, b, torch.complex64), x, dm.MIXED)
     xs = spla.splu(D.tocsc()).solve(b)
-    assert rel_err(to_host(x), xs) < 1e-4
+    assert rel_err(to_host(x), xs) < vtol
     X, st = H.solve(L, to_dev(torch, b), prec=dm.MIXED, rtol=1e-10)
     res = np.linalg.norm(b - D @ to_host(X), axis=0) / np.linalg.norm(b, axis=0)
-    assert res.max() <= 1e-10 * 1.0001 and st.iters <= 10, (res.max(), st.iters)
+    assert res.max() <= 1e-10 * 1.0001 and st.iters <= maxit, (res.max(), st.iters)
     nsamp = 10
     r = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [nsamp] * L, 5, prec=dm.MIXED, rtol=1e-10, fixed_counts=True,
                       max_samples=[nsamp] * L, keep_samples=True)
@@ -155,3 +158,40 @@ def test_direct_coarsest_solve(gpu):
     X2, st2 = H.solve(L, to_dev(torch, b), prec=dm.MIXED, rtol=1e-10)
     res2 = np.linalg.norm(b - D @ to_host(X2), axis=0) / np.linalg.norm(b, axis=0)
     assert res2.max() <= 1e-10 * 1.0001
+
+
+def test_direct_fp16_scaling_and_mode_switch(gpu):
+    """FP16 coarsest inverse: each RHS is scaled by its own power of two, so the relative
+    accuracy does not depend on its magnitude (1e-30 .. 1e30, where an unscaled FP16 copy
+    would flush to zero or overflow), a zero RHS gives zero, and the result is linear
+    in the RHS up to the rounding; switching FP16 -> FP32 -> FP16 reuses the inverses and
+    the V-cycles follow the current mode (recorded iterations are keyed by it)."""
+    torch, dm, ctx = gpu
+    name = "schwinger128"
+    W, lv, H = _gpu_hier(gpu, name)
+    L = len(lv)
+    ref = oracle_deflation(name, W.k_defl)
+    d = dm.Deflation(H, L, W.k_defl, import_X=ref.X, import_lambda=ref.lam)
+    D = lv[-1].D
+    n = D.shape[0]
+    b = random_vectors(n, 4, 78)
+    mags = np.array([1e-30, 1.0, 1e30, 0.0])
+    bs = b * mags[None, :]
+    xs = spla.splu(D.tocsc()).solve(b)
+    out = {}
+    for mode in (dm.DIRECT_FP16, dm.DIRECT_FP32, dm.DIRECT_FP16):
+        H.coarsest_direct(d, mode)
+        x = torch.empty((4, n), dtype=torch.complex64, device="cuda:0")
+        H.apply(dm.OP_VCYCLE, L, to_dev(torch, bs, torch.complex64), x, dm.MIXED)
+        xh = to_host(x)
+        assert np.all(xh[:, 3] == 0)
+        errs = [rel_err(xh[:, j] / mags[j], xs[:, j]) for j in range(3)]
+        assert max(errs) < (5e-3 if mode == dm.DIRECT_FP16 else 1e-4), (mode, errs)
+        out.setdefault(mode, []).append(xh)
+        X, st = H.solve(L, to_dev(torch, b), prec=dm.MIXED, rtol=1e-10)
+        res = np.linalg.norm(b - D @ to_host(X), axis=0) / np.linalg.norm(b, axis=0)
+        assert res.max() <= 1e-10 * 1.0001
+    # both FP16 passes ran the same kernels on the same inverse
+    assert np.array_equal(out[dm.DIRECT_FP16][0], out[dm.DIRECT_FP16][1])
+    assert not np.array_equal(out[dm.DIRECT_FP16][0], out[dm.DIRECT_FP32][0])
+    H.coarsest_direct(enable=False)
