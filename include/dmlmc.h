@@ -320,14 +320,15 @@ dmlmc_status dmlmc_set_deflation(dmlmc_hier *h, const dmlmc_defl *d);
 /* ---------------------------------------------------------------- solver parameters
  * Parameters of the solver that change iteration counts and speed but not the solution
  * (every solve still stops at its FP64 residual tolerance): SAP local minimal-residual
- * iterations, pre/post smoothing sweeps of the V-cycle, fixed GMRES iterations of the
- * coarsest solve without / with an attached coarsest deflation, the FGMRES restart
- * length (at most 31), and use_graphs: 1 (default) replays each complex-FP32 FGMRES
+ * iterations, pre/post smoothing sweeps of the V-cycle (nu_post on the fine level,
+ * nu_post_coarse on the coarse levels; every level must smooth at least once), fixed
+ * GMRES iterations of the coarsest solve without / with an attached coarsest deflation,
+ * the FGMRES restart length (at most 31), and use_graphs: 1 (default) replays each complex-FP32 FGMRES
  * iteration (preconditioner, operator, Gram-Schmidt) as a recorded HIP graph after its
  * first two runs with the same shapes, 0 launches every kernel directly (results are
  * bitwise the same).  Values < 0 keep the current setting. */
 typedef struct {
-  int sap_mr_iters, nu_pre, nu_post, coarsest_iters, coarsest_iters_defl, restart, use_graphs;
+  int sap_mr_iters, nu_pre, nu_post, coarsest_iters, coarsest_iters_defl, restart, use_graphs, nu_post_coarse;
 } dmlmc_solver_params;
 dmlmc_status dmlmc_set_solver_params(dmlmc_hier *h, const dmlmc_solver_params *p);
 dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p);

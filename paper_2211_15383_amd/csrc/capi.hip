@@ -506,12 +506,18 @@ dmlmc_status dmlmc_set_solver_params(dmlmc_hier* h, const dmlmc_solver_params* p
   const int maxb = gs_max_basis() - 1;
   if (!ok(p->sap_mr_iters, 0, 64) || !ok(p->nu_pre, 0, 16) || !ok(p->nu_post, 0, 16) ||
       !ok(p->coarsest_iters, 1, maxb) || !ok(p->coarsest_iters_defl, 1, maxb) || !ok(p->restart, 2, maxb) ||
-      !ok(p->use_graphs, 0, 1))
+      !ok(p->use_graphs, 0, 1) || !ok(p->nu_post_coarse, 0, 16))
     return DMLMC_EINVAL;
-  if (p->nu_pre == 0 && p->nu_post == 0) return DMLMC_EINVAL;
+  auto pick = [](int v, int cur) { return v >= 0 ? v : cur; };
+  const int nu_pre = pick(p->nu_pre, h->nu_pre);
+  const int nu_post = pick(p->nu_post, h->nu_post);
+  const int nu_post_coarse = pick(p->nu_post_coarse, h->nu_post_coarse);
+  // every level must smooth at least once per V-cycle
+  if (nu_pre == 0 && (nu_post == 0 || nu_post_coarse == 0)) return DMLMC_EINVAL;
+  h->nu_pre = nu_pre;
+  h->nu_post = nu_post;
+  h->nu_post_coarse = nu_post_coarse;
   if (p->sap_mr_iters >= 0) h->sap_mr_iters = p->sap_mr_iters;
-  if (p->nu_pre >= 0) h->nu_pre = p->nu_pre;
-  if (p->nu_post >= 0) h->nu_post = p->nu_post;
   if (p->coarsest_iters >= 0) h->coarsest_iters = p->coarsest_iters;
   if (p->coarsest_iters_defl >= 0) h->coarsest_iters_defl = p->coarsest_iters_defl;
   if (p->restart >= 0) h->restart = p->restart;
@@ -528,6 +534,7 @@ dmlmc_status dmlmc_get_solver_params(const dmlmc_hier* h, dmlmc_solver_params* p
   p->coarsest_iters_defl = h->coarsest_iters_defl;
   p->restart = h->restart;
   p->use_graphs = h->use_graphs ? 1 : 0;
+  p->nu_post_coarse = h->nu_post_coarse;
   return DMLMC_OK;
 }
 

@@ -218,7 +218,7 @@ struct dmlmc_hier {
   int coarsest_iters_defl = 8;
   // solver knobs (not part of the math; iteration counts only)
   int sap_mr_iters = 2;
-  int nu_pre = 0, nu_post = 3;
+  int nu_pre = 0, nu_post = 2, nu_post_coarse = 2;  // post-smoothing: fine level, coarse levels
   int coarsest_iters = 24;
   int restart = 16;
   std::vector<std::unique_ptr<Workspace>> ws;  // indexed by level-1

@@ -52,10 +52,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // acc[0..nv) summed over the 256-thread block into red[0..nv) (LDS); all threads return
 // after red is complete.
-__device__ void block_reduce(const double* acc, int nv, double* lds /* [4][NVMAX] */, double* red) {
+template <int NV>
+__device__ void block_reduce(const double (&acc)[NV], int nv, double* lds /* [4][NVMAX] */, double* red) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
-  for (int q = 0; q < NVMAX; ++q) {
+  for (int q = 0; q < NV; ++q) {
     if (q < nv) {
       const double v = wave_sum(acc[q]);
       if (l == 0) lds[w * NVMAX + q] = v;
@@ -148,7 +149,8 @@ __device__ void finish_pass(const Fin& f, int r, int nv, const double* red) {
 }
 
 // Block reduce, then either finish (one workgroup per RHS) or write partials.
-__device__ void reduce_or_partial(const double* acc, int nv, double* lds, double* red, double* __restrict__ part,
+template <int NV>
+__device__ void reduce_or_partial(const double (&acc)[NV], int nv, double* lds, double* red, double* __restrict__ part,
                                   const Fin& f, int r) {
   block_reduce(acc, nv, lds, red);
   if (gridDim.x == 1) {
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(256) void gs_update_store_kernel(Cx<RV>* __restrict
 }
 
 // ---------------------------------------------------------------- single-pass form kernels
-template <typename RW>
+template <typename RW, int NBT>
 __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U, int nb,
                                                        const Cx<RW>* __restrict__ w, int64_t n, int64_t vstride,
                                                        const double* __restrict__ wscale, double* __restrict__ part,
@@ -272,9 +274,9 @@ __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U
   __shared__ double red[NVMAX];
   const int r = blockIdx.y;
   const double ws = wscale ? wscale[r] : 1.0;
-  double acc[NVMAX];
+  double acc[2 * NBT];
 #pragma unroll
-  for (int q = 0; q < NVMAX; ++q) acc[q] = 0.0;
+  for (int q = 0; q < 2 * NBT; ++q) acc[q] = 0.0;
   // element pairs (n is even): 16-byte loads of the FP32 basis
   const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * n);
   const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * n);
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U
     const Pair<RW> bw = wr[p];
     const double b0x = ws * bw.a.x, b0y = ws * bw.a.y, b1x = ws * bw.b.x, b1y = ws * bw.b.y;
 #pragma unroll
-    for (int i = 0; i < NBMAX; ++i) {
+    for (int i = 0; i < NBT; ++i) {
       if (i < nb) {
         const Pair<float> u = Ur[i * vs + p];
         acc[2 * i] += (double)u.a.x * b0x + (double)u.a.y * b0y + (double)u.b.x * b1x + (double)u.b.y * b1y;
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U
   reduce_or_partial(acc, 2 * nb, lds, red, part, f, r);
 }
 
-template <typename RW>
+template <typename RW, int NBT>
 __global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, int nb, const Cx<RW>* __restrict__ w,
                                                          int64_t n, int64_t vstride, const c128* __restrict__ h,
                                                          int hld, const double* __restrict__ scale, int nrhs,
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, in
     const Pair<RW> bw = wr[p];
     double v0x = ws * bw.a.x, v0y = ws * bw.a.y, v1x = ws * bw.b.x, v1y = ws * bw.b.y;
 #pragma unroll
-    for (int i = 0; i < NBMAX; ++i) {
+    for (int i = 0; i < NBT; ++i) {
       if (i < nb) {
         const Pair<float> u = Ur[i * vs + p];
         const c128 hi = hs[i];
@@ -576,7 +578,19 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
   fa.scale = scale;
   {
     KTimer kt(ctx, "gs_dots", (double)nrhs * n * (nb * sizeof(c64) + sizeof(Cx<RW>)));
-    hipLaunchKernelGGL((gs1_dots_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale, part, fa);
+    // the basis count rounded up to 4, 8, 16 or 32 sizes the registers (and occupancy)
+    if (nb <= 4)
+      hipLaunchKernelGGL((gs1_dots_kernel<RW, 4>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale, part,
+                         fa);
+    else if (nb <= 8)
+      hipLaunchKernelGGL((gs1_dots_kernel<RW, 8>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale, part,
+                         fa);
+    else if (nb <= 16)
+      hipLaunchKernelGGL((gs1_dots_kernel<RW, 16>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale,
+                         part, fa);
+    else
+      hipLaunchKernelGGL((gs1_dots_kernel<RW, NBMAX>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale,
+                         part, fa);
     LAUNCH_CHECK();
     launch_partial_finish(ctx, part, G, 2 * nb, fa, nrhs);
   }
@@ -586,8 +600,18 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
   fb.scale = scale;
   {
     KTimer kt(ctx, "gs_update", (double)nrhs * n * ((nb + 1) * sizeof(c64) + sizeof(Cx<RW>)));
-    hipLaunchKernelGGL((gs1_update_kernel<RW>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, k.h1, k.hld,
-                       scale, nrhs, wscale, part, fb);
+#define GS1_UPDATE(NBT)                                                                                      \
+  hipLaunchKernelGGL((gs1_update_kernel<RW, NBT>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, k.h1, \
+                     k.hld, scale, nrhs, wscale, part, fb)
+    if (nb <= 4)
+      GS1_UPDATE(4);
+    else if (nb <= 8)
+      GS1_UPDATE(8);
+    else if (nb <= 16)
+      GS1_UPDATE(16);
+    else
+      GS1_UPDATE(NBMAX);
+#undef GS1_UPDATE
     LAUNCH_CHECK();
     launch_partial_finish(ctx, part, G, 1, fb, nrhs);
   }

@@ -311,7 +311,7 @@ void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs) {
   }
   vcycle<R>(H, l + 1, bc, xc, nrhs);
   launch_prolong<R>(ctx, L, xc, x, nrhs, H->nu_pre > 0);
-  smooth<R>(H, l, x, b, nrhs, H->nu_post);
+  smooth<R>(H, l, x, b, nrhs, L.fine ? H->nu_post : H->nu_post_coarse);
 }
 
 // ---------------------------------------------------------------- FGMRES cycle
@@ -356,7 +356,7 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, 
     Cx<RP>* zj = Z + j * vstride;
     if (f32) {
       const std::vector<int64_t> key = {l, nrhs, j, m, (int64_t)(uintptr_t)H->coarse_defl, H->coarsest_iters,
-                                        H->coarsest_iters_defl, H->nu_pre, H->nu_post, H->sap_mr_iters,
+                                        H->coarsest_iters_defl, H->nu_pre, H->nu_post, H->nu_post_coarse, H->sap_mr_iters,
                                         H->coarse_direct_mode};
       run_graphed(H, key, [&]() {
         launch_scale_vec(ctx, U + j * vstride, scale + (int64_t)j * nrhs, (c64*)vin, n, nrhs);

@@ -56,7 +56,8 @@ class SolveStats(C.Structure):
 
 class SolverParams(C.Structure):
     _fields_ = [("sap_mr_iters", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarsest_iters", C.c_int),
-                ("coarsest_iters_defl", C.c_int), ("restart", C.c_int), ("use_graphs", C.c_int)]
+                ("coarsest_iters_defl", C.c_int), ("restart", C.c_int), ("use_graphs", C.c_int),
+                ("nu_post_coarse", C.c_int)]
 
 
 class MLMCParams(C.Structure):
@@ -297,7 +298,7 @@ class Hierarchy:
 
     def solver_params(self, **kw):
         """Sets the given solver parameters (see dmlmc_solver_params); returns all of them."""
-        p = SolverParams(-1, -1, -1, -1, -1, -1, -1)
+        p = SolverParams(*([-1] * len(SolverParams._fields_)))
         for key, v in kw.items():
             setattr(p, key, int(v))
         st = lib().dmlmc_set_solver_params(self.h, C.byref(p))

@@ -61,3 +61,34 @@ def test_recorded_iterations_match_direct_launches(gpu):
         for l in range(L):
             assert np.array_equal(g.samples[l], direct.samples[l]), (rep, l)
         assert g.trace == direct.trace
+
+
+def test_smoothing_parameters(gpu):
+    """Fine and coarse post-smoothing counts are separate settings; a V-cycle that would
+    leave a level unsmoothed is rejected, and every setting still solves to tolerance
+    with the same samples up to the solve tolerance."""
+    torch, dm, ctx = gpu
+    name = "schwinger128"
+    W, m0, lv = oracle_hierarchy(name)
+    H = dm.Hierarchy(ctx, W.theta(), m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                     import_tv=[l.V for l in lv[:-1]])
+    p0 = H.solver_params()
+    assert p0["nu_pre"] == 0 and p0["nu_post"] >= 1 and p0["nu_post_coarse"] >= 1
+    with pytest.raises(dm.DmlmcError):
+        H.solver_params(nu_pre=0, nu_post_coarse=0)
+    with pytest.raises(dm.DmlmcError):
+        H.solver_params(nu_pre=0, nu_post=0)
+    assert H.solver_params() == p0  # a rejected call changes nothing
+    L = len(lv)
+    ref = oracle_deflation(name, W.k_defl)
+    d = dm.Deflation(H, L, W.k_defl, import_X=ref.X, import_lambda=ref.lam)
+    kw = dict(prec=dm.MIXED, rtol=W.rtol, fixed_counts=True, max_samples=[16] * L, keep_samples=True)
+    base = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [16] * L, 16, **kw)
+    for fine, coarse in ((1, 3), (3, 1), (2, 2)):
+        q = H.solver_params(nu_post=fine, nu_post_coarse=coarse)
+        assert (q["nu_post"], q["nu_post_coarse"]) == (fine, coarse)
+        r = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [16] * L, 16, **kw)
+        for l in range(L):
+            dev = np.max(np.abs(r.samples[l] - base.samples[l]))
+            assert dev <= 1e-7 * np.max(np.abs(base.samples[l])), (fine, coarse, l, dev)
+    H.solver_params(**p0)
