@@ -538,6 +538,67 @@ __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restric
   }
 }
 
+// FP64 form of the coarse stencil, d = 16, on v_mfma_f64_16x16x4f64 (K = 4, one value per
+// lane).  Its result fragment differs from the FP32 instruction's: lane (c, q) receives
+// D[q + 4v][c], v < 4.  So lane (row, kq) supplies block row p(row) = 4 (row % 4) + row / 4
+// of A (then D row kq + 4v is block row 4kq + v and a lane's four results are contiguous)
+// at columns 4kq + t (column-major FP64 blocks: for each t the wavefront's 16 rows read
+// one 256-byte column), and x[rhs row][4kq + t], for the four products t; two 16-RHS tiles
+// per pass share the block loads.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void cmfma64(f64x4& dre, f64x4& dim, c128 a, c128 x) {
+  dre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, x.x, dre, 0, 0, 0);
+  dre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, x.y, dre, 0, 0, 0);
+  dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, x.y, dim, 0, 0, 0);
+  dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, x.x, dim, 0, 0, 0);
+}
+
+template <bool G5>
+__global__ __launch_bounds__(256) void coarse16_f64_mfma_kernel(const c128* __restrict__ A,
+                                                                const c128* __restrict__ in, c128* __restrict__ out,
+                                                                int Lx, int Lt, int nrhs, int64_t ldx, int64_t ldy) {
+  const int64_t V = (int64_t)Lx * Lt;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t s = xcd_block() * 4 + w;
+  if (s >= V) return;  // wave-uniform
+  const int row = lane & 15, kq = lane >> 4;
+  const int prow = 4 * (row & 3) + (row >> 2);
+  const Nbr nb = neighbours(s, Lx, Lt);
+  const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
+  const double sg = (G5 && kq >= 2) ? -1.0 : 1.0;
+  const c128 zero = cmk(0.0, 0.0);
+  for (int r0 = 0; r0 < nrhs; r0 += 32) {
+    const int ra = r0 + row, rb = r0 + 16 + row;
+    const bool va = ra < nrhs, vb = rb < nrhs;
+    const int64_t oa = (int64_t)min(ra, nrhs - 1) * ldx + 4 * kq, ob = (int64_t)min(rb, nrhs - 1) * ldx + 4 * kq;
+    f64x4 are = {0.0, 0.0, 0.0, 0.0}, aim = are, bre = are, bim = are;
+#pragma unroll
+    for (int dir = 0; dir < 5; ++dir) {
+      const c128* Ab = A + (s * 5 + dir) * 256 + 64 * kq + prow;
+      const c128* xa = in + oa + sites[dir] * 16;
+      const c128* xb = in + ob + sites[dir] * 16;
+      c128 a[4], u[4], v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = Ab[16 * t];
+        u[t] = xa[t];
+        v[t] = xb[t];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        cmfma64(are, aim, a[t], va ? u[t] : zero);
+        cmfma64(bre, bim, a[t], vb ? v[t] : zero);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (va) out[(int64_t)ra * ldy + s * 16 + 4 * kq + q] = cmk(sg * are[q], sg * aim[q]);
+      if (vb) out[(int64_t)rb * ldy + s * 16 + 4 * kq + q] = cmk(sg * bre[q], sg * bim[q]);
+    }
+  }
+}
+
 // Red/black point-block Gauss-Seidel, d = 16, on the sites of one colour:
 // x_s = A_ss^-1 (b_s - sum_{dir != self} A[s][dir] x_{s+dir}); the neighbours all have the
 // other colour (even extents), so the sweep over one colour is order-independent.  The
@@ -820,6 +881,19 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
     else
       hipLaunchKernelGGL((coarse16_mfma_kernel<false>), grid, dim3(256), 0, ctx->stream, (const c64*)A, (const c64*)x,
                          (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    LAUNCH_CHECK();
+    return;
+  }
+  if (std::is_same<R, double>::value && d == 16 && nrhs >= 8) {
+    // FP64 matrix cores pay from a few RHS on (a 16-wide tile); single vectors keep the
+    // scalar kernel
+    dim3 grid((unsigned)ceil_div(V, 4));
+    if (gamma5_left)
+      hipLaunchKernelGGL((coarse16_f64_mfma_kernel<true>), grid, dim3(256), 0, ctx->stream, (const c128*)A,
+                         (const c128*)x, (c128*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    else
+      hipLaunchKernelGGL((coarse16_f64_mfma_kernel<false>), grid, dim3(256), 0, ctx->stream, (const c128*)A,
+                         (const c128*)x, (c128*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
     LAUNCH_CHECK();
     return;
   }
