@@ -409,9 +409,10 @@ void build_levels(dmlmc_hier* H, const std::vector<const c128*>& import_tv) {
       std::unique_ptr<dmlmc_hier> prov;
       for (int step = 0; step < H->n_inv; ++step) {
         // provisional hierarchy: from smoothed start vectors first, then from the
-        // current vectors (the solves are exact, so this changes only the work)
+        // current vectors (the solves are exact, so this changes only the work); the
+        // solves run complex-FP32 cycles inside FP64 refinement to the FP64 tolerance
         prov = provisional(H, l, step == 0 ? nullptr : V.as<c128>(), 4);
-        SolveResult r = solve_level(prov.get(), 1, V.as<c128>(), X.as<c128>(), N, DMLMC_FP64, 1e-12, 5000);
+        SolveResult r = solve_level(prov.get(), 1, V.as<c128>(), X.as<c128>(), N, DMLMC_MIXED, 1e-12, 5000);
         if (!r.converged) throw DmlmcError(DMLMC_ENOCONV, "setup solve did not reach 1e-12 at level " + std::to_string(l));
         HIPCHK(hipMemcpyAsync(V.p, X.p, V.bytes, hipMemcpyDeviceToDevice, ctx->stream));
         orthonormalise(H, V.as<c128>(), N, n);
