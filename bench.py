@@ -122,11 +122,12 @@ def kernel_rates(torch, dm, ctx, H, nlev: int, b: int, reps: int = 10):
     return out
 
 
-def method_comparison(torch, dm, ctx, name: str, eps: float, kdiff: int):
+def method_comparison(torch, dm, ctx, name: str, eps: float, kdiff: int, hutch_k=()):
     """The variants of the paper's Table 1 on one synthetic workload (mixed precision,
     coarsest term always deflated): plain MGMLMC; level 2 skipped (eq. 12); and each of
     those with the first difference term exactly deflated by its kdiff largest singular
-    triplets (Sec. 4.2).  Returns setup and estimate seconds per variant."""
+    triplets (Sec. 4.2); then plain Hutchinson at the fine level deflated by each k in
+    hutch_k (eqs. 4-7).  Returns setup and estimate seconds per variant."""
     from paper_2211_15383_amd.inputs import WORKLOADS, load_m0
 
     W = WORKLOADS[name]
@@ -161,6 +162,25 @@ def method_comparison(torch, dm, ctx, name: str, eps: float, kdiff: int):
                                       "rel_err": r.rel_err, "N": r.N, "var": r.var}
             log(f"method {label}: {te:.3f} s (+{td:.2f} s eigensolve) trace {r.trace:.4f} rel_err "
                 f"{r.rel_err:.2e} N {r.N}")
+    # plain Hutchinson at the fine level with exact deflation (Table 1's comparison rows)
+    for kf in hutch_k:
+        log(f"method hutchinson_exact_k{kf}: fine-level eigensolve")
+        t0 = time.perf_counter()
+        Df = dm.Deflation(H, 1, kf, eig_rtol=1e-9)
+        tf = time.perf_counter() - t0
+        kw = dict(prec=dm.MIXED, rtol=W.rtol, max_samples=1 << 15, coarsest=Dc)
+        dm.hutchinson_trace(H, Df, eps, W.noise_seed, W.n0, W.rhs_block, **kw)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = dm.hutchinson_trace(H, Df, eps, W.noise_seed, W.n0, W.rhs_block, **kw)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t0
+        label = f"hutchinson_exact_k{kf}"
+        out["variants"][label] = {"trace_s": te, "fine_eigensolve_s": tf, "trace": r.trace, "rel_err": r.rel_err,
+                                  "N": r.N, "var": r.var, "tr_defl": r.tr_defl}
+        log(f"method {label}: {te:.3f} s (+{tf:.2f} s eigensolve) trace {r.trace:.4f} rel_err {r.rel_err:.2e} "
+            f"N {r.N}")
+        Df.close()
     H.set_deflation(None)
     return out
 
@@ -207,6 +227,8 @@ def main():
                     help="also time plain / skipped-level / difference-deflated MGMLMC on WORKLOAD")
     ap.add_argument("--methods-eps", type=float, default=1e-3)
     ap.add_argument("--methods-k", type=int, default=8)
+    ap.add_argument("--methods-hutch-k", default="", help="comma-separated fine-level deflation sizes for the "
+                    "deflated plain Hutchinson rows of --methods")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the estimator's samples would shard across GPUs with one "
@@ -316,7 +338,8 @@ def main():
 
     methods = None
     if args.methods:
-        methods = method_comparison(torch, dmlmc, ctx, args.methods, args.methods_eps, args.methods_k)
+        hk = tuple(int(v) for v in args.methods_hutch_k.split(",") if v.strip())
+        methods = method_comparison(torch, dmlmc, ctx, args.methods, args.methods_eps, args.methods_k, hk)
 
     cpu = None
     if not args.skip_cpu:

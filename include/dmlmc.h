@@ -220,6 +220,23 @@ typedef struct {
 dmlmc_status dmlmc_mlmc_trace(dmlmc_ctx *ctx, const dmlmc_hier *h, const dmlmc_defl *coarsest,
                               const dmlmc_mlmc_params *p, dmlmc_trace_result *out);
 
+/* ---------------------------------------------------------------- deflated Hutchinson
+ * Plain (single-level) Hutchinson estimate of tr(D^-1) at the fine level (Sec. 1, eq. 1)
+ * with exact deflation (Sec. 2, eqs. 4-7; the comparison method of Table 1): samples
+ * s = x^H D_1^-1 (x - W W^H x), x the Z2 vector of sample i of level 1 (the noise stream
+ * of the multilevel estimator's first level), W from fine = dmlmc_deflate at level 1
+ * (k up to n_1 / 4), or fine = NULL for no deflation.  Estimate Re(mean) + tr_defl(fine),
+ * relative error sqrt(var / N) / |estimate|; N starts at n0[0] (rounded up to the RHS
+ * block) and grows to ceil(var / (eps T)^2) until the error is <= eps, unless
+ * fixed_counts.  The solves use the hierarchy's V-cycles; coarsest (NULL allowed) is
+ * attached to their coarsest solve for the call (for a one-level hierarchy, fine is).
+ * p as for dmlmc_mlmc_trace with only index 0 of n0, max_samples and samples_out used;
+ * skip and term_defl must be zero.  out: index 0 of the per-level arrays.
+ * Errors: EINVAL, ESTATE, ENOCONV. */
+dmlmc_status dmlmc_hutchinson_trace(dmlmc_ctx *ctx, const dmlmc_hier *h, const dmlmc_defl *fine,
+                                    const dmlmc_defl *coarsest, const dmlmc_mlmc_params *p,
+                                    dmlmc_trace_result *out);
+
 /* ---------------------------------------------------------------- difference-level deflation
  * Exact deflation of the term (a, b) of the telescoping sum (Sec. 4.2):
  * M_ab = D_a^-1 - P_ab D_b^-1 P_ab^H with P_ab = P_a ... P_{b-1} (b = a + 1, or further

@@ -89,6 +89,20 @@ def coarsest_sample(levels, solver: DirectSolver, defl: Optional[Deflation], see
     return complex(coarsest_term(levels, solver, defl, x))
 
 
+def hutchinson_term(levels, solver: DirectSolver, defl: Optional[Deflation], x: np.ndarray):
+    """Plain Hutchinson at the fine level with exact deflation (eq. 1 with the split of
+    eq. 5 applied to D_1): x^H D_1^-1 (x - W W^H x), W from a deflation of level 1; x may
+    hold one noise vector per column."""
+    xt = x if defl is None else x - defl.W @ (defl.W.conj().T @ x)
+    return np.sum(x.conj() * solver.solve(1, xt), axis=0)
+
+
+def hutchinson_sample(levels, solver: DirectSolver, defl: Optional[Deflation], seed: int, i: int):
+    """Sample i of the deflated fine-level Hutchinson estimator; its noise is that of level 1."""
+    x = noise.z2_noise(seed, 1, i, levels[0].n)
+    return complex(hutchinson_term(levels, solver, defl, x))
+
+
 def sample_values(levels, solver: DirectSolver, defl: Optional[Deflation], seed: int, l: int,
                   ids) -> np.ndarray:
     L = len(levels)

@@ -402,6 +402,36 @@ dmlmc_status dmlmc_mlmc_trace(dmlmc_ctx* ctx, const dmlmc_hier* h, const dmlmc_d
   });
 }
 
+dmlmc_status dmlmc_hutchinson_trace(dmlmc_ctx* ctx, const dmlmc_hier* h, const dmlmc_defl* fine,
+                                    const dmlmc_defl* coarsest, const dmlmc_mlmc_params* p, dmlmc_trace_result* out) {
+  if (!ctx) return DMLMC_EINVAL;
+  return guarded(ctx, [&]() {
+    check_hier(ctx, h);
+    REQUIRE(p != nullptr && out != nullptr, "NULL pointer");
+    const int L = (int)h->lv.size();
+    REQUIRE(p->rhs_block >= 0 && p->rhs_block <= 512, "rhs_block must be in 0..512 (0: tuned)");
+    REQUIRE(p->eps > 0.0 || p->fixed_counts, "eps must be positive");
+    REQUIRE(p->rtol > 0.0, "rtol must be positive");
+    REQUIRE(p->prec == DMLMC_FP64 || p->prec == DMLMC_MIXED, "unknown precision");
+    REQUIRE(p->n0[0] >= 1, "n0[0] must be >= 1");
+    REQUIRE(!p->samples_out[0] || p->max_samples[0] >= 1, "samples_out needs max_samples");
+    for (int l = 0; l < 8; ++l) {
+      REQUIRE(!p->skip[l] && !p->term_defl[l], "skip and term_defl do not apply to the single-level estimator");
+      REQUIRE(l == 0 || !p->samples_out[l], "only samples_out[0] applies to the single-level estimator");
+    }
+    if (fine) {
+      if (fine->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
+      REQUIRE(fine->kind == 0 && fine->level == 1, "fine must be a deflation of level 1 (dmlmc_deflate)");
+    }
+    if (coarsest) {
+      if (coarsest->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
+      REQUIRE(coarsest->level == L && coarsest->kind == 0, "deflation must be of the coarsest level");
+    }
+    std::memset(out, 0, sizeof(*out));
+    run_hutchinson(const_cast<dmlmc_hier*>(h), fine, coarsest, p, out);
+  });
+}
+
 dmlmc_status dmlmc_deflate_difference(dmlmc_ctx* ctx, dmlmc_hier* h, int a, int b, int k, double eig_rtol,
                                       double solve_rtol, dmlmc_precision prec, const void* import_X,
                                       const double* import_lambda, double corr_rtol, dmlmc_defl** out,

@@ -26,6 +26,29 @@ double now_s() {
 
 }  // namespace
 
+// Samples x^H D_l^-1 (x - W W^H x) of the Z2 block X [b][n_l] (W of `defl`, a deflation
+// of level l, or none), appended to out: the coarsest term of eq. 11 (l = L) and the
+// plain deflated Hutchinson estimator at the fine level (l = 1).
+static int deflated_block(dmlmc_hier* H, const dmlmc_defl* defl, int l, const c128* X, int b,
+                          const dmlmc_mlmc_params* p, std::vector<std::complex<double>>& out) {
+  dmlmc_ctx* ctx = H->ctx;
+  const int64_t n = H->lv[l - 1].n();
+  const int maxit = p->maxiter > 0 ? p->maxiter : 2000;
+  c128* Z = (c128*)hier_buf(H, "ml_Z", l, sizeof(c128) * (size_t)b * n);
+  c128* s1 = (c128*)hier_buf(H, "ml_s1", l, sizeof(c128) * b);
+  c128* Xt = (c128*)hier_buf(H, "ml_Xt", l, sizeof(c128) * (size_t)b * n);
+  HIPCHK(hipMemcpyAsync(Xt, X, sizeof(c128) * (size_t)b * n, hipMemcpyDeviceToDevice, ctx->stream));
+  if (defl) defl_apply(H, defl, Xt, b, n, p->prec);
+  SolveResult r = solve_level(H, l, Xt, Z, b, p->prec, p->rtol, maxit);
+  if (!r.converged) throw DmlmcError(DMLMC_ENOCONV, "sample solve did not converge at level " + std::to_string(l));
+  launch_dots<double, double>(ctx, X, Z, n, b, n, n, s1);
+  std::vector<c128> h1(b);
+  HIPCHK(hipMemcpyAsync(h1.data(), s1, sizeof(c128) * b, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int q = 0; q < b; ++q) out.emplace_back(h1[q].x, h1[q].y);
+  return r.iters;
+}
+
 // Sample values of indices [i0, i0 + b) of the term that starts at level l, appended to
 // out.  l < L: the difference term (l, lb) with lb the next level kept (l + 1, or further
 // when levels are skipped, eq. 12), deflated by tdefl when given (Sec. 4.2); l = L: the
@@ -82,17 +105,7 @@ static int sample_block(dmlmc_hier* H, const dmlmc_defl* defl, int l, int64_t i0
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int q = 0; q < b; ++q) out.emplace_back(h1[q].x - h2[q].x, h1[q].y - h2[q].y);
   } else {
-    c128* Xt = (c128*)hier_buf(H, "ml_Xt", l, sizeof(c128) * (size_t)b * n);
-    HIPCHK(hipMemcpyAsync(Xt, X, sizeof(c128) * (size_t)b * n, hipMemcpyDeviceToDevice, ctx->stream));
-    if (defl) defl_apply(H, defl, Xt, b, n, p->prec);
-    SolveResult r = solve_level(H, l, Xt, Z, b, p->prec, p->rtol, maxit);
-    if (!r.converged) throw DmlmcError(DMLMC_ENOCONV, "sample solve did not converge at the coarsest level");
-    iters = r.iters;
-    launch_dots<double, double>(ctx, X, Z, n, b, n, n, s1);
-    std::vector<c128> h1(b);
-    HIPCHK(hipMemcpyAsync(h1.data(), s1, sizeof(c128) * b, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (int q = 0; q < b; ++q) out.emplace_back(h1[q].x, h1[q].y);
+    iters = deflated_block(H, defl, l, X, b, p, out);
   }
   return iters;
 }
@@ -248,4 +261,76 @@ int tune_rhs_block(dmlmc_hier* H, const dmlmc_defl* defl, const int* cand, int n
   }
   H->tuned_block = best;
   return best;
+}
+
+void run_hutchinson(dmlmc_hier* H, const dmlmc_defl* fine, const dmlmc_defl* coarsest, const dmlmc_mlmc_params* p,
+                    dmlmc_trace_result* res) {
+  const int L = (int)H->lv.size();
+  struct Restore {
+    dmlmc_hier* H;
+    const dmlmc_defl* prev;
+    ~Restore() { H->coarse_defl = prev; }
+  } restore{H, H->coarse_defl};
+  // the V-cycles' coarsest solve: the given coarsest deflation (for a one-level hierarchy
+  // the fine deflation is that of the coarsest level)
+  if (coarsest)
+    H->coarse_defl = coarsest;
+  else if (L == 1 && fine)
+    H->coarse_defl = fine;
+  const int blk = p->rhs_block > 0 ? p->rhs_block : H->tuned_block;
+  if (blk < 1) throw DmlmcError(DMLMC_ESTATE, "rhs_block = 0 but the hierarchy has no tuned block size");
+  const double t0 = now_s();
+  auto roundup = [&](int64_t m) { return ((m + blk - 1) / blk) * blk; };
+  const int64_t n = H->lv[0].n();
+  const int64_t cap = p->max_samples[0] > 0 ? p->max_samples[0] : ((int64_t)1 << 40);
+  int64_t target = roundup(std::max(1, p->n0[0]));
+  const double tr_defl = fine ? fine->tr_defl : 0.0;
+  std::vector<std::complex<double>> S;
+  int64_t iters = 0;
+  double T = 0.0, Ti = 0.0, err = INFINITY, var = 0.0, level_time = 0.0;
+  std::complex<double> mean(0.0, 0.0);
+  while (true) {
+    while ((int64_t)S.size() < std::min(target, cap)) {
+      const int64_t i0 = (int64_t)S.size();
+      const int b = (int)std::min<int64_t>(blk, std::min(target, cap) - i0);
+      const double ts = now_s();
+      c128* X = (c128*)hier_buf(H, "ml_X", 1, sizeof(c128) * (size_t)b * n);
+      launch_z2<double>(H->ctx, X, n, p->noise_seed, 1, i0, b, n);
+      iters += deflated_block(H, fine, 1, X, b, p, S);
+      level_time += now_s() - ts;
+    }
+    mean = std::complex<double>(0.0, 0.0);
+    for (auto v : S) mean += v;
+    mean /= (double)S.size();
+    double v2 = 0.0;
+    for (auto v : S) v2 += std::norm(v - mean);
+    var = S.size() > 1 ? v2 / (double)(S.size() - 1) : 0.0;
+    T = tr_defl + mean.real();
+    Ti = mean.imag();
+    err = T != 0.0 ? std::sqrt(var / (double)S.size()) / std::fabs(T) : INFINITY;
+    if (p->fixed_counts || err <= p->eps) break;
+    // one level: N = V / (eps T)^2, the multilevel rule with a single term
+    const double want = std::ceil(var / (p->eps * p->eps * T * T));
+    const int64_t t = std::min(roundup(std::max<int64_t>((int64_t)want, (int64_t)S.size())), cap);
+    if (t <= (int64_t)S.size()) break;
+    target = t;
+  }
+  res->trace = T;
+  res->trace_imag = Ti;
+  res->rel_err = err;
+  res->tr_defl = tr_defl;
+  res->N[0] = (int64_t)S.size();
+  res->mean_re[0] = mean.real();
+  res->mean_im[0] = mean.imag();
+  res->var[0] = var;
+  res->cost_s[0] = level_time;
+  res->iters[0] = iters;
+  if (p->samples_out[0]) {
+    const int64_t m = std::min<int64_t>((int64_t)S.size(), p->max_samples[0]);
+    for (int64_t i = 0; i < m; ++i) {
+      p->samples_out[0][2 * i] = S[i].real();
+      p->samples_out[0][2 * i + 1] = S[i].imag();
+    }
+  }
+  res->t_trace_s = now_s() - t0;
 }

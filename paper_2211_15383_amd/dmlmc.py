@@ -27,6 +27,7 @@ EXPORTED = [
     "dmlmc_create", "dmlmc_destroy", "dmlmc_last_error", "dmlmc_version", "dmlmc_build_hierarchy",
     "dmlmc_free_hierarchy", "dmlmc_level_info", "dmlmc_export_level", "dmlmc_deflate", "dmlmc_deflate_difference",
     "dmlmc_free_deflation", "dmlmc_deflation_info", "dmlmc_export_deflation", "dmlmc_solve_multi_rhs", "dmlmc_mlmc_trace",
+    "dmlmc_hutchinson_trace",
     "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_set_solver_params",
     "dmlmc_get_solver_params", "dmlmc_timing_enable", "dmlmc_timing_select", "dmlmc_tune_rhs_block",
     "dmlmc_coarsest_direct",
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_export_deflation": (i32, [vp, vp, vp, C.POINTER(dbl)]),
         "dmlmc_solve_multi_rhs": (i32, [vp, vp, i32, vp, vp, vp, i32, i64, i32, dbl, i32, C.POINTER(SolveStats)]),
         "dmlmc_mlmc_trace": (i32, [vp, vp, vp, C.POINTER(MLMCParams), C.POINTER(TraceResult)]),
+        "dmlmc_hutchinson_trace": (i32, [vp, vp, vp, vp, C.POINTER(MLMCParams), C.POINTER(TraceResult)]),
         "dmlmc_apply": (i32, [vp, vp, i32, i32, vp, vp, i32, i32, u64]),
         "dmlmc_set_deflation": (i32, [vp, vp]),
         "dmlmc_z2_noise": (i32, [vp, i64, u64, i32, i64, i32, vp, i32]),
@@ -447,4 +449,37 @@ def mlmc_trace(hier: Hierarchy, defl: Optional[Deflation], eps: float, noise_see
                         [r.cost_s[l] for l in range(L)], [r.iters[l] for l in range(L)], r.tr_defl, r.t_trace_s)
     if keep_samples:
         out.samples = [bufs[l][: 2 * r.N[l]].view(np.complex128) for l in range(L)]
+    return out
+
+
+def hutchinson_trace(hier: Hierarchy, fine: Optional[Deflation], eps: float, noise_seed: int, n0: int,
+                     rhs_block: int, prec: int = FP64, rtol: float = 1e-10, fixed_counts: bool = False,
+                     max_samples: int = 0, keep_samples: bool = False, maxiter: int = 2000,
+                     coarsest: Optional[Deflation] = None) -> TraceEstimate:
+    """Deflated plain Hutchinson at the fine level (see dmlmc_hutchinson_trace); fine: a
+    Deflation of level 1 or None; the result lists have one entry."""
+    p = MLMCParams()
+    p.eps = eps
+    p.noise_seed = noise_seed
+    p.n0[0] = int(n0)
+    p.max_samples[0] = int(max_samples)
+    p.rhs_block = rhs_block
+    p.prec = prec
+    p.rtol = rtol
+    p.fixed_counts = 1 if fixed_counts else 0
+    p.maxiter = maxiter
+    buf = None
+    if keep_samples:
+        if max_samples <= 0:
+            raise ValueError("keep_samples needs max_samples")
+        buf = np.zeros(2 * int(max_samples), dtype=np.float64)
+        p.samples_out[0] = buf.ctypes.data_as(C.POINTER(C.c_double))
+    r = TraceResult()
+    hier.ctx.check(lib().dmlmc_hutchinson_trace(hier.ctx.h, hier.h, fine.h if fine is not None else None,
+                                                coarsest.h if coarsest is not None else None, C.byref(p),
+                                                C.byref(r)))
+    out = TraceEstimate(r.trace, r.trace_imag, r.rel_err, [r.N[0]], [complex(r.mean_re[0], r.mean_im[0])],
+                        [r.var[0]], [r.cost_s[0]], [r.iters[0]], r.tr_defl, r.t_trace_s)
+    if keep_samples:
+        out.samples = [buf[: 2 * r.N[0]].view(np.complex128)]
     return out

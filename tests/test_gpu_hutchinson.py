@@ -1,0 +1,98 @@
+"""Deflated plain Hutchinson at the fine level (GPU), the comparison method of Table 1
+(NEXT-4 workload): s = x^H D_1^-1 (x - W W^H x) with W from an exact deflation of the
+fine level (eqs. 4-7) and the noise of level 1.
+
+* Sample parity with the checker (same noise indices; the fine deflation imported from the
+  checker, so the comparison isolates the estimator and its solves): FP64 solves to
+  1e-13 within 1e-10 of each sample, mixed to 1e-10 within 1e-6 (relative to |s|);
+* the device eigensolver at the fine level reproduces the checker's deflation trace;
+* with fixed counts the estimate is the checker's on the same samples; adaptive counts
+  follow the single-level rule N = var / (eps T)^2 and meet the target;
+* arguments that do not fit the estimator are rejected.
+"""
+import numpy as np
+import pytest
+
+from oracle import deflation as odfl, mlmc as omlmc
+
+from _helpers import oracle_deflation, oracle_hierarchy
+
+pytestmark = pytest.mark.gpu
+
+NAME = "schwinger16"
+KF = 64  # fine-level deflation vectors (n_1 = 512)
+
+
+def _setup(gpu):
+    torch, dm, ctx = gpu
+    W, m0, lv = oracle_hierarchy(NAME)
+    H = dm.Hierarchy(ctx, W.theta(), m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                     import_tv=[l.V for l in lv[:-1]])
+    L = len(lv)
+    cref = oracle_deflation(NAME, W.k_defl)
+    dc = dm.Deflation(H, L, W.k_defl, import_X=cref.X, import_lambda=cref.lam)
+    fref = odfl.deflate(lv[0].D, lv[0].gamma5, KF)
+    df = dm.Deflation(H, 1, KF, import_X=fref.X, import_lambda=fref.lam)
+    return W, lv, H, dc, fref, df
+
+
+@pytest.mark.parametrize("prec_name,rtol,tol", [("fp64", 1e-13, 1e-10), ("mixed", 1e-10, 1e-6)])
+def test_deflated_hutchinson_samples(gpu, prec_name, rtol, tol):
+    torch, dm, ctx = gpu
+    prec = dm.FP64 if prec_name == "fp64" else dm.MIXED
+    W, lv, H, dc, fref, df = _setup(gpu)
+    assert abs(df.tr_defl - fref.tr_defl) < 1e-12 * abs(fref.tr_defl)
+    nsamp = 40
+    r = dm.hutchinson_trace(H, df, 1e-2, W.noise_seed, nsamp, 16, prec=prec, rtol=rtol, fixed_counts=True,
+                            max_samples=nsamp, keep_samples=True, coarsest=dc)
+    assert r.N == [nsamp]
+    solver = omlmc.DirectSolver(lv)
+    ref = np.array([omlmc.hutchinson_sample(lv, solver, fref, W.noise_seed, i) for i in range(nsamp)])
+    err = np.abs(r.samples[0] - ref) / np.abs(ref)
+    assert err.max() < tol, err.max()
+    # the estimate on these samples, as the checker forms it
+    T, Ti, e = omlmc.estimate([ref], fref.tr_defl)
+    assert abs(r.trace - T) < 1e-6 * abs(T) and abs(r.rel_err - e) < 1e-3 * e
+    # undeflated: the first terms of the level-1 difference samples
+    r0 = dm.hutchinson_trace(H, None, 1e-2, W.noise_seed, 8, 8, prec=prec, rtol=rtol, fixed_counts=True,
+                             max_samples=8, keep_samples=True, coarsest=dc)
+    for i in range(8):
+        _, t1, _ = omlmc.difference_sample(lv, solver, W.noise_seed, 1, i)
+        assert abs(r0.samples[0][i] - t1) < tol * abs(t1)
+    assert r0.tr_defl == 0.0
+
+
+def test_fine_level_eigensolver_and_adaptive_counts(gpu):
+    torch, dm, ctx = gpu
+    W, lv, H, dc, fref, df_imp = _setup(gpu)
+    H.set_deflation(dc)  # the V-cycles of the fine-level eigensolver's operator use it
+    dg = dm.Deflation(H, 1, KF, eig_rtol=1e-12)
+    H.set_deflation(None)
+    assert np.allclose(np.sort(np.abs(np.array(dg.export()[1]))), np.sort(np.abs(fref.lam)), rtol=1e-10, atol=0)
+    assert abs(dg.tr_defl - fref.tr_defl) < 1e-9 * abs(fref.tr_defl)
+    eps = 1e-3
+    r = dm.hutchinson_trace(H, dg, eps, W.noise_seed, 32, 32, prec=dm.MIXED, rtol=1e-10, max_samples=1 << 16,
+                            keep_samples=True, coarsest=dc)
+    assert r.rel_err <= eps
+    s = r.samples[0]
+    var = np.sum(np.abs(s - s.mean()) ** 2) / (s.size - 1)
+    assert abs(var - r.var[0]) < 1e-10 * var
+    assert abs(r.trace - (s.mean().real + dg.tr_defl)) < 1e-12 * abs(r.trace)
+    # the checker's adaptive loop on the same sample stream reaches the same count
+    solver = omlmc.DirectSolver(lv)
+    fn = lambda l, ids: np.array([omlmc.hutchinson_sample(lv, solver, fref, W.noise_seed, i) for i in ids])
+    ref = omlmc.run(fn, 1, [1.0], eps, 32, 32, fref.tr_defl)
+    assert abs(ref.N[0] - r.N[0]) <= 32, (ref.N, r.N)
+    assert abs(ref.trace - r.trace) < 3 * eps * abs(ref.trace)
+    dg.close()
+
+
+def test_hutchinson_argument_checks(gpu):
+    torch, dm, ctx = gpu
+    W, lv, H, dc, fref, df = _setup(gpu)
+    with pytest.raises(dm.DmlmcError):  # a coarsest-level deflation is not a fine one
+        dm.hutchinson_trace(H, dc, 1e-2, 1, 8, 8, fixed_counts=True)
+    with pytest.raises(dm.DmlmcError):  # the fine deflation is not a coarsest one
+        dm.hutchinson_trace(H, df, 1e-2, 1, 8, 8, fixed_counts=True, coarsest=df)
+    with pytest.raises(dm.DmlmcError):
+        dm.hutchinson_trace(H, df, 1e-2, 1, 0, 8, fixed_counts=True)
