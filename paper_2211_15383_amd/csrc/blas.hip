@@ -7,6 +7,10 @@ namespace {
 
 constexpr int RED_BLOCKS = 256;  // partial sums per RHS in the first reduction pass
 
+__global__ void fill_value_kernel(double* __restrict__ p, size_t count, double v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 template <typename T>
 __global__ void fill_zero_kernel(T* __restrict__ p, size_t count) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,6 +321,11 @@ void launch_multiaxpy(dmlmc_ctx* ctx, const Cx<RV>* V, int nb, c128* w, int64_t 
   KTimer kt(ctx, "gs_update", (double)nrhs * n * (nb * sizeof(Cx<RV>) + 2 * sizeof(c128)));
   hipLaunchKernelGGL((multiaxpy_kernel<RV>), dim3(grid_for(n), nrhs), dim3(256), 0, ctx->stream, V, nb, w, n, ld,
                      ldv, vstride, h, hld, sgn);
+  LAUNCH_CHECK();
+}
+
+void launch_fill_value(dmlmc_ctx* ctx, double* p, size_t count, double v) {
+  hipLaunchKernelGGL(fill_value_kernel, dim3(grid_for((int64_t)count)), dim3(256), 0, ctx->stream, p, count, v);
   LAUNCH_CHECK();
 }
 

@@ -338,15 +338,14 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, 
   double* scale = nullptr;
   c128* V = nullptr;
   c128* w = nullptr;
-  Cx<RP>* vin = nullptr;
   Cx<RP>* wr = nullptr;
   if (f32) {
     U = (c64*)hier_buf(H, "fg_U32", l, sizeof(c64) * (size_t)(m + 1) * vstride);
     scale = (double*)hier_buf(H, "fg_sc", l, sizeof(double) * (size_t)(m + 1) * nrhs);
-    vin = (Cx<RP>*)hier_buf(H, "fg_vin32", l, sizeof(Cx<RP>) * (size_t)vstride);
     wr = (Cx<RP>*)hier_buf(H, "fg_wr32", l, sizeof(Cx<RP>) * (size_t)vstride);
-    launch_cast<float, double>(ctx, r, U, n, nrhs, n, n);
-    HIPCHK(hipMemcpyAsync(scale, k.invb, sizeof(double) * nrhs, hipMemcpyDeviceToDevice, ctx->stream));
+    // U_0 = r / ||r|| (scale 1), so that no basis vector holds residual-sized entries
+    launch_scale_store<float>(ctx, r, k.invb, U, n, nrhs);
+    launch_fill_value(ctx, scale, nrhs, 1.0);
   } else {
     V = (c128*)hier_buf(H, "fg_V", l, sizeof(c128) * (size_t)(m + 1) * vstride);
     w = (c128*)hier_buf(H, "fg_w", l, sizeof(c128) * (size_t)vstride);
@@ -358,11 +357,14 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, 
       const std::vector<int64_t> key = {l, nrhs, j, m, (int64_t)(uintptr_t)H->coarse_defl, H->coarsest_iters,
                                         H->coarsest_iters_defl, H->nu_pre, H->nu_post, H->nu_post_coarse, H->sap_mr_iters,
                                         H->coarse_direct_mode};
+      // the preconditioner is homogeneous (M(s u) = s M(u), SAP's minimal-residual steps
+      // and the scaled FP16 coarsest solve included), so it runs on the unnormalised U_j:
+      // z'_j = M U_j, the Arnoldi step scales A z'_j by s_j in FP64, and the solution
+      // update takes y_j s_j
       run_graphed(H, key, [&]() {
-        launch_scale_vec(ctx, U + j * vstride, scale + (int64_t)j * nrhs, (c64*)vin, n, nrhs);
-        vcycle<RP>(H, l, vin, zj, nrhs);
+        vcycle<RP>(H, l, (const Cx<RP>*)(U + j * vstride), zj, nrhs);
         apply_op<RP>(ctx, L, zj, wr, nrhs);
-        arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k);
+        arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k, scale + (int64_t)j * nrhs);
       });
     } else {
       vcycle<RP>(H, l, (const Cx<RP>*)(V + j * vstride), zj, nrhs);
@@ -380,6 +382,7 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, 
     if (done) break;
   }
   krylov_solution(ctx, k, it, nrhs);
+  if (f32) krylov_scale_y(ctx, k, scale, it, nrhs);
   launch_combine<RP, double>(ctx, Z, it, k, e, n, nrhs);
   return it;
 }
@@ -449,3 +452,4 @@ template void smooth<float>(dmlmc_hier*, int, c64*, const c64*, int, int);
 template void smooth<double>(dmlmc_hier*, int, c128*, const c128*, int, int);
 template void launch_combine<double, double>(dmlmc_ctx*, const c128*, int, const KrylovArrays&, c128*, int64_t, int);
 template void launch_scale_store<double>(dmlmc_ctx*, const c128*, const double*, c128*, int64_t, int);
+template void launch_scale_store<float>(dmlmc_ctx*, const c128*, const double*, c64*, int64_t, int);
