@@ -335,7 +335,7 @@ EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout) 
     // Rayleigh-Ritz with Q^2 on the whole subspace: Y ordered by the Ritz values mu of Q^2
     applyQ(ctx, L, Y, Z, ns);
     std::vector<std::complex<double>> H2 = gram(H, Z, ns, Z, ns, n);
-    eigh_jacobi(ns, H2, mu, S);
+    if (eigh_tridiag(ns, H2, mu, S) < 0) throw DmlmcError(DMLMC_ENUMERIC, "Rayleigh-Ritz eigensolve failed");
     rotate(H, Y, ns, S, ns, T, n);
     std::swap(Y, T);
     // Rayleigh-Ritz with Q on the k leading vectors (their span converges to the invariant
@@ -344,7 +344,7 @@ EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout) 
     // with similar |lambda| at the subspace boundary)
     applyQ(ctx, L, Y, Z, k);
     std::vector<std::complex<double>> H1 = gram(H, Y, k, Z, k, n);
-    eigh_jacobi(k, H1, th1, S1);
+    if (eigh_tridiag(k, H1, th1, S1) < 0) throw DmlmcError(DMLMC_ENUMERIC, "Rayleigh-Ritz eigensolve failed");
     rotate(H, Y, k, S1, k, Q1, n);   // Ritz vectors of Q -> Q1[0..k)
     rotate(H, Z, k, S1, k, Y0, n);   // Q times them -> Y0[0..k)
     double* th = (double*)hier_buf(H, "eg_th", 0, sizeof(double) * k);
@@ -559,7 +559,7 @@ EigResult eig_difference(dmlmc_hier* H, int a, int b, int k, double tol, double 
         G[(size_t)i * cur + r] = v;
         G[(size_t)r * cur + i] = std::conj(v);
       }
-    eigh_jacobi(cur, G, th, S);
+    if (eigh_tridiag(cur, G, th, S) < 0) throw DmlmcError(DMLMC_ENUMERIC, "Rayleigh-Ritz eigensolve failed");
     const std::vector<int> ord = largest_first(th, std::min(cur, ns));
     for (int c = 0; c < k; ++c) thk[c] = th[ord[c]];
     // the k wanted Ritz vectors (T) and J applied to them (U); residuals U - theta T -> Rb
