@@ -278,6 +278,9 @@ void launch_dots(dmlmc_ctx* ctx, const Cx<RX>* x, const Cx<RY>* y, int64_t n, in
 // per-RHS squared norms (FP64), out on device
 template <typename R>
 void launch_norms2(dmlmc_ctx* ctx, const Cx<R>* x, int64_t n, int nrhs, int64_t ld, double* out);
+// y = b - y (in place) and out[r] = ||y_r||^2 (device) in one pass
+template <typename R>
+void launch_xmy_norms2(dmlmc_ctx* ctx, const Cx<R>* b, Cx<R>* y, int64_t n, int nrhs, int64_t ld, double* out);
 // y[r] = a[r] * x[r] + y[r]   (a on device, per RHS)
 template <typename R>
 void launch_axpy_dev(dmlmc_ctx* ctx, const c128* a, const Cx<R>* x, Cx<R>* y, int64_t n, int nrhs, int64_t ld);

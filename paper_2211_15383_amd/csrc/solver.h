@@ -42,7 +42,9 @@ void krylov_solution(dmlmc_ctx* ctx, const KrylovArrays& k, int iters, int nrhs)
 // y[r][i] *= scale[i][r] for i < iters
 void krylov_scale_y(dmlmc_ctx* ctx, const KrylovArrays& k, const double* scale, int iters, int nrhs);
 template <typename RZ, typename RX>
-void launch_combine(dmlmc_ctx* ctx, const Cx<RZ>* Z, int iters, const KrylovArrays& k, Cx<RX>* x, int64_t n, int nrhs);
+// x = sum_i y_i Z_i, or x += sum_i y_i Z_i (in FP64) when accumulate
+void launch_combine(dmlmc_ctx* ctx, const Cx<RZ>* Z, int iters, const KrylovArrays& k, Cx<RX>* x, int64_t n, int nrhs,
+                    bool accumulate);
 template <typename RV>
 void launch_scale_store(dmlmc_ctx* ctx, const c128* w, const double* invb, Cx<RV>* v, int64_t n, int nrhs);
 

@@ -66,7 +66,7 @@ __global__ void scale_store_kernel(const c128* __restrict__ w, const double* __r
 // x (RX) = sum_i y[r][i] Z_i (RZ)
 template <typename RZ, typename RX>
 __global__ void combine_kernel(const Cx<RZ>* __restrict__ Z, int k, const c128* __restrict__ y, int ym,
-                               Cx<RX>* __restrict__ x, int64_t n, int64_t vstride) {
+                               Cx<RX>* __restrict__ x, int64_t n, int64_t vstride, int accumulate) {
   const int r = blockIdx.y;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
     double ax = 0.0, ay = 0.0;
@@ -76,7 +76,12 @@ __global__ void combine_kernel(const Cx<RZ>* __restrict__ Z, int k, const c128* 
       ax += yi.x * (double)z.x - yi.y * (double)z.y;
       ay += yi.x * (double)z.y + yi.y * (double)z.x;
     }
-    x[r * n + p] = cmk((RX)ax, (RX)ay);
+    if (accumulate) {
+      const Cx<RX> x0 = x[r * n + p];
+      x[r * n + p] = cmk((RX)((double)x0.x + ax), (RX)((double)x0.y + ay));
+    } else {
+      x[r * n + p] = cmk((RX)ax, (RX)ay);
+    }
   }
 }
 
@@ -195,9 +200,9 @@ void krylov_solution(dmlmc_ctx* ctx, const KrylovArrays& k, int iters, int nrhs)
 
 template <typename RZ, typename RX>
 void launch_combine(dmlmc_ctx* ctx, const Cx<RZ>* Z, int iters, const KrylovArrays& k, Cx<RX>* x, int64_t n,
-                    int nrhs) {
+                    int nrhs, bool accumulate) {
   hipLaunchKernelGGL((combine_kernel<RZ, RX>), dim3(gridn(n), nrhs), dim3(256), 0, ctx->stream, Z, iters, k.y, k.m, x,
-                     n, (int64_t)nrhs * n);
+                     n, (int64_t)nrhs * n, accumulate ? 1 : 0);
   LAUNCH_CHECK();
 }
 
@@ -267,7 +272,7 @@ void coarsest_gmres(dmlmc_hier* H, int l, const Cx<R>* b_in, Cx<R>* x, int nrhs)
     }
     krylov_solution(ctx, k, m, nrhs);
   }
-  launch_combine<R, R>(ctx, V, m, k, x, n, nrhs);
+  launch_combine<R, R>(ctx, V, m, k, x, n, nrhs, false);
   if (use_defl) launch_add_cast_to<R>(ctx, e0, x, n, nrhs);
 }
 
@@ -316,10 +321,10 @@ void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs) {
 
 // ---------------------------------------------------------------- FGMRES cycle
 // Solves A e = r approximately (one cycle of at most m iterations, stopping when every
-// residual estimate is <= target[r]); r, e in FP64.  RP: precision of the operator inside
-// the cycle and of the preconditioner.  Returns the number of iterations.
+// residual estimate is <= target[r]) and adds e to x; r, x in FP64.  RP: precision of the
+// operator inside the cycle and of the preconditioner.  Returns the number of iterations.
 template <typename RP>
-int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, const std::vector<double>& target,
+int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* x, int nrhs, int m, const std::vector<double>& target,
                  std::vector<double>& res_host) {
   dmlmc_ctx* ctx = H->ctx;
   const Level& L = H->lv[l - 1];
@@ -383,7 +388,7 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* e, int nrhs, int m, 
   }
   krylov_solution(ctx, k, it, nrhs);
   if (f32) krylov_scale_y(ctx, k, scale, it, nrhs);
-  launch_combine<RP, double>(ctx, Z, it, k, e, n, nrhs);
+  launch_combine<RP, double>(ctx, Z, it, k, x, n, nrhs, true);
   return it;
 }
 
@@ -394,7 +399,6 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
   const Level& L = H->lv[l - 1];
   const int64_t n = L.n();
   c128* Rr = (c128*)hier_buf(H, "sv_R", l, sizeof(c128) * (size_t)nrhs * n);
-  c128* E = (c128*)hier_buf(H, "sv_E", l, sizeof(c128) * (size_t)nrhs * n);
   double* nrm = (double*)hier_buf(H, "sv_nrm", l, sizeof(double) * nrhs);
   std::vector<double> bn(nrhs), rn(nrhs), target(nrhs), est;
   launch_norms2<double>(ctx, B, n, nrhs, n, nrm);
@@ -426,16 +430,15 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
     if (out.iters >= maxiter) break;
     for (int q = 0; q < nrhs; ++q) target[q] = std::max(0.5 * rtol * bn[q], inner_rel * rn[q]);
     int it;
+    // each cycle adds its correction to X; then r = b - D x and ||r||^2 in FP64
     if (prec == DMLMC_MIXED)
-      it = fgmres_cycle<float>(H, l, Rr, E, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
+      it = fgmres_cycle<float>(H, l, Rr, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
     else
-      it = fgmres_cycle<double>(H, l, Rr, E, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
+      it = fgmres_cycle<double>(H, l, Rr, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
     out.iters += it;
     out.ir_steps += 1;
-    launch_add_cast<double>(ctx, E, X, n, nrhs, n, n);
     apply_op<double>(ctx, L, X, Rr, nrhs);
-    launch_xmy<double>(ctx, B, Rr, n, nrhs, n, n);
-    launch_norms2<double>(ctx, Rr, n, nrhs, n, nrm);
+    launch_xmy_norms2<double>(ctx, B, Rr, n, nrhs, n, nrm);
     HIPCHK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int q = 0; q < nrhs; ++q) {
@@ -450,6 +453,7 @@ template void vcycle<float>(dmlmc_hier*, int, const c64*, c64*, int);
 template void vcycle<double>(dmlmc_hier*, int, const c128*, c128*, int);
 template void smooth<float>(dmlmc_hier*, int, c64*, const c64*, int, int);
 template void smooth<double>(dmlmc_hier*, int, c128*, const c128*, int, int);
-template void launch_combine<double, double>(dmlmc_ctx*, const c128*, int, const KrylovArrays&, c128*, int64_t, int);
+template void launch_combine<double, double>(dmlmc_ctx*, const c128*, int, const KrylovArrays&, c128*, int64_t, int,
+                                             bool);
 template void launch_scale_store<double>(dmlmc_ctx*, const c128*, const double*, c128*, int64_t, int);
 template void launch_scale_store<float>(dmlmc_ctx*, const c128*, const double*, c64*, int64_t, int);
