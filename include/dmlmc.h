@@ -346,6 +346,10 @@ dmlmc_status dmlmc_set_deflation(dmlmc_hier *h, const dmlmc_defl *d);
  * bitwise the same).  Values < 0 keep the current setting. */
 typedef struct {
   int sap_mr_iters, nu_pre, nu_post, coarsest_iters, coarsest_iters_defl, restart, use_graphs, nu_post_coarse;
+  /* mixed precision: each complex-FP32 FGMRES cycle stops once it has reduced the FP64
+   * residual it started from by this factor (0 < inner_rtol < 1), after which the
+   * residual is recomputed in FP64 and a new cycle starts; < 0 keeps the setting */
+  double inner_rtol;
 } dmlmc_solver_params;
 dmlmc_status dmlmc_set_solver_params(dmlmc_hier *h, const dmlmc_solver_params *p);
 dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p);

@@ -538,6 +538,7 @@ dmlmc_status dmlmc_set_solver_params(dmlmc_hier* h, const dmlmc_solver_params* p
       !ok(p->coarsest_iters, 1, maxb) || !ok(p->coarsest_iters_defl, 1, maxb) || !ok(p->restart, 2, maxb) ||
       !ok(p->use_graphs, 0, 1) || !ok(p->nu_post_coarse, 0, 16))
     return DMLMC_EINVAL;
+  if (p->inner_rtol >= 0.0 && !(p->inner_rtol > 0.0 && p->inner_rtol < 1.0)) return DMLMC_EINVAL;
   auto pick = [](int v, int cur) { return v >= 0 ? v : cur; };
   const int nu_pre = pick(p->nu_pre, h->nu_pre);
   const int nu_post = pick(p->nu_post, h->nu_post);
@@ -552,6 +553,7 @@ dmlmc_status dmlmc_set_solver_params(dmlmc_hier* h, const dmlmc_solver_params* p
   if (p->coarsest_iters_defl >= 0) h->coarsest_iters_defl = p->coarsest_iters_defl;
   if (p->restart >= 0) h->restart = p->restart;
   if (p->use_graphs >= 0) h->use_graphs = p->use_graphs != 0;
+  if (p->inner_rtol >= 0.0) h->inner_rtol = p->inner_rtol;
   return DMLMC_OK;
 }
 
@@ -565,6 +567,7 @@ dmlmc_status dmlmc_get_solver_params(const dmlmc_hier* h, dmlmc_solver_params* p
   p->restart = h->restart;
   p->use_graphs = h->use_graphs ? 1 : 0;
   p->nu_post_coarse = h->nu_post_coarse;
+  p->inner_rtol = h->inner_rtol;
   return DMLMC_OK;
 }
 

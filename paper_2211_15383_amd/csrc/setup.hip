@@ -366,6 +366,7 @@ std::unique_ptr<dmlmc_hier> provisional(dmlmc_hier* H, int l, const c128* V_firs
   P->nu_pre = H->nu_pre;
   P->nu_post = H->nu_post;
   P->nu_post_coarse = H->nu_post_coarse;
+  P->inner_rtol = H->inner_rtol;
   P->coarsest_iters = H->coarsest_iters;
   P->restart = H->restart;
   P->lv.push_back(clone_operator(ctx, H->lv[l - 1]));

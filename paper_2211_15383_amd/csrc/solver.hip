@@ -413,7 +413,7 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
   }
   SolveResult out;
   const int m = std::max(2, H->restart);
-  const double inner_rel = (prec == DMLMC_MIXED) ? 2e-6 : 0.0;
+  const double inner_rel = (prec == DMLMC_MIXED) ? H->inner_rtol : 0.0;
   while (true) {
     bool all = true;
     double worst = 0.0;

@@ -58,7 +58,7 @@ class SolveStats(C.Structure):
 class SolverParams(C.Structure):
     _fields_ = [("sap_mr_iters", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarsest_iters", C.c_int),
                 ("coarsest_iters_defl", C.c_int), ("restart", C.c_int), ("use_graphs", C.c_int),
-                ("nu_post_coarse", C.c_int)]
+                ("nu_post_coarse", C.c_int), ("inner_rtol", C.c_double)]
 
 
 class MLMCParams(C.Structure):
@@ -302,7 +302,7 @@ class Hierarchy:
         """Sets the given solver parameters (see dmlmc_solver_params); returns all of them."""
         p = SolverParams(*([-1] * len(SolverParams._fields_)))
         for key, v in kw.items():
-            setattr(p, key, int(v))
+            setattr(p, key, float(v) if key == "inner_rtol" else int(v))
         st = lib().dmlmc_set_solver_params(self.h, C.byref(p))
         if st != OK:
             raise DmlmcError(st, f"invalid solver parameters {kw}")

@@ -64,9 +64,10 @@ def test_recorded_iterations_match_direct_launches(gpu):
 
 
 def test_smoothing_parameters(gpu):
-    """Fine and coarse post-smoothing counts are separate settings; a V-cycle that would
-    leave a level unsmoothed is rejected, and every setting still solves to tolerance
-    with the same samples up to the solve tolerance."""
+    """Fine and coarse post-smoothing counts and the reduction target of the complex-FP32
+    cycles are settings; a V-cycle that would leave a level unsmoothed and a target outside
+    (0, 1) are rejected, and every setting still solves to tolerance with the same samples
+    up to the solve tolerance."""
     torch, dm, ctx = gpu
     name = "schwinger128"
     W, m0, lv = oracle_hierarchy(name)
@@ -78,17 +79,20 @@ def test_smoothing_parameters(gpu):
         H.solver_params(nu_pre=0, nu_post_coarse=0)
     with pytest.raises(dm.DmlmcError):
         H.solver_params(nu_pre=0, nu_post=0)
+    with pytest.raises(dm.DmlmcError):
+        H.solver_params(inner_rtol=1.5)
     assert H.solver_params() == p0  # a rejected call changes nothing
+    assert 0.0 < p0["inner_rtol"] < 1.0
     L = len(lv)
     ref = oracle_deflation(name, W.k_defl)
     d = dm.Deflation(H, L, W.k_defl, import_X=ref.X, import_lambda=ref.lam)
     kw = dict(prec=dm.MIXED, rtol=W.rtol, fixed_counts=True, max_samples=[16] * L, keep_samples=True)
     base = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [16] * L, 16, **kw)
-    for fine, coarse in ((1, 3), (3, 1), (2, 2)):
-        q = H.solver_params(nu_post=fine, nu_post_coarse=coarse)
-        assert (q["nu_post"], q["nu_post_coarse"]) == (fine, coarse)
+    for fine, coarse, inner in ((1, 3, 1e-2), (3, 1, 2e-6), (2, 2, 0.1)):
+        q = H.solver_params(nu_post=fine, nu_post_coarse=coarse, inner_rtol=inner)
+        assert (q["nu_post"], q["nu_post_coarse"], q["inner_rtol"]) == (fine, coarse, inner)
         r = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [16] * L, 16, **kw)
         for l in range(L):
             dev = np.max(np.abs(r.samples[l] - base.samples[l]))
-            assert dev <= 1e-7 * np.max(np.abs(base.samples[l])), (fine, coarse, l, dev)
+            assert dev <= 1e-7 * np.max(np.abs(base.samples[l])), (fine, coarse, inner, l, dev)
     H.solver_params(**p0)
