@@ -136,16 +136,6 @@ __global__ void add_to_kernel(const c128* __restrict__ e, Cx<RX>* __restrict__ x
   }
 }
 
-__global__ void scale_vec_kernel(const c64* __restrict__ x, const double* __restrict__ sc, c64* __restrict__ y,
-                                 int64_t n) {
-  const int r = blockIdx.y;
-  const float s = (float)sc[r];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const c64 v = x[r * n + i];
-    y[r * n + i] = cmk(s * v.x, s * v.y);
-  }
-}
-
 // SplitMix64 step (Steele, Lea & Flood 2014): add the golden gamma, then mix.
 __device__ __forceinline__ uint64_t sm64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
@@ -300,11 +290,6 @@ void launch_add_cast_to(dmlmc_ctx* ctx, const c128* e, Cx<RX>* x, int64_t n, int
 }
 template void launch_add_cast_to<float>(dmlmc_ctx*, const c128*, c64*, int64_t, int);
 template void launch_add_cast_to<double>(dmlmc_ctx*, const c128*, c128*, int64_t, int);
-
-void launch_scale_vec(dmlmc_ctx* ctx, const c64* x, const double* sc, c64* y, int64_t n, int nrhs) {
-  hipLaunchKernelGGL(scale_vec_kernel, dim3(grid_for(n), nrhs), dim3(256), 0, ctx->stream, x, sc, y, n);
-  LAUNCH_CHECK();
-}
 
 static uint64_t sm64_host(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;

@@ -299,8 +299,6 @@ void launch_add_cast(dmlmc_ctx* ctx, const Cx<RE>* e, c128* x, int64_t n, int nr
 // x (RX) += e (FP64), [nrhs][n]
 template <typename RX>
 void launch_add_cast_to(dmlmc_ctx* ctx, const c128* e, Cx<RX>* x, int64_t n, int nrhs);
-// y[r] = sc[r] * x[r] (complex FP32, per-RHS FP64 scale)
-void launch_scale_vec(dmlmc_ctx* ctx, const c64* x, const double* sc, c64* y, int64_t n, int nrhs);
 // Z2 noise
 template <typename R>
 void launch_z2(dmlmc_ctx* ctx, Cx<R>* out, int64_t n, uint64_t seed, int level, int64_t sample0, int nrhs,

@@ -321,11 +321,12 @@ void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs) {
 
 // ---------------------------------------------------------------- FGMRES cycle
 // Solves A e = r approximately (one cycle of at most m iterations, stopping when every
-// residual estimate is <= target[r]) and adds e to x; r, x in FP64.  RP: precision of the
+// residual estimate is <= target[r]) and adds e to x; r, x in FP64, rnorm2 = ||r||^2 per
+// RHS (device, as the refinement loop has just computed it).  RP: precision of the
 // operator inside the cycle and of the preconditioner.  Returns the number of iterations.
 template <typename RP>
-int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* x, int nrhs, int m, const std::vector<double>& target,
-                 std::vector<double>& res_host) {
+int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128* x, int nrhs, int m,
+                 const std::vector<double>& target, std::vector<double>& res_host) {
   dmlmc_ctx* ctx = H->ctx;
   const Level& L = H->lv[l - 1];
   const int64_t n = L.n();
@@ -333,7 +334,7 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, c128* x, int nrhs, int m, 
   const int64_t vstride = (int64_t)nrhs * n;
   Cx<RP>* Z = (Cx<RP>*)hier_buf(H, f32 ? "fg_Z32" : "fg_Z64", l, sizeof(Cx<RP>) * (size_t)m * vstride);
   KrylovArrays k = krylov_arrays(H, "fg_", l, m, nrhs);
-  launch_norms2<double>(ctx, r, n, nrhs, n, k.nrm2);
+  HIPCHK(hipMemcpyAsync(k.nrm2, rnorm2, sizeof(double) * nrhs, hipMemcpyDeviceToDevice, ctx->stream));
   krylov_init(ctx, k, nrhs);
   int it = 0;
   res_host.assign(nrhs, 0.0);
@@ -432,9 +433,9 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
     int it;
     // each cycle adds its correction to X; then r = b - D x and ||r||^2 in FP64
     if (prec == DMLMC_MIXED)
-      it = fgmres_cycle<float>(H, l, Rr, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
+      it = fgmres_cycle<float>(H, l, Rr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
     else
-      it = fgmres_cycle<double>(H, l, Rr, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
+      it = fgmres_cycle<double>(H, l, Rr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
     out.iters += it;
     out.ir_steps += 1;
     apply_op<double>(ctx, L, X, Rr, nrhs);
