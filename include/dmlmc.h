@@ -350,6 +350,11 @@ typedef struct {
    * residual it started from by this factor (0 < inner_rtol < 1), after which the
    * residual is recomputed in FP64 and a new cycle starts; < 0 keeps the setting */
   double inner_rtol;
+  /* 1 (default): the coarse-level block Gauss-Seidel sweeps of the complex-FP32 V-cycles
+   * read complex-FP16 copies of the hop and inverse self blocks (half the block bytes;
+   * the products and vectors stay FP32; a preconditioner, so iteration counts only);
+   * 0: the FP32 blocks; < 0 keeps the setting */
+  int smoother_half;
 } dmlmc_solver_params;
 dmlmc_status dmlmc_set_solver_params(dmlmc_hier *h, const dmlmc_solver_params *p);
 dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p);

@@ -536,7 +536,7 @@ dmlmc_status dmlmc_set_solver_params(dmlmc_hier* h, const dmlmc_solver_params* p
   const int maxb = gs_max_basis() - 1;
   if (!ok(p->sap_mr_iters, 0, 64) || !ok(p->nu_pre, 0, 16) || !ok(p->nu_post, 0, 16) ||
       !ok(p->coarsest_iters, 1, maxb) || !ok(p->coarsest_iters_defl, 1, maxb) || !ok(p->restart, 2, maxb) ||
-      !ok(p->use_graphs, 0, 1) || !ok(p->nu_post_coarse, 0, 16))
+      !ok(p->use_graphs, 0, 1) || !ok(p->nu_post_coarse, 0, 16) || !ok(p->smoother_half, 0, 1))
     return DMLMC_EINVAL;
   if (p->inner_rtol >= 0.0 && !(p->inner_rtol > 0.0 && p->inner_rtol < 1.0)) return DMLMC_EINVAL;
   auto pick = [](int v, int cur) { return v >= 0 ? v : cur; };
@@ -554,6 +554,7 @@ dmlmc_status dmlmc_set_solver_params(dmlmc_hier* h, const dmlmc_solver_params* p
   if (p->restart >= 0) h->restart = p->restart;
   if (p->use_graphs >= 0) h->use_graphs = p->use_graphs != 0;
   if (p->inner_rtol >= 0.0) h->inner_rtol = p->inner_rtol;
+  if (p->smoother_half >= 0) h->smoother_half = p->smoother_half != 0;
   return DMLMC_OK;
 }
 
@@ -568,6 +569,7 @@ dmlmc_status dmlmc_get_solver_params(const dmlmc_hier* h, dmlmc_solver_params* p
   p->use_graphs = h->use_graphs ? 1 : 0;
   p->nu_post_coarse = h->nu_post_coarse;
   p->inner_rtol = h->inner_rtol;
+  p->smoother_half = h->smoother_half ? 1 : 0;
   return DMLMC_OK;
 }
 

@@ -170,6 +170,10 @@ struct Level {
   // blocks column-major (entry (i, j) at j * d + i); FP32 blocks the same except at
   // d = 16, where they are row-major (entry (i, j) at i * 16 + j, the matrix-core layout)
   DevBuf A64, A32, Ainv64, Ainv32;
+  // d = 16: complex-FP16 copies (real part in the low half of a 32-bit word, row-major) of
+  // the four hop blocks [site][4][16][16] and of the inverse self blocks, read by the
+  // half-precision operands form of the coarse Gauss-Seidel smoother
+  DevBuf Ahop16, Ainv16;
   // interpolation to level l+1 (if not coarsest): blocks P[cs][chir][row][k]
   int ax = 0, at = 0, N = 0;
   DevBuf P64, P32;
@@ -225,6 +229,7 @@ struct dmlmc_hier {
   int sap_mr_iters = 2;
   int nu_pre = 0, nu_post = 2, nu_post_coarse = 2;  // post-smoothing: fine level, coarse levels
   double inner_rtol = INNER_RTOL_DEFAULT;            // reduction per complex-FP32 FGMRES cycle
+  bool smoother_half = true;  // complex-FP32 coarse Gauss-Seidel reads the FP16 block copies
   int coarsest_iters = 24;
   int restart = 16;
   std::vector<std::unique_ptr<Workspace>> ws;  // indexed by level-1
@@ -265,7 +270,8 @@ template <typename R>
 void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color,
                 int mr_iters);
 template <typename R>
-void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color);
+void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color,
+                      bool half = false);
 template <typename R>
 void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc, int nrhs);
 template <typename R>

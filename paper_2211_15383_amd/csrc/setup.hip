@@ -230,6 +230,28 @@ __global__ void cast_blocks_kernel(const c128* __restrict__ src, c64* __restrict
   }
 }
 
+// complex-FP16 copies of 16 x 16 row-major FP32 blocks: dst block (b, q) = src block
+// (b, q + off) for q < nd, with ns source blocks per site
+__global__ void half_blocks_kernel(const c64* __restrict__ src, uint32_t* __restrict__ dst, int64_t nsites, int ns,
+                                   int nd, int off) {
+  const int64_t total = nsites * nd * 256;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = i / 256;
+    const int e = (int)(i % 256);
+    const int64_t site = blk / nd;
+    const int q = (int)(blk % nd);
+    const c64 v = src[(site * ns + q + off) * 256 + e];
+    const _Float16 re = (_Float16)v.x, im = (_Float16)v.y;
+    dst[i] = (uint32_t)__builtin_bit_cast(uint16_t, re) | ((uint32_t)__builtin_bit_cast(uint16_t, im) << 16);
+  }
+}
+
+void half_blocks(dmlmc_ctx* ctx, const c64* src, uint32_t* dst, int64_t nsites, int ns, int nd, int off) {
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(nsites * nd * 256, 256), 8192);
+  hipLaunchKernelGGL(half_blocks_kernel, dim3(grid), dim3(256), 0, ctx->stream, src, dst, nsites, ns, nd, off);
+  LAUNCH_CHECK();
+}
+
 void cast_blocks(dmlmc_ctx* ctx, const c128* src, c64* dst, int64_t nblocks, int d) {
   const int64_t total = nblocks * d * d;
   const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
@@ -305,6 +327,12 @@ Level galerkin_level(dmlmc_ctx* ctx, const Level& F) {
   LAUNCH_CHECK();
   C.Ainv32.alloc(sizeof(c64) * (size_t)Vc * dc * dc);
   cast_blocks(ctx, C.Ainv64.as<c128>(), C.Ainv32.as<c64>(), (int64_t)Vc, dc);
+  if (dc == 16) {
+    C.Ahop16.alloc(sizeof(uint32_t) * (size_t)Vc * 4 * 256);
+    half_blocks(ctx, C.A32.as<c64>(), C.Ahop16.as<uint32_t>(), Vc, 5, 4, 1);
+    C.Ainv16.alloc(sizeof(uint32_t) * (size_t)Vc * 256);
+    half_blocks(ctx, C.Ainv32.as<c64>(), C.Ainv16.as<uint32_t>(), Vc, 1, 1, 0);
+  }
   int nfail = 0;
   HIPCHK(hipMemcpyAsync(&nfail, fail.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -352,6 +380,8 @@ Level clone_operator(dmlmc_ctx* ctx, const Level& S) {
   cp(L.A32, S.A32);
   cp(L.Ainv64, S.Ainv64);
   cp(L.Ainv32, S.Ainv32);
+  cp(L.Ahop16, S.Ahop16);
+  cp(L.Ainv16, S.Ainv16);
   return L;
 }
 
@@ -367,6 +397,7 @@ std::unique_ptr<dmlmc_hier> provisional(dmlmc_hier* H, int l, const c128* V_firs
   P->nu_post = H->nu_post;
   P->nu_post_coarse = H->nu_post_coarse;
   P->inner_rtol = H->inner_rtol;
+  P->smoother_half = H->smoother_half;
   P->coarsest_iters = H->coarsest_iters;
   P->restart = H->restart;
   P->lv.push_back(clone_operator(ctx, H->lv[l - 1]));

@@ -285,7 +285,7 @@ void smooth(dmlmc_hier* H, int l, Cx<R>* x, const Cx<R>* b, int nrhs, int sweeps
       if (L.fine)
         launch_sap<R>(H->ctx, L, x, b, nrhs, color, H->sap_mr_iters);
       else
-        launch_coarse_gs<R>(H->ctx, L, x, b, nrhs, color);
+        launch_coarse_gs<R>(H->ctx, L, x, b, nrhs, color, H->smoother_half);
     }
   }
 }
@@ -361,8 +361,8 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128
     Cx<RP>* zj = Z + j * vstride;
     if (f32) {
       const std::vector<int64_t> key = {l, nrhs, j, m, (int64_t)(uintptr_t)H->coarse_defl, H->coarsest_iters,
-                                        H->coarsest_iters_defl, H->nu_pre, H->nu_post, H->nu_post_coarse, H->sap_mr_iters,
-                                        H->coarse_direct_mode};
+                                        H->coarsest_iters_defl, H->nu_pre, H->nu_post, H->nu_post_coarse,
+                                        H->sap_mr_iters, H->smoother_half, H->coarse_direct_mode};
       // the preconditioner is homogeneous (M(s u) = s M(u), SAP's minimal-residual steps
       // and the scaled FP16 coarsest solve included), so it runs on the unnormalised U_j:
       // z'_j = M U_j, the Arnoldi step scales A z'_j by s_j in FP64, and the solution

@@ -603,9 +603,27 @@ __global__ __launch_bounds__(256) void coarse16_f64_mfma_kernel(const c128* __re
 // x_s = A_ss^-1 (b_s - sum_{dir != self} A[s][dir] x_{s+dir}); the neighbours all have the
 // other colour (even extents), so the sweep over one colour is order-independent.  The
 // residual fragment stays in registers as the B operand of the inverse-block product.
-__global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ Ainv,
-                                                               c64* __restrict__ x, const c64* __restrict__ b, int Lx,
-                                                               int Lt, int nrhs, int color) {
+// H16: the four hop blocks and the inverse self block are read from their complex-FP16
+// copies (16 bytes per lane quad instead of 32) and widened to FP32 in registers; the
+// products and the vectors stay complex FP32.
+__device__ __forceinline__ Quad load_quad_h(const uint32_t* __restrict__ p) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+  Quad r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w[v] & 0xffffu));
+    const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w[v] >> 16));
+    r.v[v] = cmk((float)re, (float)im);
+  }
+  return r;
+}
+
+template <bool H16>
+__global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __restrict__ Av,
+                                                               const void* __restrict__ Ainvv, c64* __restrict__ x,
+                                                               const c64* __restrict__ b, int Lx, int Lt, int nrhs,
+                                                               int color) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t k = xcd_block() * 4 + w;
   const int64_t half = Lx / 2;
@@ -622,14 +640,20 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const c64* __rest
     const int ra = r0 + row, rb = r0 + 16 + row;
     const bool va = ra < nrhs, vb = rb < nrhs;
     const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq, ob = (int64_t)min(rb, nrhs - 1) * ld + 4 * kq;
-    Quad a[4], xa[4], xb[4];
+    Quad a[4], xa[4], xb[4], ai;
 #pragma unroll
     for (int dir = 0; dir < 4; ++dir) {
-      a[dir] = load_quad(A + (s * 5 + dir + 1) * 256 + row * 16 + 4 * kq);
+      if (H16)
+        a[dir] = load_quad_h(static_cast<const uint32_t*>(Av) + (s * 4 + dir) * 256 + row * 16 + 4 * kq);
+      else
+        a[dir] = load_quad(static_cast<const c64*>(Av) + (s * 5 + dir + 1) * 256 + row * 16 + 4 * kq);
       xa[dir] = load_quad(x + oa + sites[dir] * 16);
       xb[dir] = load_quad(x + ob + sites[dir] * 16);
     }
-    const Quad ai = load_quad(Ainv + s * 256 + row * 16 + 4 * kq);
+    if (H16)
+      ai = load_quad_h(static_cast<const uint32_t*>(Ainvv) + s * 256 + row * 16 + 4 * kq);
+    else
+      ai = load_quad(static_cast<const c64*>(Ainvv) + s * 256 + row * 16 + 4 * kq);
     Quad qa = load_quad(b + oa - 4 * kq + own);
     Quad qb = load_quad(b + ob - 4 * kq + own);
     __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
@@ -942,7 +966,7 @@ void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nr
 }
 
 template <typename R>
-void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color) {
+void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color, bool half) {
   const int d = L.dofs;
   const int spb = std::max(1, 256 / d);
   const int64_t V = L.sites();
@@ -956,10 +980,16 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
     // colour's sites) and the four hop blocks and the inverse self block
     REQUIRE(even && L.Lt % 2 == 0, "block Gauss-Seidel needs even extents");
     REQUIRE(((uintptr_t)x | (uintptr_t)b) % 16 == 0, "matrix-core Gauss-Seidel needs 16-byte aligned vectors");
+    const bool h16 = half && L.Ahop16.p && L.Ainv16.p;
     KTimer kt(ctx, "coarse_gs",
-              (double)nrhs * (V / 2) * d * 3 * sizeof(Cx<R>) + (double)(V / 2) * 5 * d * d * sizeof(Cx<R>));
-    hipLaunchKernelGGL(coarse16_gs_mfma_kernel, dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0, ctx->stream,
-                       (const c64*)A, (const c64*)Ai, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color);
+              (double)nrhs * (V / 2) * d * 3 * sizeof(Cx<R>) + (double)(V / 2) * 5 * d * d * (h16 ? 4 : sizeof(Cx<R>)));
+    if (h16)
+      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
+                         ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color);
+    else
+      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<false>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
+                         ctx->stream, (const void*)A, (const void*)Ai, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs,
+                         color);
     LAUNCH_CHECK();
     return;
   }
@@ -1027,7 +1057,7 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
   template void launch_coarse<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, int64_t, int64_t, bool); \
   template void apply_op<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, bool);                        \
   template void launch_sap<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int, int);                  \
-  template void launch_coarse_gs<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int);                 \
+  template void launch_coarse_gs<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int, bool);           \
   template void launch_restrict<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int);                       \
   template void launch_prolong<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, bool);
 INST(float)

@@ -58,7 +58,7 @@ class SolveStats(C.Structure):
 class SolverParams(C.Structure):
     _fields_ = [("sap_mr_iters", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarsest_iters", C.c_int),
                 ("coarsest_iters_defl", C.c_int), ("restart", C.c_int), ("use_graphs", C.c_int),
-                ("nu_post_coarse", C.c_int), ("inner_rtol", C.c_double)]
+                ("nu_post_coarse", C.c_int), ("inner_rtol", C.c_double), ("smoother_half", C.c_int)]
 
 
 class MLMCParams(C.Structure):

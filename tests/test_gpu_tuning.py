@@ -64,8 +64,8 @@ def test_recorded_iterations_match_direct_launches(gpu):
 
 
 def test_smoothing_parameters(gpu):
-    """Fine and coarse post-smoothing counts and the reduction target of the complex-FP32
-    cycles are settings; a V-cycle that would leave a level unsmoothed and a target outside
+    """Fine and coarse post-smoothing counts, the reduction target of the complex-FP32
+    cycles and the precision of the smoother's coarse blocks are settings; a V-cycle that would leave a level unsmoothed and a target outside
     (0, 1) are rejected, and every setting still solves to tolerance with the same samples
     up to the solve tolerance."""
     torch, dm, ctx = gpu
@@ -81,6 +81,8 @@ def test_smoothing_parameters(gpu):
         H.solver_params(nu_pre=0, nu_post=0)
     with pytest.raises(dm.DmlmcError):
         H.solver_params(inner_rtol=1.5)
+    with pytest.raises(dm.DmlmcError):
+        H.solver_params(smoother_half=2)
     assert H.solver_params() == p0  # a rejected call changes nothing
     assert 0.0 < p0["inner_rtol"] < 1.0
     L = len(lv)
@@ -88,11 +90,11 @@ def test_smoothing_parameters(gpu):
     d = dm.Deflation(H, L, W.k_defl, import_X=ref.X, import_lambda=ref.lam)
     kw = dict(prec=dm.MIXED, rtol=W.rtol, fixed_counts=True, max_samples=[16] * L, keep_samples=True)
     base = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [16] * L, 16, **kw)
-    for fine, coarse, inner in ((1, 3, 1e-2), (3, 1, 2e-6), (2, 2, 0.1)):
-        q = H.solver_params(nu_post=fine, nu_post_coarse=coarse, inner_rtol=inner)
-        assert (q["nu_post"], q["nu_post_coarse"], q["inner_rtol"]) == (fine, coarse, inner)
+    for fine, coarse, inner, half in ((1, 3, 1e-2, 1), (3, 1, 2e-6, 0), (2, 2, 0.1, 0), (2, 2, 1e-2, 1)):
+        q = H.solver_params(nu_post=fine, nu_post_coarse=coarse, inner_rtol=inner, smoother_half=half)
+        assert (q["nu_post"], q["nu_post_coarse"], q["inner_rtol"], q["smoother_half"]) == (fine, coarse, inner, half)
         r = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [16] * L, 16, **kw)
         for l in range(L):
             dev = np.max(np.abs(r.samples[l] - base.samples[l]))
-            assert dev <= 1e-7 * np.max(np.abs(base.samples[l])), (fine, coarse, inner, l, dev)
+            assert dev <= 1e-7 * np.max(np.abs(base.samples[l])), (fine, coarse, inner, half, l, dev)
     H.solver_params(**p0)
