@@ -604,19 +604,14 @@ __global__ __launch_bounds__(256) void coarse16_f64_mfma_kernel(const c128* __re
 // other colour (even extents), so the sweep over one colour is order-independent.  The
 // residual fragment stays in registers as the B operand of the inverse-block product.
 // H16: the four hop blocks and the inverse self block are read from their complex-FP16
-// copies (16 bytes per lane quad instead of 32) and widened to FP32 in registers; the
-// products and the vectors stay complex FP32.
-__device__ __forceinline__ Quad load_quad_h(const uint32_t* __restrict__ p) {
-  const uint4 u = *reinterpret_cast<const uint4*>(p);
-  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-  Quad r;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w[v] & 0xffffu));
-    const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w[v] >> 16));
-    r.v[v] = cmk((float)re, (float)im);
-  }
-  return r;
+// copies (16 bytes per lane quad instead of 32), kept packed in registers and widened to
+// FP32 just before each product, and the RHS are taken one 16-wide tile at a time, so the
+// wavefront needs few enough registers for four waves per SIMD; the products and the
+// vectors stay complex FP32.
+__device__ __forceinline__ c64 half2_to_c64(uint32_t w) {
+  const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+  const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+  return cmk((float)re, (float)im);
 }
 
 template <bool H16>
@@ -636,43 +631,72 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[4] = {nb.xp, nb.xm, nb.tp, nb.tm};
   const int64_t own = s * 16 + 4 * kq;
-  for (int r0 = 0; r0 < nrhs; r0 += 32) {
-    const int ra = r0 + row, rb = r0 + 16 + row;
-    const bool va = ra < nrhs, vb = rb < nrhs;
-    const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq, ob = (int64_t)min(rb, nrhs - 1) * ld + 4 * kq;
-    Quad a[4], xa[4], xb[4], ai;
+  if constexpr (H16) {
+    const uint32_t* A = static_cast<const uint32_t*>(Av);
+    const uint32_t* Ainv = static_cast<const uint32_t*>(Ainvv);
+    uint4 a[4];
 #pragma unroll
-    for (int dir = 0; dir < 4; ++dir) {
-      if (H16)
-        a[dir] = load_quad_h(static_cast<const uint32_t*>(Av) + (s * 4 + dir) * 256 + row * 16 + 4 * kq);
-      else
-        a[dir] = load_quad(static_cast<const c64*>(Av) + (s * 5 + dir + 1) * 256 + row * 16 + 4 * kq);
-      xa[dir] = load_quad(x + oa + sites[dir] * 16);
-      xb[dir] = load_quad(x + ob + sites[dir] * 16);
-    }
-    if (H16)
-      ai = load_quad_h(static_cast<const uint32_t*>(Ainvv) + s * 256 + row * 16 + 4 * kq);
-    else
-      ai = load_quad(static_cast<const c64*>(Ainvv) + s * 256 + row * 16 + 4 * kq);
-    Quad qa = load_quad(b + oa - 4 * kq + own);
-    Quad qb = load_quad(b + ob - 4 * kq + own);
-    __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
-    f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
+    for (int dir = 0; dir < 4; ++dir) a[dir] = *reinterpret_cast<const uint4*>(A + (s * 4 + dir) * 256 + row * 16 + 4 * kq);
+    const uint4 ai = *reinterpret_cast<const uint4*>(Ainv + s * 256 + row * 16 + 4 * kq);
+    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+      const int ra = r0 + row;
+      const bool va = ra < nrhs;
+      const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq;
+      Quad xa[4];
 #pragma unroll
-    for (int dir = 0; dir < 4; ++dir) {
-      block_mfma(are, aim, a[dir], select_quad(va, xa[dir]));
-      block_mfma(bre, bim, a[dir], select_quad(vb, xb[dir]));
-    }
+      for (int dir = 0; dir < 4; ++dir) xa[dir] = load_quad(x + oa + sites[dir] * 16);
+      Quad qa = load_quad(b + oa - 4 * kq + own);
+      __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
+      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      qa.v[v] = cmk(qa.v[v].x - are[v], qa.v[v].y - aim[v]);
-      qb.v[v] = cmk(qb.v[v].x - bre[v], qb.v[v].y - bim[v]);
+      for (int dir = 0; dir < 4; ++dir) {
+        const uint32_t wv[4] = {a[dir].x, a[dir].y, a[dir].z, a[dir].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cmfma(are, aim, half2_to_c64(wv[q]), va ? xa[dir].v[q] : cmk(0.f, 0.f));
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qa.v[v] = cmk(qa.v[v].x - are[v], qa.v[v].y - aim[v]);
+      f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere;
+      const uint32_t wi[4] = {ai.x, ai.y, ai.z, ai.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cmfma(ere, eim, half2_to_c64(wi[q]), va ? qa.v[q] : cmk(0.f, 0.f));
+      if (va) store_quad(x + (int64_t)ra * ld + own, ere, eim, 1.f);
     }
-    f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere, fre = ere, fim = ere;
-    block_mfma(ere, eim, ai, select_quad(va, qa));
-    block_mfma(fre, fim, ai, select_quad(vb, qb));
-    if (va) store_quad(x + (int64_t)ra * ld + own, ere, eim, 1.f);
-    if (vb) store_quad(x + (int64_t)rb * ld + own, fre, fim, 1.f);
+  } else {
+    const c64* A = static_cast<const c64*>(Av);
+    const c64* Ainv = static_cast<const c64*>(Ainvv);
+    for (int r0 = 0; r0 < nrhs; r0 += 32) {
+      const int ra = r0 + row, rb = r0 + 16 + row;
+      const bool va = ra < nrhs, vb = rb < nrhs;
+      const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq, ob = (int64_t)min(rb, nrhs - 1) * ld + 4 * kq;
+      Quad a[4], xa[4], xb[4];
+#pragma unroll
+      for (int dir = 0; dir < 4; ++dir) {
+        a[dir] = load_quad(A + (s * 5 + dir + 1) * 256 + row * 16 + 4 * kq);
+        xa[dir] = load_quad(x + oa + sites[dir] * 16);
+        xb[dir] = load_quad(x + ob + sites[dir] * 16);
+      }
+      const Quad ai = load_quad(Ainv + s * 256 + row * 16 + 4 * kq);
+      Quad qa = load_quad(b + oa - 4 * kq + own);
+      Quad qb = load_quad(b + ob - 4 * kq + own);
+      __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
+      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
+#pragma unroll
+      for (int dir = 0; dir < 4; ++dir) {
+        block_mfma(are, aim, a[dir], select_quad(va, xa[dir]));
+        block_mfma(bre, bim, a[dir], select_quad(vb, xb[dir]));
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qa.v[v] = cmk(qa.v[v].x - are[v], qa.v[v].y - aim[v]);
+        qb.v[v] = cmk(qb.v[v].x - bre[v], qb.v[v].y - bim[v]);
+      }
+      f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere, fre = ere, fim = ere;
+      block_mfma(ere, eim, ai, select_quad(va, qa));
+      block_mfma(fre, fim, ai, select_quad(vb, qb));
+      if (va) store_quad(x + (int64_t)ra * ld + own, ere, eim, 1.f);
+      if (vb) store_quad(x + (int64_t)rb * ld + own, fre, fim, 1.f);
+    }
   }
 }
 
