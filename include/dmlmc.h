@@ -337,18 +337,19 @@ dmlmc_status dmlmc_set_deflation(dmlmc_hier *h, const dmlmc_defl *d);
 /* ---------------------------------------------------------------- solver parameters
  * Parameters of the solver that change iteration counts and speed but not the solution
  * (every solve still stops at its FP64 residual tolerance): SAP local minimal-residual
- * iterations, pre/post smoothing sweeps of the V-cycle (nu_post on the fine level,
- * nu_post_coarse on the coarse levels; every level must smooth at least once), fixed
- * GMRES iterations of the coarsest solve without / with an attached coarsest deflation,
- * the FGMRES restart length (at most 31), and use_graphs: 1 (default) replays each complex-FP32 FGMRES
- * iteration (preconditioner, operator, Gram-Schmidt) as a recorded HIP graph after its
- * first two runs with the same shapes, 0 launches every kernel directly (results are
- * bitwise the same).  Values < 0 keep the current setting. */
+ * iterations (default 2), pre/post smoothing sweeps of the V-cycle (nu_pre 0, nu_post 2
+ * on the fine level, nu_post_coarse 2 on the coarse levels; every level must smooth at
+ * least once), fixed GMRES iterations of the coarsest solve without / with an attached
+ * coarsest deflation (24 / 8), the FGMRES restart length (16, at most 31), and
+ * use_graphs: 1 (default) replays each complex-FP32 FGMRES iteration (preconditioner,
+ * operator, Gram-Schmidt) as a recorded HIP graph after its first two runs with the same
+ * shapes, 0 launches every kernel directly (results are bitwise the same).  Values < 0
+ * keep the current setting; a rejected call (EINVAL) changes nothing. */
 typedef struct {
   int sap_mr_iters, nu_pre, nu_post, coarsest_iters, coarsest_iters_defl, restart, use_graphs, nu_post_coarse;
   /* mixed precision: each complex-FP32 FGMRES cycle stops once it has reduced the FP64
-   * residual it started from by this factor (0 < inner_rtol < 1), after which the
-   * residual is recomputed in FP64 and a new cycle starts; < 0 keeps the setting */
+   * residual it started from by this factor (0 < inner_rtol < 1, default 1e-2), after
+   * which the residual is recomputed in FP64 and a new cycle starts; < 0 keeps it */
   double inner_rtol;
   /* 1 (default): the coarse-level block Gauss-Seidel sweeps of the complex-FP32 V-cycles
    * read complex-FP16 copies of the hop and inverse self blocks (half the block bytes;
