@@ -55,3 +55,15 @@ def test_no_device_is_an_error_not_a_crash():
     lib = dmlmc.load()
     h = C.c_void_p()
     assert lib.dmlmc_create(C.byref(h), 0, None) == dmlmc.EHIP
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark measures one GPU's share; asking for more exits with a message."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
