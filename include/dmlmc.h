@@ -353,7 +353,8 @@ typedef struct {
   double inner_rtol;
   /* 1 (default): the coarse-level block Gauss-Seidel sweeps of the complex-FP32 V-cycles
    * read complex-FP16 copies of the hop and inverse self blocks (half the block bytes;
-   * the products and vectors stay FP32; a preconditioner, so iteration counts only);
+   * the products and vectors stay FP32; a preconditioner, so iteration counts only; a
+   * level with a block entry beyond the FP16 range keeps its FP32 blocks);
    * 0: the FP32 blocks; < 0 keeps the setting */
   int smoother_half;
 } dmlmc_solver_params;

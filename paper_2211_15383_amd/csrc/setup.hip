@@ -231,9 +231,10 @@ __global__ void cast_blocks_kernel(const c128* __restrict__ src, c64* __restrict
 }
 
 // complex-FP16 copies of 16 x 16 row-major FP32 blocks: dst block (b, q) = src block
-// (b, q + off) for q < nd, with ns source blocks per site
+// (b, q + off) for q < nd, with ns source blocks per site; *overflow is set when an
+// entry is not finite or beyond the FP16 range
 __global__ void half_blocks_kernel(const c64* __restrict__ src, uint32_t* __restrict__ dst, int64_t nsites, int ns,
-                                   int nd, int off) {
+                                   int nd, int off, int* __restrict__ overflow) {
   const int64_t total = nsites * nd * 256;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t blk = i / 256;
@@ -241,14 +242,17 @@ __global__ void half_blocks_kernel(const c64* __restrict__ src, uint32_t* __rest
     const int64_t site = blk / nd;
     const int q = (int)(blk % nd);
     const c64 v = src[(site * ns + q + off) * 256 + e];
+    if (!(fabsf(v.x) <= 65000.f && fabsf(v.y) <= 65000.f)) *overflow = 1;
     const _Float16 re = (_Float16)v.x, im = (_Float16)v.y;
     dst[i] = (uint32_t)__builtin_bit_cast(uint16_t, re) | ((uint32_t)__builtin_bit_cast(uint16_t, im) << 16);
   }
 }
 
-void half_blocks(dmlmc_ctx* ctx, const c64* src, uint32_t* dst, int64_t nsites, int ns, int nd, int off) {
+void half_blocks(dmlmc_ctx* ctx, const c64* src, uint32_t* dst, int64_t nsites, int ns, int nd, int off,
+                 int* overflow) {
   const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(nsites * nd * 256, 256), 8192);
-  hipLaunchKernelGGL(half_blocks_kernel, dim3(grid), dim3(256), 0, ctx->stream, src, dst, nsites, ns, nd, off);
+  hipLaunchKernelGGL(half_blocks_kernel, dim3(grid), dim3(256), 0, ctx->stream, src, dst, nsites, ns, nd, off,
+                     overflow);
   LAUNCH_CHECK();
 }
 
@@ -328,10 +332,20 @@ Level galerkin_level(dmlmc_ctx* ctx, const Level& F) {
   C.Ainv32.alloc(sizeof(c64) * (size_t)Vc * dc * dc);
   cast_blocks(ctx, C.Ainv64.as<c128>(), C.Ainv32.as<c64>(), (int64_t)Vc, dc);
   if (dc == 16) {
+    // the half-precision smoother operands exist only when every entry fits FP16
+    DevBuf over(sizeof(int));
+    HIPCHK(hipMemsetAsync(over.p, 0, sizeof(int), ctx->stream));
     C.Ahop16.alloc(sizeof(uint32_t) * (size_t)Vc * 4 * 256);
-    half_blocks(ctx, C.A32.as<c64>(), C.Ahop16.as<uint32_t>(), Vc, 5, 4, 1);
+    half_blocks(ctx, C.A32.as<c64>(), C.Ahop16.as<uint32_t>(), Vc, 5, 4, 1, over.as<int>());
     C.Ainv16.alloc(sizeof(uint32_t) * (size_t)Vc * 256);
-    half_blocks(ctx, C.Ainv32.as<c64>(), C.Ainv16.as<uint32_t>(), Vc, 1, 1, 0);
+    half_blocks(ctx, C.Ainv32.as<c64>(), C.Ainv16.as<uint32_t>(), Vc, 1, 1, 0, over.as<int>());
+    int novf = 0;
+    HIPCHK(hipMemcpyAsync(&novf, over.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (novf) {
+      C.Ahop16.release();
+      C.Ainv16.release();
+    }
   }
   int nfail = 0;
   HIPCHK(hipMemcpyAsync(&nfail, fail.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
