@@ -122,7 +122,7 @@ def kernel_rates(torch, dm, ctx, H, nlev: int, b: int, reps: int = 10):
     return out
 
 
-def method_comparison(torch, dm, ctx, name: str, eps: float, kdiff: int, hutch_k=()):
+def method_comparison(torch, dm, ctx, name: str, eps: float, kdiff: int, hutch_k=(), diff=True):
     """The variants of the paper's Table 1 on one synthetic workload (mixed precision,
     coarsest term always deflated): plain MGMLMC; level 2 skipped (eq. 12); and each of
     those with the first difference term exactly deflated by its kdiff largest singular
@@ -137,11 +137,17 @@ def method_comparison(torch, dm, ctx, name: str, eps: float, kdiff: int, hutch_k
     Dc = dm.Deflation(H, L, W.k_defl, eig_rtol=1e-9)
     t_coarse = time.perf_counter() - t0
     H.set_deflation(Dc)  # the difference-level eigensolves use the deflated coarsest solve
+    coarsest = "deflated fixed-count GMRES"
+    try:  # the measured configuration's coarsest solve, where the level allows it
+        H.coarsest_direct(Dc, dm.DIRECT_FP16)
+        coarsest = "explicit inverse applied in complex FP16"
+    except dm.DmlmcError:
+        pass
     out = {"workload": name, "eps": eps, "k_coarsest": W.k_defl, "k_difference": kdiff,
-           "coarsest_eigensolve_s": t_coarse, "variants": {}}
+           "coarsest_eigensolve_s": t_coarse, "coarsest_solve": coarsest, "variants": {}}
     for skip in ((), (2,)):
         b = 3 if skip else 2
-        for defl in (False, True):
+        for defl in ((False, True) if diff else (False,)):
             label = ("skip2" if skip else "all_levels") + ("+diff_defl" if defl else "")
             td = 0.0
             term = [None] * L
@@ -249,6 +255,8 @@ def main():
                     help="also time plain / skipped-level / difference-deflated MGMLMC on WORKLOAD")
     ap.add_argument("--methods-eps", type=float, default=1e-3)
     ap.add_argument("--methods-k", type=int, default=8)
+    ap.add_argument("--methods-no-diff", action="store_true",
+                    help="leave out the variants with a deflated difference term in --methods")
     ap.add_argument("--methods-hutch-k", default="", help="comma-separated fine-level deflation sizes for the "
                     "deflated plain Hutchinson rows of --methods")
     args = ap.parse_args()
@@ -361,7 +369,8 @@ def main():
     methods = None
     if args.methods:
         hk = tuple(int(v) for v in args.methods_hutch_k.split(",") if v.strip())
-        methods = method_comparison(torch, dmlmc, ctx, args.methods, args.methods_eps, args.methods_k, hk)
+        methods = method_comparison(torch, dmlmc, ctx, args.methods, args.methods_eps, args.methods_k, hk,
+                                    diff=not args.methods_no_diff)
 
     cpu = None
     if not args.skip_cpu:
