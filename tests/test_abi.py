@@ -67,3 +67,29 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_recorded_traffic_lookup():
+    """The benchmark reports HBM traffic only from a committed counter summary taken on the
+    current source of the kernel and the same launch mix (algorithmic bytes within 0.5 %)."""
+    import importlib.util
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    argv = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        spec.loader.exec_module(b)
+    finally:
+        sys.argv = argv
+    text = open(os.path.join(root, "profiles", "hbm_traffic_coarse16_gs_mfma_mgmlmc1024.md")).read()
+    m = re.search(r"traffic: class=coarse_gs source_sha256=(\S+) bytes_per_launch=(\S+) "
+                  r"algorithmic_bytes_per_launch=(\S+)", text)
+    assert m, "the summary has no traffic line"
+    assert m.group(1) == b.source_digest("coarse_gs"), "counters were taken on another source of the kernel"
+    alg = float(m.group(3))
+    got, src = b.recorded_traffic("coarse_gs", alg)
+    assert got == float(m.group(2)) and src.startswith("hbm_traffic_")
+    assert b.recorded_traffic("coarse_gs", alg * 1.02) == (None, None)
