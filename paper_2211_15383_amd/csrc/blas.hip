@@ -71,23 +71,6 @@ __global__ __launch_bounds__(256) void norms_partial(const Cx<R>* __restrict__ x
   if (threadIdx.x == 0) part[(int64_t)r * gridDim.x + blockIdx.x] = t;
 }
 
-// y = b - y and the per-block partial sums of |y|^2 (the residual of a refinement step and
-// its norm in one pass; the same blocking and order as norms_partial)
-template <typename R>
-__global__ __launch_bounds__(256) void xmy_norms_partial(const Cx<R>* __restrict__ b, Cx<R>* __restrict__ y, int64_t n,
-                                                         int64_t ld, double* __restrict__ part) {
-  __shared__ double sh[8];
-  const int r = blockIdx.y;
-  double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const Cx<R> v = b[r * ld + i] - y[r * ld + i];
-    y[r * ld + i] = v;
-    s += cabs2(v);
-  }
-  double t = block_sum(s, sh);
-  if (threadIdx.x == 0) part[(int64_t)r * gridDim.x + blockIdx.x] = t;
-}
-
 // out[r * stride + c] = sum_g part[(r * G + g) * width + c] for c < width
 __global__ void reduce_partials(const double* __restrict__ part, int G, int width, double* __restrict__ out,
                                 int stride) {
@@ -256,16 +239,6 @@ void launch_norms2(dmlmc_ctx* ctx, const Cx<R>* x, int64_t n, int nrhs, int64_t 
 }
 
 template <typename R>
-void launch_xmy_norms2(dmlmc_ctx* ctx, const Cx<R>* b, Cx<R>* y, int64_t n, int nrhs, int64_t ld, double* out) {
-  const int G = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, ceil_div(n, 1024)));
-  double* part = partial_buf(ctx, (size_t)nrhs * G);
-  hipLaunchKernelGGL((xmy_norms_partial<R>), dim3(G, nrhs), dim3(256), 0, ctx->stream, b, y, n, ld, part);
-  LAUNCH_CHECK();
-  hipLaunchKernelGGL(reduce_partials, dim3(nrhs), dim3(256), 0, ctx->stream, part, G, 1, out, 1);
-  LAUNCH_CHECK();
-}
-
-template <typename R>
 void launch_axpy_dev(dmlmc_ctx* ctx, const c128* a, const Cx<R>* x, Cx<R>* y, int64_t n, int nrhs, int64_t ld) {
   hipLaunchKernelGGL((axpy_dev_kernel<R>), dim3(grid_for(n), nrhs), dim3(256), 0, ctx->stream, a, x, y, n, ld);
   LAUNCH_CHECK();
@@ -353,7 +326,6 @@ template void launch_dots<float, float>(dmlmc_ctx*, const c64*, const c64*, int6
 template void launch_dots<float, double>(dmlmc_ctx*, const c64*, const c128*, int64_t, int, int64_t, int64_t, c128*);
 template void launch_norms2<double>(dmlmc_ctx*, const c128*, int64_t, int, int64_t, double*);
 template void launch_norms2<float>(dmlmc_ctx*, const c64*, int64_t, int, int64_t, double*);
-template void launch_xmy_norms2<double>(dmlmc_ctx*, const c128*, c128*, int64_t, int, int64_t, double*);
 template void launch_axpy_dev<double>(dmlmc_ctx*, const c128*, const c128*, c128*, int64_t, int, int64_t);
 template void launch_axpy_dev<float>(dmlmc_ctx*, const c128*, const c64*, c64*, int64_t, int, int64_t);
 template void launch_xmy<double>(dmlmc_ctx*, const c128*, c128*, int64_t, int, int64_t, int64_t);

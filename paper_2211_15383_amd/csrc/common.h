@@ -257,15 +257,18 @@ struct dmlmc_defl {
 
 // ------------------------------------------------------------------ kernel launchers
 // precision tag: R = float -> c64 path, R = double -> c128 path
+// y = D x (or Gamma5 D x); with sub given, the residual form y = sub - D x
 template <typename R>
 void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx,
-                   int64_t ldy, bool gamma5_left);
+                   int64_t ldy, bool gamma5_left, const Cx<R>* sub = nullptr);
 template <typename R>
 void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx,
-                   int64_t ldy, bool gamma5_left);
+                   int64_t ldy, bool gamma5_left, const Cx<R>* sub = nullptr);
 template <typename R>
 void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, bool gamma5_left = false);
-// mixed: y (double) = D (double) x (float) -- operator in FP64 on an FP32 input
+// r = b - D x in one pass (the refinement residual)
+template <typename R>
+void apply_residual(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, const Cx<R>* b, Cx<R>* r, int nrhs);
 template <typename R>
 void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color,
                 int mr_iters);
@@ -290,9 +293,6 @@ void launch_dots(dmlmc_ctx* ctx, const Cx<RX>* x, const Cx<RY>* y, int64_t n, in
 // per-RHS squared norms (FP64), out on device
 template <typename R>
 void launch_norms2(dmlmc_ctx* ctx, const Cx<R>* x, int64_t n, int nrhs, int64_t ld, double* out);
-// y = b - y (in place) and out[r] = ||y_r||^2 (device) in one pass
-template <typename R>
-void launch_xmy_norms2(dmlmc_ctx* ctx, const Cx<R>* b, Cx<R>* y, int64_t n, int nrhs, int64_t ld, double* out);
 // y[r] = a[r] * x[r] + y[r]   (a on device, per RHS)
 template <typename R>
 void launch_axpy_dev(dmlmc_ctx* ctx, const c128* a, const Cx<R>* x, Cx<R>* y, int64_t n, int nrhs, int64_t ld);

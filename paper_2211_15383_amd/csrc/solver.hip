@@ -431,15 +431,16 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
     if (out.iters >= maxiter) break;
     for (int q = 0; q < nrhs; ++q) target[q] = std::max(0.5 * rtol * bn[q], inner_rel * rn[q]);
     int it;
-    // each cycle adds its correction to X; then r = b - D x and ||r||^2 in FP64
+    // each cycle adds its correction to X; then r = b - D x (one operator pass) and
+    // ||r||^2 in FP64
     if (prec == DMLMC_MIXED)
       it = fgmres_cycle<float>(H, l, Rr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
     else
       it = fgmres_cycle<double>(H, l, Rr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
     out.iters += it;
     out.ir_steps += 1;
-    apply_op<double>(ctx, L, X, Rr, nrhs);
-    launch_xmy_norms2<double>(ctx, B, Rr, n, nrhs, n, nrm);
+    apply_residual<double>(ctx, L, X, B, Rr, nrhs);
+    launch_norms2<double>(ctx, Rr, n, nrhs, n, nrm);
     HIPCHK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int q = 0; q < nrhs; ++q) {

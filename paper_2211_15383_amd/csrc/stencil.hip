@@ -70,7 +70,8 @@ __device__ __forceinline__ int64_t xcd_block() {
 template <typename R, bool G5>
 __global__ __launch_bounds__(256) void wilson_kernel(const Cx<R>* __restrict__ U, const Cx<R>* __restrict__ in,
                                                      Cx<R>* __restrict__ out, int Lx, int Lt, R diag, int nrhs,
-                                                     int rb, int64_t ldx, int64_t ldy) {
+                                                     int rb, int64_t ldx, int64_t ldy,
+                                                     const Cx<R>* __restrict__ sub) {
   const int64_t V = (int64_t)Lx * Lt;
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= V) return;
@@ -105,6 +106,11 @@ __global__ __launch_bounds__(256) void wilson_kernel(const Cx<R>* __restrict__ U
     o.s0 = diag * c0.s0 - half * a0;
     o.s1 = diag * c0.s1 - half * a1;
     if (G5) o.s1 = cmk(-o.s1.x, -o.s1.y);
+    if (sub) {  // residual form: out = sub - D in
+      const Spinor<R> bb = reinterpret_cast<const Spinor<R>*>(sub + r * ldy)[s];
+      o.s0 = bb.s0 - o.s0;
+      o.s1 = bb.s1 - o.s1;
+    }
     // the result is not re-read by this launch: non-temporal store
     R* of = reinterpret_cast<R*>(out + r * ldy + 2 * s);
     __builtin_nontemporal_store(o.s0.x, of);
@@ -120,7 +126,8 @@ __global__ __launch_bounds__(256) void wilson_kernel(const Cx<R>* __restrict__ U
 template <typename R, int RB, bool G5>
 __global__ __launch_bounds__(256) void coarse_kernel(const Cx<R>* __restrict__ A, const Cx<R>* __restrict__ in,
                                                      Cx<R>* __restrict__ out, int Lx, int Lt, int d, int spb,
-                                                     int nrhs, int64_t ldx, int64_t ldy) {
+                                                     int nrhs, int64_t ldx, int64_t ldy,
+                                                     const Cx<R>* __restrict__ sub) {
   const int64_t V = (int64_t)Lx * Lt;
   const int i = threadIdx.x % d;
   const int64_t s = (int64_t)blockIdx.x * spb + threadIdx.x / d;
@@ -147,7 +154,10 @@ __global__ __launch_bounds__(256) void coarse_kernel(const Cx<R>* __restrict__ A
   const bool neg = G5 && (i >= d / 2);
 #pragma unroll
   for (int q = 0; q < RB; ++q) {
-    if (q < nr) out[(r0 + q) * ldy + s * d + i] = neg ? cmk(-acc[q].x, -acc[q].y) : acc[q];
+    if (q < nr) {
+      const Cx<R> v = neg ? cmk(-acc[q].x, -acc[q].y) : acc[q];
+      out[(r0 + q) * ldy + s * d + i] = sub ? sub[(r0 + q) * ldy + s * d + i] - v : v;
+    }
   }
 }
 
@@ -557,7 +567,8 @@ __device__ __forceinline__ void cmfma64(f64x4& dre, f64x4& dim, c128 a, c128 x) 
 template <bool G5>
 __global__ __launch_bounds__(256) void coarse16_f64_mfma_kernel(const c128* __restrict__ A,
                                                                 const c128* __restrict__ in, c128* __restrict__ out,
-                                                                int Lx, int Lt, int nrhs, int64_t ldx, int64_t ldy) {
+                                                                int Lx, int Lt, int nrhs, int64_t ldx, int64_t ldy,
+                                                                const c128* __restrict__ sub) {
   const int64_t V = (int64_t)Lx * Lt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t s = xcd_block() * 4 + w;
@@ -593,8 +604,10 @@ __global__ __launch_bounds__(256) void coarse16_f64_mfma_kernel(const c128* __re
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (va) out[(int64_t)ra * ldy + s * 16 + 4 * kq + q] = cmk(sg * are[q], sg * aim[q]);
-      if (vb) out[(int64_t)rb * ldy + s * 16 + 4 * kq + q] = cmk(sg * bre[q], sg * bim[q]);
+      const int64_t ia = (int64_t)ra * ldy + s * 16 + 4 * kq + q, ib = (int64_t)rb * ldy + s * 16 + 4 * kq + q;
+      const c128 ya = cmk(sg * are[q], sg * aim[q]), yb = cmk(sg * bre[q], sg * bim[q]);
+      if (va) out[ia] = sub ? sub[ia] - ya : ya;  // residual form: out = sub - D in
+      if (vb) out[ib] = sub ? sub[ib] - yb : yb;
     }
   }
 }
@@ -894,32 +907,35 @@ inline int rhs_block_for(int64_t threads, int nrhs) {
 
 template <typename R>
 void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx, int64_t ldy,
-                   bool gamma5_left) {
+                   bool gamma5_left, const Cx<R>* sub) {
   const int64_t V = L.sites();
   // at most 8 RHS per thread: more workgroups in flight; links are re-read nrhs / 8 times
   const int rb = std::min(8, rhs_block_for(V, nrhs));
   dim3 grid((unsigned)ceil_div(V, 256), (unsigned)ceil_div(nrhs, rb));
   const Cx<R>* U = std::is_same<R, float>::value ? (const Cx<R>*)L.U32.p : (const Cx<R>*)L.U64.p;
-  KTimer kt(ctx, "wilson", (double)nrhs * V * 4 * sizeof(Cx<R>) + (double)V * 2 * sizeof(Cx<R>));
+  REQUIRE(!(sub && gamma5_left), "the residual form has no Gamma5");
+  KTimer kt(ctx, "wilson", (double)nrhs * V * (sub ? 6 : 4) * sizeof(Cx<R>) + (double)V * 2 * sizeof(Cx<R>));
   if (gamma5_left)
     hipLaunchKernelGGL((wilson_kernel<R, true>), grid, dim3(256), 0, ctx->stream, U, x, y, L.Lx, L.Lt,
-                       (R)(L.m0 + 2.0), nrhs, rb, ldx, ldy);
+                       (R)(L.m0 + 2.0), nrhs, rb, ldx, ldy, (const Cx<R>*)nullptr);
   else
     hipLaunchKernelGGL((wilson_kernel<R, false>), grid, dim3(256), 0, ctx->stream, U, x, y, L.Lx, L.Lt,
-                       (R)(L.m0 + 2.0), nrhs, rb, ldx, ldy);
+                       (R)(L.m0 + 2.0), nrhs, rb, ldx, ldy, sub);
   LAUNCH_CHECK();
 }
 
 template <typename R>
 void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx, int64_t ldy,
-                   bool gamma5_left) {
+                   bool gamma5_left, const Cx<R>* sub) {
   const int d = L.dofs;
   const int spb = std::max(1, 256 / d);
   const int64_t V = L.sites();
   const Cx<R>* A = std::is_same<R, float>::value ? (const Cx<R>*)L.A32.p : (const Cx<R>*)L.A64.p;
+  REQUIRE(!(sub && gamma5_left), "the residual form has no Gamma5");
   KTimer kt(ctx, "coarse",
-            (double)nrhs * L.n() * 2 * sizeof(Cx<R>) + (double)V * 5 * d * d * sizeof(Cx<R>));
+            (double)nrhs * L.n() * (sub ? 3 : 2) * sizeof(Cx<R>) + (double)V * 5 * d * d * sizeof(Cx<R>));
   if (std::is_same<R, float>::value && d == 16) {
+    REQUIRE(sub == nullptr, "the complex-FP32 matrix-core stencil has no residual form");
     REQUIRE(ldx % 2 == 0 && ldy % 2 == 0 && ((uintptr_t)x | (uintptr_t)y) % 16 == 0,
             "matrix-core coarse stencil needs 16-byte aligned RHS rows");
     dim3 grid((unsigned)ceil_div(V, 4));
@@ -938,10 +954,10 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
     dim3 grid((unsigned)ceil_div(V, 4));
     if (gamma5_left)
       hipLaunchKernelGGL((coarse16_f64_mfma_kernel<true>), grid, dim3(256), 0, ctx->stream, (const c128*)A,
-                         (const c128*)x, (c128*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+                         (const c128*)x, (c128*)y, L.Lx, L.Lt, nrhs, ldx, ldy, (const c128*)nullptr);
     else
       hipLaunchKernelGGL((coarse16_f64_mfma_kernel<false>), grid, dim3(256), 0, ctx->stream, (const c128*)A,
-                         (const c128*)x, (c128*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+                         (const c128*)x, (c128*)y, L.Lx, L.Lt, nrhs, ldx, ldy, (const c128*)sub);
     LAUNCH_CHECK();
     return;
   }
@@ -950,19 +966,27 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
   dim3 block((unsigned)(spb * d));
   if (gamma5_left)
     hipLaunchKernelGGL((coarse_kernel<R, RB, true>), grid, block, 0, ctx->stream, A, x, y, L.Lx, L.Lt, d, spb, nrhs,
-                       ldx, ldy);
+                       ldx, ldy, (const Cx<R>*)nullptr);
   else
     hipLaunchKernelGGL((coarse_kernel<R, RB, false>), grid, block, 0, ctx->stream, A, x, y, L.Lx, L.Lt, d, spb,
-                       nrhs, ldx, ldy);
+                       nrhs, ldx, ldy, sub);
   LAUNCH_CHECK();
 }
 
 template <typename R>
 void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, bool gamma5_left) {
   if (L.fine)
-    launch_wilson<R>(ctx, L, x, y, nrhs, L.n(), L.n(), gamma5_left);
+    launch_wilson<R>(ctx, L, x, y, nrhs, L.n(), L.n(), gamma5_left, nullptr);
   else
-    launch_coarse<R>(ctx, L, x, y, nrhs, L.n(), L.n(), gamma5_left);
+    launch_coarse<R>(ctx, L, x, y, nrhs, L.n(), L.n(), gamma5_left, nullptr);
+}
+
+template <typename R>
+void apply_residual(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, const Cx<R>* b, Cx<R>* r, int nrhs) {
+  if (L.fine)
+    launch_wilson<R>(ctx, L, x, r, nrhs, L.n(), L.n(), false, b);
+  else
+    launch_coarse<R>(ctx, L, x, r, nrhs, L.n(), L.n(), false, b);
 }
 
 template <typename R>
@@ -1077,9 +1101,12 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
 }
 
 #define INST(R)                                                                                                  \
-  template void launch_wilson<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, int64_t, int64_t, bool); \
-  template void launch_coarse<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, int64_t, int64_t, bool); \
+  template void launch_wilson<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, int64_t, int64_t, bool,     \
+                                 const Cx<R>*);                                                                  \
+  template void launch_coarse<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, int64_t, int64_t, bool,     \
+                                 const Cx<R>*);                                                                  \
   template void apply_op<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, bool);                        \
+  template void apply_residual<R>(dmlmc_ctx*, const Level&, const Cx<R>*, const Cx<R>*, Cx<R>*, int);          \
   template void launch_sap<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int, int);                  \
   template void launch_coarse_gs<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int, bool);           \
   template void launch_restrict<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int);                       \
