@@ -257,7 +257,9 @@ struct dmlmc_defl {
 
 // ------------------------------------------------------------------ kernel launchers
 // precision tag: R = float -> c64 path, R = double -> c128 path
-// y = D x (or Gamma5 D x); with sub given, the residual form y = sub - D x
+// Vectors of nrhs right-hand sides are stored one after another, RHS r at r * ld; ld = 0
+// stands for the level size n.  y = D x (or Gamma5 D x); with sub given, the residual
+// form y = sub - D x
 template <typename R>
 void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx,
                    int64_t ldy, bool gamma5_left, const Cx<R>* sub = nullptr);
@@ -265,20 +267,23 @@ template <typename R>
 void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx,
                    int64_t ldy, bool gamma5_left, const Cx<R>* sub = nullptr);
 template <typename R>
-void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, bool gamma5_left = false);
+void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, bool gamma5_left = false,
+              int64_t ld = 0);
 // r = b - D x in one pass (the refinement residual)
 template <typename R>
 void apply_residual(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, const Cx<R>* b, Cx<R>* r, int nrhs);
 template <typename R>
 void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color,
-                int mr_iters);
+                int mr_iters, int64_t ld = 0);
 template <typename R>
 void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color,
-                      bool half = false);
+                      bool half = false, int64_t ld = 0);
 template <typename R>
-void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc, int nrhs);
+void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc, int nrhs, int64_t ldf = 0,
+                     int64_t ldc = 0);
 template <typename R>
-void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, int nrhs, bool add);
+void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, int nrhs, bool add,
+                    int64_t ldc = 0, int64_t ldf = 0);
 
 // BLAS-like (blas.hip)
 template <typename T>

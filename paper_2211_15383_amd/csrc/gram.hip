@@ -269,7 +269,7 @@ template <typename RW, int NBT>
 __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U, int nb,
                                                        const Cx<RW>* __restrict__ w, int64_t n, int64_t vstride,
                                                        const double* __restrict__ wscale, double* __restrict__ part,
-                                                       Fin f) {
+                                                       Fin f, int64_t ld) {
   __shared__ double lds[4 * NVMAX];
   __shared__ double red[NVMAX];
   const int r = blockIdx.y;
@@ -278,8 +278,8 @@ __global__ __launch_bounds__(256) void gs1_dots_kernel(const c64* __restrict__ U
 #pragma unroll
   for (int q = 0; q < 2 * NBT; ++q) acc[q] = 0.0;
   // element pairs (n is even): 16-byte loads of the FP32 basis
-  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * n);
-  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * n);
+  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * ld);
+  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * ld);
   const int64_t np = n / 2, vs = vstride / 2;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
     const Pair<RW> bw = wr[p];
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, in
                                                          int64_t n, int64_t vstride, const c128* __restrict__ h,
                                                          int hld, const double* __restrict__ scale, int nrhs,
                                                          const double* __restrict__ wscale, double* __restrict__ part,
-                                                         Fin f) {
+                                                         Fin f, int64_t ld) {
   __shared__ double lds[4 * NVMAX];
   __shared__ double red[NVMAX];
   __shared__ c128 hs[NBMAX];
@@ -314,9 +314,9 @@ __global__ __launch_bounds__(256) void gs1_update_kernel(c64* __restrict__ U, in
   }
   __syncthreads();
   double acc[1] = {0.0};
-  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * n);
-  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * n);
-  Pair<float>* out = reinterpret_cast<Pair<float>*>(U + (int64_t)nb * vstride + (int64_t)r * n);
+  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * ld);
+  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * ld);
+  Pair<float>* out = reinterpret_cast<Pair<float>*>(U + (int64_t)nb * vstride + (int64_t)r * ld);
   const int64_t np = n / 2, vs = vstride / 2;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
     const Pair<RW> bw = wr[p];
@@ -375,7 +375,7 @@ template <typename RW>
 __global__ __launch_bounds__(FUSED_THREADS) void gs1_fused_kernel(c64* __restrict__ U, int nb,
                                                                   const Cx<RW>* __restrict__ w, int64_t n,
                                                                   int64_t vstride, const double* __restrict__ wscale,
-                                                                  Fin f) {
+                                                                  Fin f, int64_t ld) {
   constexpr int NW = FUSED_THREADS / 64;
   __shared__ double lds[NW][2 * FUSED_CHUNK];
   __shared__ double red[NVMAX];
@@ -385,8 +385,8 @@ __global__ __launch_bounds__(FUSED_THREADS) void gs1_fused_kernel(c64* __restric
   const int nrhs = f.nrhs;
   const double ws = wscale ? wscale[r] : 1.0;
   const int64_t np = n / 2, vs = vstride / 2;
-  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * n);
-  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * n);
+  const Pair<RW>* wr = reinterpret_cast<const Pair<RW>*>(w + (int64_t)r * ld);
+  const Pair<float>* Ur = reinterpret_cast<const Pair<float>*>(U + (int64_t)r * ld);
   // h_i = s_i <u_i, ws w>, FUSED_CHUNK basis vectors per reduction round (w is re-read
   // from L2 per round rather than held in registers)
   for (int c0 = 0; c0 < nb; c0 += FUSED_CHUNK) {
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(FUSED_THREADS) void gs1_fused_kernel(c64* __restric
   }
   __syncthreads();
   // u_{j+1} = ws w - sum_i (h_i s_i) u_i, its norm from the stored FP32 values
-  Pair<float>* out = reinterpret_cast<Pair<float>*>(U + (int64_t)nb * vstride + (int64_t)r * n);
+  Pair<float>* out = reinterpret_cast<Pair<float>*>(U + (int64_t)nb * vstride + (int64_t)r * ld);
   double nrm = 0.0;
 #pragma unroll
   for (int q = 0; q < FUSED_PPT; ++q) {
@@ -553,10 +553,12 @@ void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs
 // One Arnoldi step, single-pass form on an unnormalised complex-FP32 basis.
 template <typename RW>
 void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, int j, int64_t n, int nrhs,
-                       const KrylovArrays& k, const double* wscale) {
+                       const KrylovArrays& k, const double* wscale, int64_t ld) {
   const int nb = j + 1;
   if (nb > NBMAX) throw DmlmcError(DMLMC_EINVAL, "Krylov basis larger than the Gram-Schmidt limit");
-  const int64_t vstride = (int64_t)nrhs * n;
+  if (ld <= 0) ld = n;
+  REQUIRE(ld >= n && ld % 2 == 0, "Gram-Schmidt vectors need an even stride of at least their length");
+  const int64_t vstride = (int64_t)nrhs * ld;
   if (n <= 2 * (int64_t)FUSED_THREADS * FUSED_PPT) {
     Fin f = base_fin(k, j, nrhs);
     f.mode = FIN_CGS1;
@@ -564,7 +566,7 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
     f.scale = scale;
     KTimer kt(ctx, "gs_fused", (double)nrhs * n * ((2 * nb + 1) * sizeof(c64) + sizeof(Cx<RW>)));
     hipLaunchKernelGGL((gs1_fused_kernel<RW>), dim3(nrhs), dim3(FUSED_THREADS), 0, ctx->stream, U, nb, w, n, vstride,
-                       wscale, f);
+                       wscale, f, ld);
     LAUNCH_CHECK();
     return;
   }
@@ -581,16 +583,16 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
     // the basis count rounded up to 4, 8, 16 or 32 sizes the registers (and occupancy)
     if (nb <= 4)
       hipLaunchKernelGGL((gs1_dots_kernel<RW, 4>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale, part,
-                         fa);
+                         fa, ld);
     else if (nb <= 8)
       hipLaunchKernelGGL((gs1_dots_kernel<RW, 8>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale, part,
-                         fa);
+                         fa, ld);
     else if (nb <= 16)
       hipLaunchKernelGGL((gs1_dots_kernel<RW, 16>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale,
-                         part, fa);
+                         part, fa, ld);
     else
       hipLaunchKernelGGL((gs1_dots_kernel<RW, NBMAX>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, wscale,
-                         part, fa);
+                         part, fa, ld);
     LAUNCH_CHECK();
     launch_partial_finish(ctx, part, G, 2 * nb, fa, nrhs);
   }
@@ -602,7 +604,7 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
     KTimer kt(ctx, "gs_update", (double)nrhs * n * ((nb + 1) * sizeof(c64) + sizeof(Cx<RW>)));
 #define GS1_UPDATE(NBT)                                                                                      \
   hipLaunchKernelGGL((gs1_update_kernel<RW, NBT>), grid, dim3(256), 0, ctx->stream, U, nb, w, n, vstride, k.h1, \
-                     k.hld, scale, nrhs, wscale, part, fb)
+                     k.hld, scale, nrhs, wscale, part, fb, ld)
     if (nb <= 4)
       GS1_UPDATE(4);
     else if (nb <= 8)
@@ -620,6 +622,6 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
 template void arnoldi_step<double>(dmlmc_ctx*, c128*, c128*, int, int64_t, int, const KrylovArrays&);
 template void arnoldi_step<float>(dmlmc_ctx*, c64*, c128*, int, int64_t, int, const KrylovArrays&);
 template void arnoldi_step_cgs1<float>(dmlmc_ctx*, c64*, double*, const c64*, int, int64_t, int, const KrylovArrays&,
-                                       const double*);
+                                       const double*, int64_t);
 template void arnoldi_step_cgs1<double>(dmlmc_ctx*, c64*, double*, const c128*, int, int64_t, int,
-                                        const KrylovArrays&, const double*);
+                                        const KrylovArrays&, const double*, int64_t);

@@ -34,24 +34,35 @@ template <typename RV>
 void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs, const KrylovArrays& k);
 // Single-pass form: unnormalised complex-FP32 basis u_i with scales s_i = 1/||u_i||
 // (scale[i][nrhs]); the new vector is wscale[r] * w (wscale NULL: factor 1), w complex
-// FP32 or FP64; FP64 arithmetic.
+// FP32 or FP64; FP64 arithmetic.  U and w hold RHS r at r * ld (ld = 0: n), basis vector
+// i at i * nrhs * ld.
 template <typename RW>
 void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, int j, int64_t n, int nrhs,
-                       const KrylovArrays& k, const double* wscale = nullptr);
+                       const KrylovArrays& k, const double* wscale = nullptr, int64_t ld = 0);
 void krylov_solution(dmlmc_ctx* ctx, const KrylovArrays& k, int iters, int nrhs);
 // y[r][i] *= scale[i][r] for i < iters
 void krylov_scale_y(dmlmc_ctx* ctx, const KrylovArrays& k, const double* scale, int iters, int nrhs);
 template <typename RZ, typename RX>
-// x = sum_i y_i Z_i, or x += sum_i y_i Z_i (in FP64) when accumulate
+// x = sum_i y_i Z_i, or x += sum_i y_i Z_i (in FP64) when accumulate; Z_i holds RHS r at
+// i * nrhs * ldz + r * ldz, x at r * ldx (0: n)
 void launch_combine(dmlmc_ctx* ctx, const Cx<RZ>* Z, int iters, const KrylovArrays& k, Cx<RX>* x, int64_t n, int nrhs,
-                    bool accumulate);
+                    bool accumulate, int64_t ldz = 0, int64_t ldx = 0);
+// v (stride ldv) = w (stride ldw) * invb[r]
 template <typename RV>
-void launch_scale_store(dmlmc_ctx* ctx, const c128* w, const double* invb, Cx<RV>* v, int64_t n, int nrhs);
+void launch_scale_store(dmlmc_ctx* ctx, const c128* w, const double* invb, Cx<RV>* v, int64_t n, int nrhs,
+                        int64_t ldw = 0, int64_t ldv = 0);
 
+// Stride of the solver's internal multi-RHS work vectors on level l: the level size plus
+// 256 entries below the coarsest level (from 4096 entries on), so that one entry of
+// consecutive right-hand sides does not repeat the same HBM channel at power-of-two
+// level sizes; the coarsest level keeps its size.
+int64_t work_ld(const dmlmc_hier* H, int l);
+
+// b, x: RHS r at r * ld (ld = 0: the level size); the coarser levels' vectors use work_ld
 template <typename R>
-void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs);
+void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs, int64_t ld = 0);
 template <typename R>
-void smooth(dmlmc_hier* H, int l, Cx<R>* x, const Cx<R>* b, int nrhs, int sweeps);
+void smooth(dmlmc_hier* H, int l, Cx<R>* x, const Cx<R>* b, int nrhs, int sweeps, int64_t ld = 0);
 
 struct SolveResult {
   int iters = 0;

@@ -54,33 +54,34 @@ __global__ void scale_y_kernel(c128* __restrict__ y, int m, const double* __rest
 // v_out (RV) = w * invb[r]
 template <typename RV>
 __global__ void scale_store_kernel(const c128* __restrict__ w, const double* __restrict__ invb, Cx<RV>* __restrict__ v,
-                                   int64_t n) {
+                                   int64_t n, int64_t ldw, int64_t ldv) {
   const int r = blockIdx.y;
   const double s = invb[r];
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    const c128 a = w[r * n + p];
-    v[r * n + p] = cmk((RV)(a.x * s), (RV)(a.y * s));
+    const c128 a = w[r * ldw + p];
+    v[r * ldv + p] = cmk((RV)(a.x * s), (RV)(a.y * s));
   }
 }
 
 // x (RX) = sum_i y[r][i] Z_i (RZ)
 template <typename RZ, typename RX>
 __global__ void combine_kernel(const Cx<RZ>* __restrict__ Z, int k, const c128* __restrict__ y, int ym,
-                               Cx<RX>* __restrict__ x, int64_t n, int64_t vstride, int accumulate) {
+                               Cx<RX>* __restrict__ x, int64_t n, int64_t vstride, int accumulate, int64_t ldz,
+                               int64_t ldx) {
   const int r = blockIdx.y;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
     double ax = 0.0, ay = 0.0;
     for (int i = 0; i < k; ++i) {
       const c128 yi = y[r * ym + i];
-      const Cx<RZ> z = Z[i * vstride + r * n + p];
+      const Cx<RZ> z = Z[i * vstride + r * ldz + p];
       ax += yi.x * (double)z.x - yi.y * (double)z.y;
       ay += yi.x * (double)z.y + yi.y * (double)z.x;
     }
     if (accumulate) {
-      const Cx<RX> x0 = x[r * n + p];
-      x[r * n + p] = cmk((RX)((double)x0.x + ax), (RX)((double)x0.y + ay));
+      const Cx<RX> x0 = x[r * ldx + p];
+      x[r * ldx + p] = cmk((RX)((double)x0.x + ax), (RX)((double)x0.y + ay));
     } else {
-      x[r * n + p] = cmk((RX)ax, (RX)ay);
+      x[r * ldx + p] = cmk((RX)ax, (RX)ay);
     }
   }
 }
@@ -200,15 +201,23 @@ void krylov_solution(dmlmc_ctx* ctx, const KrylovArrays& k, int iters, int nrhs)
 
 template <typename RZ, typename RX>
 void launch_combine(dmlmc_ctx* ctx, const Cx<RZ>* Z, int iters, const KrylovArrays& k, Cx<RX>* x, int64_t n,
-                    int nrhs, bool accumulate) {
+                    int nrhs, bool accumulate, int64_t ldz, int64_t ldx) {
+  if (ldz <= 0) ldz = n;
+  if (ldx <= 0) ldx = n;
+  REQUIRE(ldz >= n && ldx >= n, "vector strides below the vector length");
   hipLaunchKernelGGL((combine_kernel<RZ, RX>), dim3(gridn(n), nrhs), dim3(256), 0, ctx->stream, Z, iters, k.y, k.m, x,
-                     n, (int64_t)nrhs * n, accumulate ? 1 : 0);
+                     n, (int64_t)nrhs * ldz, accumulate ? 1 : 0, ldz, ldx);
   LAUNCH_CHECK();
 }
 
 template <typename RV>
-void launch_scale_store(dmlmc_ctx* ctx, const c128* w, const double* invb, Cx<RV>* v, int64_t n, int nrhs) {
-  hipLaunchKernelGGL((scale_store_kernel<RV>), dim3(gridn(n), nrhs), dim3(256), 0, ctx->stream, w, invb, v, n);
+void launch_scale_store(dmlmc_ctx* ctx, const c128* w, const double* invb, Cx<RV>* v, int64_t n, int nrhs,
+                        int64_t ldw, int64_t ldv) {
+  if (ldw <= 0) ldw = n;
+  if (ldv <= 0) ldv = n;
+  REQUIRE(ldw >= n && ldv >= n, "vector strides below the vector length");
+  hipLaunchKernelGGL((scale_store_kernel<RV>), dim3(gridn(n), nrhs), dim3(256), 0, ctx->stream, w, invb, v, n, ldw,
+                     ldv);
   LAUNCH_CHECK();
 }
 
@@ -277,46 +286,54 @@ void coarsest_gmres(dmlmc_hier* H, int l, const Cx<R>* b_in, Cx<R>* x, int nrhs)
 }
 
 // ---------------------------------------------------------------- V-cycle
+int64_t work_ld(const dmlmc_hier* H, int l) {
+  const Level& L = H->lv[l - 1];
+  const int64_t n = L.n();
+  return (l < (int)H->lv.size() && n >= 4096) ? n + 256 : n;
+}
+
 template <typename R>
-void smooth(dmlmc_hier* H, int l, Cx<R>* x, const Cx<R>* b, int nrhs, int sweeps) {
+void smooth(dmlmc_hier* H, int l, Cx<R>* x, const Cx<R>* b, int nrhs, int sweeps, int64_t ld) {
   const Level& L = H->lv[l - 1];
   for (int s = 0; s < sweeps; ++s) {
     for (int color = 0; color < 2; ++color) {
       if (L.fine)
-        launch_sap<R>(H->ctx, L, x, b, nrhs, color, H->sap_mr_iters);
+        launch_sap<R>(H->ctx, L, x, b, nrhs, color, H->sap_mr_iters, ld);
       else
-        launch_coarse_gs<R>(H->ctx, L, x, b, nrhs, color, H->smoother_half);
+        launch_coarse_gs<R>(H->ctx, L, x, b, nrhs, color, H->smoother_half, ld);
     }
   }
 }
 
 template <typename R>
-void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs) {
+void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs, int64_t ld) {
   const int Lmax = (int)H->lv.size();
+  const Level& L = H->lv[l - 1];
+  const int64_t n = L.n();
+  if (ld <= 0) ld = n;
   if (l == Lmax) {
+    REQUIRE(ld == n, "coarsest-level vectors are stored unpadded");
     coarsest_gmres<R>(H, l, b, x, nrhs);
     return;
   }
   dmlmc_ctx* ctx = H->ctx;
-  const Level& L = H->lv[l - 1];
-  const Level& C = H->lv[l];
   const bool f32 = std::is_same<R, float>::value;
-  const int64_t n = L.n(), nc = C.n();
-  Cx<R>* bc = (Cx<R>*)hier_buf(H, f32 ? "vc_b32" : "vc_b64", l + 1, sizeof(Cx<R>) * (size_t)nrhs * nc);
-  Cx<R>* xc = (Cx<R>*)hier_buf(H, f32 ? "vc_x32" : "vc_x64", l + 1, sizeof(Cx<R>) * (size_t)nrhs * nc);
+  const int64_t ldc = work_ld(H, l + 1);
+  Cx<R>* bc = (Cx<R>*)hier_buf(H, f32 ? "vc_b32" : "vc_b64", l + 1, sizeof(Cx<R>) * (size_t)nrhs * ldc);
+  Cx<R>* xc = (Cx<R>*)hier_buf(H, f32 ? "vc_x32" : "vc_x64", l + 1, sizeof(Cx<R>) * (size_t)nrhs * ldc);
   if (H->nu_pre > 0) {
-    Cx<R>* r = (Cx<R>*)hier_buf(H, f32 ? "vc_r32" : "vc_r64", l, sizeof(Cx<R>) * (size_t)nrhs * n);
-    launch_fill_zero<Cx<R>>(ctx, x, (size_t)nrhs * n);
-    smooth<R>(H, l, x, b, nrhs, H->nu_pre);
-    apply_op<R>(ctx, L, x, r, nrhs);
-    launch_xmy<R>(ctx, b, r, n, nrhs, n, n);
-    launch_restrict<R>(ctx, L, r, bc, nrhs);
+    Cx<R>* r = (Cx<R>*)hier_buf(H, f32 ? "vc_r32" : "vc_r64", l, sizeof(Cx<R>) * (size_t)nrhs * ld);
+    launch_fill_zero<Cx<R>>(ctx, x, (size_t)(nrhs - 1) * ld + n);
+    smooth<R>(H, l, x, b, nrhs, H->nu_pre, ld);
+    apply_op<R>(ctx, L, x, r, nrhs, false, ld);
+    launch_xmy<R>(ctx, b, r, n, nrhs, ld, ld);
+    launch_restrict<R>(ctx, L, r, bc, nrhs, ld, ldc);
   } else {
-    launch_restrict<R>(ctx, L, b, bc, nrhs);
+    launch_restrict<R>(ctx, L, b, bc, nrhs, ld, ldc);
   }
-  vcycle<R>(H, l + 1, bc, xc, nrhs);
-  launch_prolong<R>(ctx, L, xc, x, nrhs, H->nu_pre > 0);
-  smooth<R>(H, l, x, b, nrhs, L.fine ? H->nu_post : H->nu_post_coarse);
+  vcycle<R>(H, l + 1, bc, xc, nrhs, ldc);
+  launch_prolong<R>(ctx, L, xc, x, nrhs, H->nu_pre > 0, ldc, ld);
+  smooth<R>(H, l, x, b, nrhs, L.fine ? H->nu_post : H->nu_post_coarse, ld);
 }
 
 // ---------------------------------------------------------------- FGMRES cycle
@@ -331,7 +348,10 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128
   const Level& L = H->lv[l - 1];
   const int64_t n = L.n();
   const bool f32 = std::is_same<RP, float>::value;
-  const int64_t vstride = (int64_t)nrhs * n;
+  // the complex-FP32 cycle keeps its basis and preconditioned vectors at the padded work
+  // stride; r and x (FP64, the caller's) stay unpadded
+  const int64_t ldw = f32 ? work_ld(H, l) : n;
+  const int64_t vstride = (int64_t)nrhs * ldw;
   Cx<RP>* Z = (Cx<RP>*)hier_buf(H, f32 ? "fg_Z32" : "fg_Z64", l, sizeof(Cx<RP>) * (size_t)m * vstride);
   KrylovArrays k = krylov_arrays(H, "fg_", l, m, nrhs);
   HIPCHK(hipMemcpyAsync(k.nrm2, rnorm2, sizeof(double) * nrhs, hipMemcpyDeviceToDevice, ctx->stream));
@@ -350,7 +370,7 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128
     scale = (double*)hier_buf(H, "fg_sc", l, sizeof(double) * (size_t)(m + 1) * nrhs);
     wr = (Cx<RP>*)hier_buf(H, "fg_wr32", l, sizeof(Cx<RP>) * (size_t)vstride);
     // U_0 = r / ||r|| (scale 1), so that no basis vector holds residual-sized entries
-    launch_scale_store<float>(ctx, r, k.invb, U, n, nrhs);
+    launch_scale_store<float>(ctx, r, k.invb, U, n, nrhs, n, ldw);
     launch_fill_value(ctx, scale, nrhs, 1.0);
   } else {
     V = (c128*)hier_buf(H, "fg_V", l, sizeof(c128) * (size_t)(m + 1) * vstride);
@@ -368,9 +388,9 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128
       // z'_j = M U_j, the Arnoldi step scales A z'_j by s_j in FP64, and the solution
       // update takes y_j s_j
       run_graphed(H, key, [&]() {
-        vcycle<RP>(H, l, (const Cx<RP>*)(U + j * vstride), zj, nrhs);
-        apply_op<RP>(ctx, L, zj, wr, nrhs);
-        arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k, scale + (int64_t)j * nrhs);
+        vcycle<RP>(H, l, (const Cx<RP>*)(U + j * vstride), zj, nrhs, ldw);
+        apply_op<RP>(ctx, L, zj, wr, nrhs, false, ldw);
+        arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k, scale + (int64_t)j * nrhs, ldw);
       });
     } else {
       vcycle<RP>(H, l, (const Cx<RP>*)(V + j * vstride), zj, nrhs);
@@ -389,7 +409,7 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128
   }
   krylov_solution(ctx, k, it, nrhs);
   if (f32) krylov_scale_y(ctx, k, scale, it, nrhs);
-  launch_combine<RP, double>(ctx, Z, it, k, x, n, nrhs, true);
+  launch_combine<RP, double>(ctx, Z, it, k, x, n, nrhs, true, ldw, n);
   return it;
 }
 
@@ -451,11 +471,12 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
   return out;
 }
 
-template void vcycle<float>(dmlmc_hier*, int, const c64*, c64*, int);
-template void vcycle<double>(dmlmc_hier*, int, const c128*, c128*, int);
-template void smooth<float>(dmlmc_hier*, int, c64*, const c64*, int, int);
-template void smooth<double>(dmlmc_hier*, int, c128*, const c128*, int, int);
+template void vcycle<float>(dmlmc_hier*, int, const c64*, c64*, int, int64_t);
+template void vcycle<double>(dmlmc_hier*, int, const c128*, c128*, int, int64_t);
+template void smooth<float>(dmlmc_hier*, int, c64*, const c64*, int, int, int64_t);
+template void smooth<double>(dmlmc_hier*, int, c128*, const c128*, int, int, int64_t);
 template void launch_combine<double, double>(dmlmc_ctx*, const c128*, int, const KrylovArrays&, c128*, int64_t, int,
-                                             bool);
-template void launch_scale_store<double>(dmlmc_ctx*, const c128*, const double*, c128*, int64_t, int);
-template void launch_scale_store<float>(dmlmc_ctx*, const c128*, const double*, c64*, int64_t, int);
+                                             bool, int64_t, int64_t);
+template void launch_scale_store<double>(dmlmc_ctx*, const c128*, const double*, c128*, int64_t, int, int64_t,
+                                         int64_t);
+template void launch_scale_store<float>(dmlmc_ctx*, const c128*, const double*, c64*, int64_t, int, int64_t, int64_t);

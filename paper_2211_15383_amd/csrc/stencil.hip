@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void coarse_kernel(const Cx<R>* __restrict__ A
 template <typename R, int BSX, int BST>
 __global__ __launch_bounds__(256) void sap_kernel(const Cx<R>* __restrict__ U, Cx<R>* __restrict__ x,
                                                   const Cx<R>* __restrict__ b, int Lx, int Lt, R diag, int nrhs,
-                                                  int rb, int color, int mr) {
+                                                  int rb, int color, int mr, int64_t ld) {
   constexpr int BL = BSX * BST;  // lanes per block
   const int64_t V = (int64_t)Lx * Lt;
   const int nbx = Lx / BSX, nbt = Lt / BST;  // nbx even: blocks of one colour are every other block of a row
@@ -194,7 +194,6 @@ __global__ __launch_bounds__(256) void sap_kernel(const Cx<R>* __restrict__ U, C
   const R half = (R)0.5;
   const int r0 = blockIdx.y * rb;
   const int r1 = min(r0 + rb, nrhs);
-  const int64_t ld = 2 * V;
   // x at the site and its four neighbours and b of RHS r + 1 are requested before RHS r
   // is worked on (inactive lanes read site 0 and discard it)
   Spinor<R> xc, fx, bx, ft, bt, bb;
@@ -287,7 +286,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void coarse_gs_kernel(const Cx<R>* __restrict__ A, const Cx<R>* __restrict__ Ainv,
                                                         Cx<R>* __restrict__ x, const Cx<R>* __restrict__ b, int Lx,
                                                         int Lt, int d, int spb, int nrhs, int rb, int color,
-                                                        int even_lx) {
+                                                        int even_lx, int64_t ld) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* res = reinterpret_cast<Cx<R>*>(smem_raw);
   const int64_t V = (int64_t)Lx * Lt;
@@ -310,7 +309,6 @@ __global__ __launch_bounds__(256) void coarse_gs_kernel(const Cx<R>* __restrict_
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
   const Cx<R>* Ab = A + s * 5 * d * d;
-  const int64_t ld = V * d;
   const int r0 = blockIdx.y * rb;
   const int r1 = min(r0 + rb, nrhs);
   for (int r = r0; r < r1; ++r) {
@@ -349,7 +347,7 @@ __global__ __launch_bounds__(256) void coarse_gs_kernel(const Cx<R>* __restrict_
 template <typename R, int RB>
 __global__ __launch_bounds__(256) void restrict_kernel(const Cx<R>* __restrict__ P, const Cx<R>* __restrict__ xf,
                                                        Cx<R>* __restrict__ yc, int Lxf, int Ltf, int df, int ax,
-                                                       int at, int N, int nrhs) {
+                                                       int at, int N, int nrhs, int64_t ldf, int64_t ldc) {
   const int Lxc = Lxf / ax, Ltc = Ltf / at;
   const int64_t Vc = (int64_t)Lxc * Ltc;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (cs, c, k)
@@ -361,7 +359,6 @@ __global__ __launch_bounds__(256) void restrict_kernel(const Cx<R>* __restrict__
   const int h = df / 2;
   const int rows = ax * at * h;
   const Cx<R>* Pb = P + (cs * 2 + c) * (int64_t)rows * N + k;
-  const int64_t ldf = (int64_t)Lxf * Ltf * df, ldc = Vc * 2 * N;
   const int r0 = blockIdx.y * RB;
   const int nr = min(RB, nrhs - r0);
   Cx<R> acc[RB];
@@ -390,7 +387,7 @@ __global__ __launch_bounds__(256) void restrict_kernel(const Cx<R>* __restrict__
 template <typename R, int RB>
 __global__ __launch_bounds__(256) void prolong_kernel(const Cx<R>* __restrict__ P, const Cx<R>* __restrict__ ec,
                                                       Cx<R>* __restrict__ xf, int Lxf, int Ltf, int df, int ax, int at,
-                                                      int N, int nrhs, int add) {
+                                                      int N, int nrhs, int add, int64_t ldf, int64_t ldc) {
   const int64_t nf = (int64_t)Lxf * Ltf * df;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= nf) return;
@@ -405,14 +402,13 @@ __global__ __launch_bounds__(256) void prolong_kernel(const Cx<R>* __restrict__ 
   const int row = ((x % ax) + ax * (t % at)) * h + j;
   const int rows = ax * at * h;
   const Cx<R>* Pr = P + ((cs * 2 + c) * (int64_t)rows + row) * N;
-  const int64_t ldc = Vc * 2 * N;
   const int r0 = blockIdx.y * RB;
   const int nr = min(RB, nrhs - r0);
   const Cx<R>* er = ec + (int64_t)r0 * ldc + cs * 2 * N + c * N;
   Cx<R> acc[RB];
 #pragma unroll
   for (int q = 0; q < RB; ++q)
-    acc[q] = (add && q < nr) ? xf[(int64_t)(r0 + q) * nf + tid] : cmk((R)0, (R)0);
+    acc[q] = (add && q < nr) ? xf[(int64_t)(r0 + q) * ldf + tid] : cmk((R)0, (R)0);
   for (int kk = 0; kk < N; ++kk) {
     const Cx<R> pv = Pr[kk];
 #pragma unroll
@@ -421,7 +417,7 @@ __global__ __launch_bounds__(256) void prolong_kernel(const Cx<R>* __restrict__ 
   }
 #pragma unroll
   for (int q = 0; q < RB; ++q)
-    if (q < nr) xf[(int64_t)(r0 + q) * nf + tid] = acc[q];
+    if (q < nr) xf[(int64_t)(r0 + q) * ldf + tid] = acc[q];
 }
 
 // ---------------------------------------------------------------- matrix-core forms (d = 16, complex FP32)
@@ -631,15 +627,13 @@ template <bool H16>
 __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __restrict__ Av,
                                                                const void* __restrict__ Ainvv, c64* __restrict__ x,
                                                                const c64* __restrict__ b, int Lx, int Lt, int nrhs,
-                                                               int color) {
+                                                               int color, int64_t ld) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t k = xcd_block() * 4 + w;
   const int64_t half = Lx / 2;
   const int64_t t = k / half;
   if (t >= Lt) return;  // wave-uniform
   const int64_t s = 2 * (k % half) + ((t + color) & 1) + t * Lx;
-  const int64_t V = (int64_t)Lx * Lt;
-  const int64_t ld = V * 16;
   const int row = lane & 15, kq = lane >> 4;
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[4] = {nb.xp, nb.xm, nb.tp, nb.tm};
@@ -741,7 +735,7 @@ struct AggMap {
 // all requested before the first product.
 __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restrict__ P, const c64* __restrict__ ec,
                                                              c64* __restrict__ xf, AggMap g, int64_t Vc, int mtw,
-                                                             int nrhs, int add) {
+                                                             int nrhs, int add, int64_t ldf, int64_t ldc) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int groups = g.E / 16 / mtw;
   const int64_t wave = xcd_block() * 4 + w;
@@ -749,8 +743,6 @@ __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restri
   if (cs >= Vc) return;  // wave-uniform
   const int grp = (int)(wave % groups);
   const int row = lane & 15, kq = lane >> 4;
-  const int64_t nf = (int64_t)g.Lxf * (Vc / g.Lxc) * g.at * g.df;
-  const int64_t ldc = Vc * 16;
   // coarse dof 4 kq + t has chirality kq / 2 and test vector 4 (kq % 2) + t
   const int cj = kq >> 1, k0 = 4 * (kq & 1);
   Quad a[4];
@@ -769,7 +761,7 @@ __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restri
   for (int r0 = 0; r0 < nrhs; r0 += 32) {
     const int ra = r0 + row, rb = r0 + 16 + row;
     const bool va = ra < nrhs, vb = rb < nrhs;
-    const int64_t oa = (int64_t)min(ra, nrhs - 1) * nf, ob = (int64_t)min(rb, nrhs - 1) * nf;
+    const int64_t oa = (int64_t)min(ra, nrhs - 1) * ldf, ob = (int64_t)min(rb, nrhs - 1) * ldf;
     // rows beyond nrhs load a valid row and are zeroed (no divergent loads)
     const Quad ea = select_quad(va, load_quad(ec + (int64_t)min(ra, nrhs - 1) * ldc + cs * 16 + 4 * kq));
     const Quad eb = select_quad(vb, load_quad(ec + (int64_t)min(rb, nrhs - 1) * ldc + cs * 16 + 4 * kq));
@@ -812,7 +804,7 @@ __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restri
 // of the wavefronts meet in LDS.  Every wavefront reaches the barriers.
 __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restrict__ P, const c64* __restrict__ xf,
                                                               c64* __restrict__ yc, AggMap g, int64_t Vc, int nrhs,
-                                                              int wpa) {
+                                                              int wpa, int64_t ldf, int64_t ldc) {
   __shared__ f32x4 part[4][4][64];  // [wave][are, aim, bre, bim][lane]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t cs_raw = xcd_block() * (4 / wpa) + w / wpa;
@@ -820,8 +812,6 @@ __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restr
   const int64_t cs = valid ? cs_raw : Vc - 1;
   const int sub = w % wpa;
   const int row = lane & 15, kq = lane >> 4;
-  const int64_t nf = (int64_t)g.Lxf * (Vc / g.Lxc) * g.at * g.df;
-  const int64_t ldc = Vc * 16;
   // A operand: lane (row, kq) supplies conj(P_full[e][row]) for e = 16 kt + 4 kq + t
   const int cj = row >> 3, kj = row & 7;
   const int ntile = g.E / 16;
@@ -829,7 +819,7 @@ __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restr
     const int ra = r0 + row, rb = r0 + 16 + row;
     const bool va = ra < nrhs, vb = rb < nrhs;
     f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
-    const int64_t oa = (int64_t)min(ra, nrhs - 1) * nf, ob = (int64_t)min(rb, nrhs - 1) * nf;
+    const int64_t oa = (int64_t)min(ra, nrhs - 1) * ldf, ob = (int64_t)min(rb, nrhs - 1) * ldf;
     for (int kt0 = sub; kt0 < ntile; kt0 += 4 * wpa) {
       Quad a[4], xa[4], xb[4];
 #pragma unroll
@@ -974,11 +964,12 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
 }
 
 template <typename R>
-void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, bool gamma5_left) {
+void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, bool gamma5_left, int64_t ld) {
+  if (ld <= 0) ld = L.n();
   if (L.fine)
-    launch_wilson<R>(ctx, L, x, y, nrhs, L.n(), L.n(), gamma5_left, nullptr);
+    launch_wilson<R>(ctx, L, x, y, nrhs, ld, ld, gamma5_left, nullptr);
   else
-    launch_coarse<R>(ctx, L, x, y, nrhs, L.n(), L.n(), gamma5_left, nullptr);
+    launch_coarse<R>(ctx, L, x, y, nrhs, ld, ld, gamma5_left, nullptr);
 }
 
 template <typename R>
@@ -990,7 +981,10 @@ void apply_residual(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, const Cx<R>*
 }
 
 template <typename R>
-void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color, int mr_iters) {
+void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color, int mr_iters,
+                int64_t ld) {
+  if (ld <= 0) ld = L.n();
+  REQUIRE(ld >= L.n() && ld % 2 == 0, "SAP vectors need an even stride of at least the level size");
   const Cx<R>* U = std::is_same<R, float>::value ? (const Cx<R>*)L.U32.p : (const Cx<R>*)L.U64.p;
   const int64_t V = L.sites();
   const int rb = std::min(4, rhs_block_for(V, nrhs));  // 4 RHS per thread: more workgroups in flight
@@ -1003,18 +997,21 @@ void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nr
     const int nblk = (L.Lx / 4) * (L.Lt / 4) / 2;  // blocks of one colour
     dim3 grid((unsigned)ceil_div(nblk, 16), (unsigned)ceil_div(nrhs, rb));
     hipLaunchKernelGGL((sap_kernel<R, 4, 4>), grid, dim3(256), 0, ctx->stream, U, x, b, L.Lx, L.Lt,
-                       (R)(L.m0 + 2.0), nrhs, rb, color, mr_iters);
+                       (R)(L.m0 + 2.0), nrhs, rb, color, mr_iters, ld);
   } else {
     const int nblk = (L.Lx / 2) * (L.Lt / 2) / 2;
     dim3 grid((unsigned)ceil_div(nblk, 64), (unsigned)ceil_div(nrhs, rb));
     hipLaunchKernelGGL((sap_kernel<R, 2, 2>), grid, dim3(256), 0, ctx->stream, U, x, b, L.Lx, L.Lt,
-                       (R)(L.m0 + 2.0), nrhs, rb, color, mr_iters);
+                       (R)(L.m0 + 2.0), nrhs, rb, color, mr_iters, ld);
   }
   LAUNCH_CHECK();
 }
 
 template <typename R>
-void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color, bool half) {
+void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color, bool half,
+                      int64_t ld) {
+  if (ld <= 0) ld = L.n();
+  REQUIRE(ld >= L.n(), "Gauss-Seidel vectors need a stride of at least the level size");
   const int d = L.dofs;
   const int spb = std::max(1, 256 / d);
   const int64_t V = L.sites();
@@ -1027,17 +1024,18 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
     // direct form: reads b and the neighbours' x, writes x (three vector passes over the
     // colour's sites) and the four hop blocks and the inverse self block
     REQUIRE(even && L.Lt % 2 == 0, "block Gauss-Seidel needs even extents");
-    REQUIRE(((uintptr_t)x | (uintptr_t)b) % 16 == 0, "matrix-core Gauss-Seidel needs 16-byte aligned vectors");
+    REQUIRE(((uintptr_t)x | (uintptr_t)b) % 16 == 0 && ld % 2 == 0,
+            "matrix-core Gauss-Seidel needs 16-byte aligned vectors");
     const bool h16 = half && L.Ahop16.p && L.Ainv16.p;
     KTimer kt(ctx, "coarse_gs",
               (double)nrhs * (V / 2) * d * 3 * sizeof(Cx<R>) + (double)(V / 2) * 5 * d * d * (h16 ? 4 : sizeof(Cx<R>)));
     if (h16)
       hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
-                         ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color);
+                         ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, ld);
     else
       hipLaunchKernelGGL((coarse16_gs_mfma_kernel<false>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
                          ctx->stream, (const void*)A, (const void*)Ai, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs,
-                         color);
+                         color, ld);
     LAUNCH_CHECK();
     return;
   }
@@ -1047,15 +1045,20 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
   dim3 block((unsigned)(spb * d));
   size_t shm = (size_t)spb * d * sizeof(Cx<R>);
   hipLaunchKernelGGL((coarse_gs_kernel<R>), grid, block, shm, ctx->stream, A, Ai, x, b, L.Lx, L.Lt, d, spb, nrhs,
-                     rb, color, even);
+                     rb, color, even, ld);
   LAUNCH_CHECK();
 }
 
 template <typename R>
-void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc, int nrhs) {
+void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc, int nrhs, int64_t ldf,
+                     int64_t ldc) {
   const Cx<R>* P = std::is_same<R, float>::value ? (const Cx<R>*)L.P32.p : (const Cx<R>*)L.P64.p;
   const int64_t Vc = (int64_t)(L.Lx / L.ax) * (L.Lt / L.at);
   const int64_t threads = Vc * 2 * L.N;
+  if (ldf <= 0) ldf = L.n();
+  if (ldc <= 0) ldc = threads;
+  REQUIRE(ldf >= L.n() && ldc >= threads && ldf % 2 == 0 && ldc % 2 == 0,
+          "restriction vectors need even strides of at least the level sizes");
   KTimer kt(ctx, "restrict",
             (double)nrhs * (L.n() + threads) * sizeof(Cx<R>) + (double)L.n() * L.N * sizeof(Cx<R>));
   if (std::is_same<R, float>::value && transfer16_ok(L)) {
@@ -1063,22 +1066,27 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
     const AggMap g = agg_map(L);
     const int wpa = g.E / 16 >= 4 ? 4 : 1;  // wavefronts per aggregate
     hipLaunchKernelGGL(restrict16_mfma_kernel, dim3((unsigned)ceil_div(Vc, 4 / wpa)), dim3(256), 0, ctx->stream,
-                       (const c64*)P, (const c64*)xf, (c64*)yc, g, Vc, nrhs, wpa);
+                       (const c64*)P, (const c64*)xf, (c64*)yc, g, Vc, nrhs, wpa, ldf, ldc);
     LAUNCH_CHECK();
     return;
   }
   constexpr int RB = 4;
   dim3 grid((unsigned)ceil_div(threads, 256), (unsigned)ceil_div(nrhs, RB));
   hipLaunchKernelGGL((restrict_kernel<R, RB>), grid, dim3(256), 0, ctx->stream, P, xf, yc, L.Lx, L.Lt, L.dofs, L.ax,
-                     L.at, L.N, nrhs);
+                     L.at, L.N, nrhs, ldf, ldc);
   LAUNCH_CHECK();
 }
 
 template <typename R>
-void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, int nrhs, bool add) {
+void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, int nrhs, bool add, int64_t ldc,
+                    int64_t ldf) {
   const Cx<R>* P = std::is_same<R, float>::value ? (const Cx<R>*)L.P32.p : (const Cx<R>*)L.P64.p;
   const int64_t nf = L.n();
   const int64_t nc = (int64_t)(L.Lx / L.ax) * (L.Lt / L.at) * 2 * L.N;
+  if (ldf <= 0) ldf = nf;
+  if (ldc <= 0) ldc = nc;
+  REQUIRE(ldf >= nf && ldc >= nc && ldf % 2 == 0 && ldc % 2 == 0,
+          "prolongation vectors need even strides of at least the level sizes");
   KTimer kt(ctx, "prolong",
             (double)nrhs * ((add ? 2 : 1) * nf + nc) * sizeof(Cx<R>) + (double)nf * L.N * sizeof(Cx<R>));
   if (std::is_same<R, float>::value && transfer16_ok(L)) {
@@ -1089,14 +1097,14 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
     const int64_t Vc = nc / 16;
     const int64_t waves = Vc * (tiles / mtw);
     hipLaunchKernelGGL(prolong16_mfma_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, ctx->stream,
-                       (const c64*)P, (const c64*)ec, (c64*)xf, g, Vc, mtw, nrhs, add ? 1 : 0);
+                       (const c64*)P, (const c64*)ec, (c64*)xf, g, Vc, mtw, nrhs, add ? 1 : 0, ldf, ldc);
     LAUNCH_CHECK();
     return;
   }
   constexpr int RB = 4;
   dim3 grid((unsigned)ceil_div(nf, 256), (unsigned)ceil_div(nrhs, RB));
   hipLaunchKernelGGL((prolong_kernel<R, RB>), grid, dim3(256), 0, ctx->stream, P, ec, xf, L.Lx, L.Lt, L.dofs, L.ax,
-                     L.at, L.N, nrhs, add ? 1 : 0);
+                     L.at, L.N, nrhs, add ? 1 : 0, ldf, ldc);
   LAUNCH_CHECK();
 }
 
@@ -1105,11 +1113,11 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
                                  const Cx<R>*);                                                                  \
   template void launch_coarse<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, int64_t, int64_t, bool,     \
                                  const Cx<R>*);                                                                  \
-  template void apply_op<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, bool);                        \
+  template void apply_op<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, bool, int64_t);               \
   template void apply_residual<R>(dmlmc_ctx*, const Level&, const Cx<R>*, const Cx<R>*, Cx<R>*, int);          \
-  template void launch_sap<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int, int);                  \
-  template void launch_coarse_gs<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int, bool);           \
-  template void launch_restrict<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int);                       \
-  template void launch_prolong<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, bool);
+  template void launch_sap<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int, int, int64_t);         \
+  template void launch_coarse_gs<R>(dmlmc_ctx*, const Level&, Cx<R>*, const Cx<R>*, int, int, bool, int64_t);  \
+  template void launch_restrict<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, int64_t, int64_t);     \
+  template void launch_prolong<R>(dmlmc_ctx*, const Level&, const Cx<R>*, Cx<R>*, int, bool, int64_t, int64_t);
 INST(float)
 INST(double)
