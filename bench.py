@@ -91,27 +91,28 @@ def copy_ceiling(torch, nbytes: int = 1 << 30, reps: int = 10) -> float:
 
 
 def kernel_rates(torch, dm, ctx, H, nlev: int, b: int, reps: int = 10):
-    """Each stencil-class kernel alone at the workload's real shapes (b RHS, complex FP32),
-    reps launches after one warm-up: algorithmic bytes per launch / mean event time."""
+    """Each stencil-class kernel alone at the workload's real shapes (b RHS, complex FP32,
+    rows at the solver's padded work stride), reps launches after one warm-up: algorithmic
+    bytes per launch / mean event time."""
     out = {}
     ctx.timing_select(None)
     ctx.timing(True)
     dev = "cuda:0"
     for l in range(1, nlev):
-        n, nc = H.n(l), H.n(l + 1)
-        x = torch.randn(b, n, dtype=torch.complex64, device=dev)
-        y = torch.randn(b, n, dtype=torch.complex64, device=dev)
-        xc = torch.randn(b, nc, dtype=torch.complex64, device=dev)
+        ld, ldc = H.work_stride(l), H.work_stride(l + 1)
+        x = torch.randn(b, ld, dtype=torch.complex64, device=dev)
+        y = torch.randn(b, ld, dtype=torch.complex64, device=dev)
+        xc = torch.randn(b, ldc, dtype=torch.complex64, device=dev)
         yc = torch.empty_like(xc)
-        cases = [("wilson" if l == 1 else "coarse", dm.OP_D, x, y, 0),
-                 ("restrict", dm.OP_RESTRICT, x, yc, 0),
-                 ("prolong", dm.OP_PROLONG, xc, y, 0),
-                 ("sap" if l == 1 else "coarse_gs", dm.OP_SMOOTH, x, y, 1)]
-        for cls, op, a, o, arg in cases:
-            H.apply(op, l, a, o, dm.MIXED, arg)
+        cases = [("wilson" if l == 1 else "coarse", dm.OP_D, x, y, ld, ld, 0),
+                 ("restrict", dm.OP_RESTRICT, x, yc, ld, ldc, 0),
+                 ("prolong", dm.OP_PROLONG, xc, y, ldc, ld, 0),
+                 ("sap" if l == 1 else "coarse_gs", dm.OP_SMOOTH, x, y, ld, ld, 1)]
+        for cls, op, a, o, lda, ldo, arg in cases:
+            H.apply(op, l, a, o, dm.MIXED, arg, ld_in=lda, ld_out=ldo)
             ctx.timing_reset()
             for _ in range(reps):
-                H.apply(op, l, a, o, dm.MIXED, arg)
+                H.apply(op, l, a, o, dm.MIXED, arg, ld_in=lda, ld_out=ldo)
             nl, ms, by = ctx.timing_get(cls)
             out[f"{cls}_level{l}"] = {"launches": nl, "avg_us": 1e3 * ms / max(1, nl),
                                       "bytes_per_launch": by / max(1, nl),

@@ -110,6 +110,13 @@ void dmlmc_free_hierarchy(dmlmc_hier *h);
 /* Level geometry: lattice extents and dofs per site of level `level`. */
 dmlmc_status dmlmc_level_info(const dmlmc_hier *h, int level, int *Lx, int *Lt, int *dofs);
 
+/* Stride (in complex entries) between consecutive right-hand sides of the solver's
+ * internal work vectors on level `level`: the level size n, plus 256 below the coarsest
+ * level once n >= 4096 (at power-of-two level sizes the same entry of consecutive RHS
+ * would otherwise fall on the same HBM channels).  Vectors passed through this interface
+ * are [nrhs][n] unless an entry point takes strides.  Errors: EINVAL. */
+dmlmc_status dmlmc_work_stride(const dmlmc_hier *h, int level, int64_t *ld);
+
 /* Copies level data to host buffers (any of them may be NULL):
  *   P_host:  complex128 [n_level][n_{level+1}] dense row-major interpolator P_level
  *            (level < L; zero outside the aggregate blocks);
@@ -320,6 +327,15 @@ enum {
 };
 dmlmc_status dmlmc_apply(dmlmc_ctx *ctx, const dmlmc_hier *h, int op, int level, const void *in,
                          void *out, int nrhs, dmlmc_precision prec, uint64_t arg);
+
+/* dmlmc_apply with the vectors' strides given: RHS r of in at r * ld_in, of out at
+ * r * ld_out (complex entries; 0 stands for n of the vector's level).  Entries between n
+ * and the stride are neither read nor written.  Strides must be even and at least n;
+ * DMLMC_OP_SMOOTH and DMLMC_OP_VCYCLE need ld_in == ld_out, the DMLMC_OP_DEFL_* operators
+ * unpadded vectors.  Errors: as dmlmc_apply. */
+dmlmc_status dmlmc_apply_strided(dmlmc_ctx *ctx, const dmlmc_hier *h, int op, int level, const void *in,
+                                 int64_t ld_in, void *out, int64_t ld_out, int nrhs, dmlmc_precision prec,
+                                 uint64_t arg);
 
 /* Writes the real Z2 noise vectors of samples sample0 .. sample0 + nrhs - 1 of level
  * `level` (length n each, [nrhs][n], device, complex128 for DMLMC_FP64 / complex64 for

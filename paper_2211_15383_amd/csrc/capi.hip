@@ -586,8 +586,9 @@ dmlmc_status dmlmc_z2_noise(dmlmc_ctx* ctx, int64_t n, uint64_t seed, int level,
   });
 }
 
-dmlmc_status dmlmc_apply(dmlmc_ctx* ctx, const dmlmc_hier* h, int op, int level, const void* in, void* out, int nrhs,
-                         dmlmc_precision prec, uint64_t arg) {
+dmlmc_status dmlmc_apply_strided(dmlmc_ctx* ctx, const dmlmc_hier* h, int op, int level, const void* in,
+                                 int64_t ld_in, void* out, int64_t ld_out, int nrhs, dmlmc_precision prec,
+                                 uint64_t arg) {
   if (!ctx) return DMLMC_EINVAL;
   return guarded(ctx, [&]() {
     check_hier(ctx, h);
@@ -598,39 +599,59 @@ dmlmc_status dmlmc_apply(dmlmc_ctx* ctx, const dmlmc_hier* h, int op, int level,
     const Level& L = H->lv[level - 1];
     const int Lmax = (int)H->lv.size();
     const bool f32 = prec == DMLMC_MIXED;
+    const int64_t n = L.n();
+    const int64_t nc = level < Lmax ? H->lv[level].n() : 0;
+    // the level each vector lives on
+    const int64_t n_in = op == DMLMC_OP_PROLONG ? nc : n;
+    const int64_t n_out = op == DMLMC_OP_RESTRICT ? nc : n;
+    if (op == DMLMC_OP_RESTRICT || op == DMLMC_OP_PROLONG)
+      REQUIRE(level < Lmax, "no transfer below the coarsest level");
+    if (ld_in == 0) ld_in = n_in;
+    if (ld_out == 0) ld_out = n_out;
+    REQUIRE(ld_in >= n_in && ld_out >= n_out && ld_in % 2 == 0 && ld_out % 2 == 0,
+            "strides must be even and at least the vector length");
     switch (op) {
       case DMLMC_OP_D:
-      case DMLMC_OP_GAMMA5_D:
-        if (f32) apply_op<float>(ctx, L, (const c64*)in, (c64*)out, nrhs, op == DMLMC_OP_GAMMA5_D);
-        else apply_op<double>(ctx, L, (const c128*)in, (c128*)out, nrhs, op == DMLMC_OP_GAMMA5_D);
+      case DMLMC_OP_GAMMA5_D: {
+        const bool g5 = op == DMLMC_OP_GAMMA5_D;
+        if (L.fine) {
+          if (f32) launch_wilson<float>(ctx, L, (const c64*)in, (c64*)out, nrhs, ld_in, ld_out, g5);
+          else launch_wilson<double>(ctx, L, (const c128*)in, (c128*)out, nrhs, ld_in, ld_out, g5);
+        } else {
+          if (f32) launch_coarse<float>(ctx, L, (const c64*)in, (c64*)out, nrhs, ld_in, ld_out, g5);
+          else launch_coarse<double>(ctx, L, (const c128*)in, (c128*)out, nrhs, ld_in, ld_out, g5);
+        }
         break;
+      }
       case DMLMC_OP_RESTRICT:
-        REQUIRE(level < Lmax, "no restriction from the coarsest level");
-        if (f32) launch_restrict<float>(ctx, L, (const c64*)in, (c64*)out, nrhs);
-        else launch_restrict<double>(ctx, L, (const c128*)in, (c128*)out, nrhs);
+        if (f32) launch_restrict<float>(ctx, L, (const c64*)in, (c64*)out, nrhs, ld_in, ld_out);
+        else launch_restrict<double>(ctx, L, (const c128*)in, (c128*)out, nrhs, ld_in, ld_out);
         break;
       case DMLMC_OP_PROLONG:
-        REQUIRE(level < Lmax, "no prolongation to below the coarsest level");
-        if (f32) launch_prolong<float>(ctx, L, (const c64*)in, (c64*)out, nrhs, false);
-        else launch_prolong<double>(ctx, L, (const c128*)in, (c128*)out, nrhs, false);
+        if (f32) launch_prolong<float>(ctx, L, (const c64*)in, (c64*)out, nrhs, false, ld_in, ld_out);
+        else launch_prolong<double>(ctx, L, (const c128*)in, (c128*)out, nrhs, false, ld_in, ld_out);
         break;
       case DMLMC_OP_SMOOTH:
         REQUIRE(level < Lmax, "the coarsest level has no smoother");
         REQUIRE(arg >= 1 && arg <= 1000, "sweeps must be in 1..1000");
-        if (f32) smooth<float>(H, level, (c64*)out, (const c64*)in, nrhs, (int)arg);
-        else smooth<double>(H, level, (c128*)out, (const c128*)in, nrhs, (int)arg);
+        REQUIRE(ld_in == ld_out, "the smoother takes one stride for b and x");
+        if (f32) smooth<float>(H, level, (c64*)out, (const c64*)in, nrhs, (int)arg, ld_in);
+        else smooth<double>(H, level, (c128*)out, (const c128*)in, nrhs, (int)arg, ld_in);
         break;
       case DMLMC_OP_VCYCLE:
-        if (f32) vcycle<float>(H, level, (const c64*)in, (c64*)out, nrhs);
-        else vcycle<double>(H, level, (const c128*)in, (c128*)out, nrhs);
+        REQUIRE(ld_in == ld_out, "the V-cycle takes one stride for its input and output");
+        REQUIRE(level < Lmax || ld_in == n, "coarsest-level vectors are unpadded");
+        if (f32) vcycle<float>(H, level, (const c64*)in, (c64*)out, nrhs, ld_in);
+        else vcycle<double>(H, level, (const c128*)in, (c128*)out, nrhs, ld_in);
         break;
       case DMLMC_OP_DEFL_C:
       case DMLMC_OP_DEFL_P: {
+        // DMLMC_OP_DEFL_C writes [nrhs][k] coefficients, not a level vector
+        REQUIRE(ld_in == n && (op == DMLMC_OP_DEFL_C || ld_out == n), "the deflation operators take unpadded vectors");
         const dmlmc_defl* D = H->attached;
         REQUIRE(D != nullptr, "no deflation attached (dmlmc_set_deflation)");
         REQUIRE(D->level == level, "attached deflation is for another level");
         // complex128 vectors for both precisions; prec selects FP64 or FP32 matrix-core kernels
-        const int64_t n = L.n();
         c128* C = (c128*)hier_buf(H, "api_C", level, sizeof(c128) * (size_t)D->k * nrhs);
         if (f32) defl_coeffs_mfma(ctx, D, (const c128*)in, nrhs, n, C, hier_devbuf(H, "api_part", level));
         else defl_coeffs_fp64(ctx, D, (const c128*)in, nrhs, n, C);
@@ -649,6 +670,17 @@ dmlmc_status dmlmc_apply(dmlmc_ctx* ctx, const dmlmc_hier* h, int op, int level,
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
   });
+}
+
+dmlmc_status dmlmc_apply(dmlmc_ctx* ctx, const dmlmc_hier* h, int op, int level, const void* in, void* out, int nrhs,
+                         dmlmc_precision prec, uint64_t arg) {
+  return dmlmc_apply_strided(ctx, h, op, level, in, 0, out, 0, nrhs, prec, arg);
+}
+
+dmlmc_status dmlmc_work_stride(const dmlmc_hier* h, int level, int64_t* ld) {
+  if (!h || !ld || level < 1 || level > (int)h->lv.size()) return DMLMC_EINVAL;
+  *ld = work_ld(h, level);
+  return DMLMC_OK;
 }
 
 dmlmc_status dmlmc_timing_enable(dmlmc_ctx* ctx, int enable) {

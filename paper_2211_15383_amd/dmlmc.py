@@ -25,7 +25,7 @@ OP_D, OP_RESTRICT, OP_PROLONG, OP_SMOOTH, OP_VCYCLE, OP_DEFL_C, OP_DEFL_P, OP_GA
 
 EXPORTED = [
     "dmlmc_create", "dmlmc_destroy", "dmlmc_last_error", "dmlmc_version", "dmlmc_build_hierarchy",
-    "dmlmc_free_hierarchy", "dmlmc_level_info", "dmlmc_export_level", "dmlmc_deflate", "dmlmc_deflate_difference",
+    "dmlmc_free_hierarchy", "dmlmc_level_info", "dmlmc_work_stride", "dmlmc_apply_strided", "dmlmc_export_level", "dmlmc_deflate", "dmlmc_deflate_difference",
     "dmlmc_free_deflation", "dmlmc_deflation_info", "dmlmc_export_deflation", "dmlmc_solve_multi_rhs", "dmlmc_mlmc_trace",
     "dmlmc_hutchinson_trace",
     "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_set_solver_params",
@@ -99,6 +99,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_mlmc_trace": (i32, [vp, vp, vp, C.POINTER(MLMCParams), C.POINTER(TraceResult)]),
         "dmlmc_hutchinson_trace": (i32, [vp, vp, vp, vp, C.POINTER(MLMCParams), C.POINTER(TraceResult)]),
         "dmlmc_apply": (i32, [vp, vp, i32, i32, vp, vp, i32, i32, u64]),
+        "dmlmc_apply_strided": (i32, [vp, vp, i32, i32, vp, i64, vp, i64, i32, i32, u64]),
+        "dmlmc_work_stride": (i32, [vp, i32, C.POINTER(i64)]),
         "dmlmc_set_deflation": (i32, [vp, vp]),
         "dmlmc_z2_noise": (i32, [vp, i64, u64, i32, i64, i32, vp, i32]),
         "dmlmc_set_solver_params": (i32, [vp, C.POINTER(SolverParams)]),
@@ -129,6 +131,13 @@ def lib() -> C.CDLL:
 
 
 def _ptr(t) -> int:
+    """Device address of a tensor handed to the library.  The library enqueues on its own
+    stream when torch runs on the default one, so torch's pending work on t's device (which
+    may still be writing t) is waited for before the address is passed on."""
+    if t.is_cuda:
+        import torch
+
+        torch.cuda.current_stream(t.device).synchronize()
     return t.data_ptr()
 
 
@@ -281,11 +290,25 @@ class Hierarchy:
         return dc // 2
 
     # ---------------------------------------------------------------- operators
-    def apply(self, op: int, level: int, x, out, prec: int = FP64, arg: int = 0):
+    def apply(self, op: int, level: int, x, out, prec: int = FP64, arg: int = 0, ld_in: int = 0, ld_out: int = 0):
+        """ld_in / ld_out: strides between the RHS of x / out in complex entries (0: the
+        vector's level size); with both 0 this is dmlmc_apply, else dmlmc_apply_strided."""
         nrhs = x.shape[0] if op != OP_PROLONG else out.shape[0]
-        self.ctx.check(lib().dmlmc_apply(self.ctx.h, self.h, op, level, C.c_void_p(_ptr(x)),
-                                         C.c_void_p(_ptr(out)), nrhs, prec, arg))
+        if ld_in == 0 and ld_out == 0:
+            self.ctx.check(lib().dmlmc_apply(self.ctx.h, self.h, op, level, C.c_void_p(_ptr(x)),
+                                             C.c_void_p(_ptr(out)), nrhs, prec, arg))
+        else:
+            self.ctx.check(lib().dmlmc_apply_strided(self.ctx.h, self.h, op, level, C.c_void_p(_ptr(x)), ld_in,
+                                                     C.c_void_p(_ptr(out)), ld_out, nrhs, prec, arg))
         return out
+
+    def work_stride(self, level: int) -> int:
+        """Stride between RHS of the solver's internal work vectors on `level`."""
+        ld = C.c_int64()
+        st = lib().dmlmc_work_stride(self.h, level, C.byref(ld))
+        if st != OK:
+            raise DmlmcError(st, "dmlmc_work_stride failed")
+        return ld.value
 
     def solve(self, level: int, B, prec: int = FP64, rtol: float = 1e-10, maxiter: int = 2000, proj=None):
         torch = self.ctx.torch
