@@ -5,6 +5,10 @@ Every operator called on RHS blocks padded that way must give bit-identical resu
 the unpadded call (the arithmetic is the same, only the addresses move), and must neither
 read nor write the padding: NaN planted in the pads of the input does not leak into the
 result, and NaN planted in the pads of the output stays where it is.
+
+The padded inputs are made by device-side fills and copies that may still be pending on
+torch's stream when the library is called, so this also checks that every library call
+is ordered after torch's pending work (the binding waits for it before passing a tensor).
 """
 import pytest
 
