@@ -28,13 +28,13 @@ METRIC = "time to 1e-2 rel. trace error, mixed+batched vs FP64 (s); stencil HBM 
 HBM_PEAK_GBPS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_CLASSES = ("wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong", "gs_dots", "gs_update",
-               "coarse_direct16")
+               "coarse_direct16", "coarse_direct8")
 STENCIL_CLASSES = ("wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong")
 # source file of each timed kernel class (a recorded HBM traffic figure is only valid for the
 # source it was measured on)
 CLASS_SOURCE = {"wilson": "stencil.hip", "coarse": "stencil.hip", "sap": "stencil.hip", "coarse_gs": "stencil.hip",
                 "restrict": "stencil.hip", "prolong": "stencil.hip", "gs_dots": "gram.hip", "gs_update": "gram.hip",
-                "coarse_direct16": "dense.hip"}
+                "coarse_direct16": "dense.hip", "coarse_direct8": "dense.hip"}
 
 
 def log(msg):
@@ -243,9 +243,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="schwinger1024")
-    ap.add_argument("--direct", choices=("fp16", "fp32", "off"), default="fp16",
+    ap.add_argument("--direct", choices=("fp16", "fp32", "fp8", "off"), default="fp16",
                     help="coarsest solve inside the complex-FP32 V-cycles: explicit inverse applied in "
-                         "FP16 or FP32, or the iterative deflated GMRES")
+                         "FP16, FP32 or the 8-bit form, or the iterative deflated GMRES")
     ap.add_argument("--skip-fp64", action="store_true", help="skip the FP64 single-RHS baseline run")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU checker baseline")
     ap.add_argument("--cpu-workload", default="schwinger128")
@@ -288,7 +288,8 @@ def main():
     t_eig = time.perf_counter() - t0
     log(f"deflation k={W.k_defl} in {t_eig:.2f} s, tr_defl {D.tr_defl:.6f}, {D.info()}")
     t0 = time.perf_counter()
-    direct_mode = {"fp16": dmlmc.DIRECT_FP16, "fp32": dmlmc.DIRECT_FP32, "off": dmlmc.DIRECT_OFF}[args.direct]
+    direct_mode = {"fp16": dmlmc.DIRECT_FP16, "fp32": dmlmc.DIRECT_FP32, "fp8": dmlmc.DIRECT_FP8,
+                   "off": dmlmc.DIRECT_OFF}[args.direct]
     if direct_mode != dmlmc.DIRECT_OFF:  # explicit coarsest inverse for the complex-FP32 coarsest solves
         H.coarsest_direct(D, direct_mode)
     torch.cuda.synchronize()
@@ -389,6 +390,7 @@ def main():
 
     coarsest = {"fp16": "explicit inverse applied in complex FP16 (FP32 accumulation)",
                 "fp32": "explicit inverse applied in complex FP32",
+                "fp8": "explicit inverse applied from an 8-bit (E4M3, row-scaled) copy (FP32 accumulation)",
                 "off": "deflated fixed-count GMRES"}[args.direct]
     out = {
         "metric": METRIC,

@@ -281,10 +281,18 @@ dmlmc_status dmlmc_deflate_difference(dmlmc_ctx *ctx, dmlmc_hier *h, int a, int 
  *   enable = 2: applied from a complex-FP16 copy (n_L^2 * 4 more bytes, made on first
  *               use; one power-of-two scale for the matrix and one per RHS, FP32
  *               accumulation): each coarsest solve is then accurate to ~1e-3 relative,
- *               half the bytes and half the matrix-core instructions of enable = 1.
+ *               half the bytes and half the matrix-core instructions of enable = 1;
+ *   enable = 3: applied from an 8-bit copy (n_L^2 * 2 more bytes, made on first use):
+ *               each component is a byte of sign, 4 exponent bits (bias 7) and 3
+ *               mantissa bits, nearest with ties to even, after its row is scaled by a
+ *               power of two that brings the row's largest component below 256.  In the
+ *               kernel a byte is widened exactly to FP16, and the products run as for
+ *               enable = 2.  Each coarsest solve is then accurate to a few percent
+ *               (2^-4 relative rounding per entry), with a quarter of the bytes of
+ *               enable = 1.
  * Every solve still stops at its FP64 residual tolerance, so the precision changes
  * iteration counts only.  enable = 0 returns to the iterative coarsest solve and frees
- * both inverses.  Needs a coarse coarsest level with 16 dofs per site and
+ * every inverse.  Needs a coarse coarsest level with 16 dofs per site and
  * n_L <= 65536, n_L a multiple of 256 (EINVAL otherwise); ENOCONV if a column solve
  * fails, ENUMERIC if the inverse holds NaN/Inf.  The FP64 solver path is unaffected. */
 dmlmc_status dmlmc_coarsest_direct(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_defl *coarsest, int enable);

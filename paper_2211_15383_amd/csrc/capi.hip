@@ -484,7 +484,7 @@ dmlmc_status dmlmc_coarsest_direct(dmlmc_ctx* ctx, dmlmc_hier* h, const dmlmc_de
   if (!ctx) return DMLMC_EINVAL;
   return guarded(ctx, [&]() {
     check_hier(ctx, h);
-    REQUIRE(enable >= 0 && enable <= 2, "enable must be 0, 1 or 2");
+    REQUIRE(enable >= 0 && enable <= 3, "enable must be 0, 1, 2 or 3");
     if (coarsest) {
       if (coarsest->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
       REQUIRE(coarsest->kind == 0 && coarsest->level == (int)h->lv.size(), "deflation must be of the coarsest level");
@@ -493,11 +493,14 @@ dmlmc_status dmlmc_coarsest_direct(dmlmc_ctx* ctx, dmlmc_hier* h, const dmlmc_de
       h->coarse_direct_mode = 0;
       h->coarse_dinv.release();
       h->coarse_dinv16.release();
+      h->coarse_dinv8.release();
+      h->coarse_dinv8_rows.release();
       h->coarse_dinv_n = 0;
       return;
     }
     if (h->coarse_dinv_n == 0) build_coarse_direct(h, coarsest);
     if (enable == 2 && h->coarse_dinv16.p == nullptr) build_coarse_direct16(h);
+    if (enable == 3 && h->coarse_dinv8.p == nullptr) build_coarse_direct8(h);
     h->coarse_direct_mode = enable;
   });
 }

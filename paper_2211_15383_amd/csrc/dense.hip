@@ -200,6 +200,88 @@ __global__ __launch_bounds__(256) void dense16_apply_kernel(const uint32_t* __re
   }
 }
 
+// 8-bit form of the inverse: a byte holds sign, exponent (4 bits, bias 7) and mantissa (3
+// bits), the OCP E4M3 layout that gfx950's FP8 -> FP16 conversion reads (checked against
+// every byte pattern on the device).  One conversion widens the two bytes of a complex
+// entry to its complex-FP16 word exactly (values below 256, subnormals included).
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void widen8(uint32_t w, uint32_t& lo, uint32_t& hi) {
+  lo = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w, 1.0f, false));
+  hi = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w, 1.0f, true));
+}
+
+// As dense16_apply_kernel with the inverse in the 8-bit form: lane (row, g) reads the 16
+// bytes of complex entries j0 + 32 q + 8 g .. + 7 of its rows and widens them to the same
+// FP16 fragments; the row factors are applied in the reduction.
+template <int TI>
+__global__ __launch_bounds__(256) void dense8_apply_kernel(const uint32_t* __restrict__ Dinv8,
+                                                           const uint32_t* __restrict__ B, c64* __restrict__ part,
+                                                           int64_t n, int nrhs, int KS) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t grp = (int64_t)blockIdx.x * 4 + w;
+  if (grp * 16 * TI >= n) return;  // wave-uniform
+  const int ks = blockIdx.y;
+  const int64_t i0 = grp * 16 * TI;
+  const int64_t kc = n / KS;
+  const int64_t j0 = ks * kc;
+  const int row = lane & 15, g = lane >> 4;
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  for (int r0 = 0; r0 < nrhs; r0 += 32) {
+    const int ra = r0 + row, rb = r0 + 16 + row;
+    const bool va = ra < nrhs, vb = rb < nrhs;
+    const u32x4* Ba = reinterpret_cast<const u32x4*>(B + (int64_t)min(ra, nrhs - 1) * n + j0 + 8 * g);
+    const u32x4* Bb = reinterpret_cast<const u32x4*>(B + (int64_t)min(rb, nrhs - 1) * n + j0 + 8 * g);
+    // one 32-bit word holds two complex entries: row i starts at word i n / 2
+    const u32x4* Ar[TI];
+#pragma unroll
+    for (int t = 0; t < TI; ++t)
+      Ar[t] = reinterpret_cast<const u32x4*>(Dinv8 + ((i0 + 16 * t + row) * n + j0 + 8 * g) / 2);
+    f32x4 are[TI], aim[TI], bre[TI], bim[TI];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) are[t] = aim[t] = bre[t] = bim[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int steps = (int)(kc / 32);
+    for (int q = 0; q < steps; ++q) {
+      u32x4 xa[2], xb[2], a8[TI];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        xa[u] = Ba[8 * q + u];
+        xb[u] = Bb[8 * q + u];
+      }
+#pragma unroll
+      for (int t = 0; t < TI; ++t) a8[t] = Ar[t][4 * q];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        // rows beyond nrhs read a valid row and contribute zeros
+        const u32x4 pa = va ? xa[u] : zero, pb = vb ? xb[u] : zero;
+        const half8 a_re = as_half8(pa ^ 0x80000000u), a_im = as_half8((pa >> 16) | (pa << 16));
+        const half8 b_re = as_half8(pb ^ 0x80000000u), b_im = as_half8((pb >> 16) | (pb << 16));
+#pragma unroll
+        for (int t = 0; t < TI; ++t) {
+          uint32_t w0, w1, w2, w3;
+          widen8(u == 0 ? a8[t].x : a8[t].z, w0, w1);
+          widen8(u == 0 ? a8[t].y : a8[t].w, w2, w3);
+          const u32x4 wv = {w0, w1, w2, w3};
+          const half8 m = as_half8(wv);
+          are[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(m, a_re, are[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(m, a_im, aim[t], 0, 0, 0);
+          bre[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(m, b_re, bre[t], 0, 0, 0);
+          bim[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(m, b_im, bim[t], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      c64* pa = part + ((int64_t)ks * nrhs + min(ra, nrhs - 1)) * n + i0 + 16 * t + 4 * g;
+      c64* pb = part + ((int64_t)ks * nrhs + min(rb, nrhs - 1)) * n + i0 + 16 * t + 4 * g;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (va) pa[v] = cmk(are[t][v], aim[t][v]);
+        if (vb) pb[v] = cmk(bre[t][v], bim[t][v]);
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ float block_max_1024(float m, float* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
@@ -229,8 +311,10 @@ __global__ __launch_bounds__(1024) void dense16_rhs_kernel(const c64* __restrict
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) o[i] = pack_half2(s * b[i].x, s * b[i].y);
 }
 
+// Y[r][i] = rs[r] (rows ? rows[i] : 1) sum_k part[k][r][i]
 __global__ void dense16_reduce_kernel(const c64* __restrict__ part, int KS, int64_t n, int64_t m,
-                                      const float* __restrict__ rs, c64* __restrict__ Y) {
+                                      const float* __restrict__ rs, const float* __restrict__ rows,
+                                      c64* __restrict__ Y) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m) return;
   float sx = 0.f, sy = 0.f;
@@ -239,7 +323,7 @@ __global__ void dense16_reduce_kernel(const c64* __restrict__ part, int KS, int6
     sx += v.x;
     sy += v.y;
   }
-  const float f = rs[e / n];
+  const float f = rows ? rs[e / n] * rows[e % n] : rs[e / n];
   Y[e] = cmk(f * sx, f * sy);
 }
 
@@ -257,6 +341,49 @@ __global__ __launch_bounds__(1024) void absmax_partial_kernel(const c64* __restr
 __global__ void to_half_kernel(const c64* __restrict__ A, int64_t m, float s, uint32_t* __restrict__ A16) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
     A16[i] = pack_half2(s * A[i].x, s * A[i].y);
+}
+
+// Nearest 8-bit float (sign, 4 exponent bits with bias 7, 3 mantissa bits, ties to even)
+// for |q| < 256: normal numbers 2^(F-7) (1 + m/8) for exponent field F = 1..14, subnormal
+// numbers m/8 2^-6 for F = 0.
+__device__ __forceinline__ uint32_t encode8(float q) {
+  const uint32_t sign = q < 0.f ? 0x80u : 0u;
+  const float a = fabsf(q);
+  if (!(a >= 0x1p-10f)) return sign;  // below half the smallest subnormal 2^-9 (or NaN)
+  int e;
+  frexpf(a, &e);  // a = f 2^e, 0.5 <= f < 1
+  int E = e - 1;  // a = (2f) 2^E
+  if (E < -6) {
+    const int mant = (int)rintf(a * 512.f);  // units of 2^-9
+    return sign | (uint32_t)mant;            // mant = 8 is the smallest normal number
+  }
+  int mant = (int)rintf((ldexpf(a, -E) - 1.f) * 8.f);
+  if (mant == 8) {
+    mant = 0;
+    ++E;
+  }
+  const int F = min(E + 7, 15);
+  return sign | ((uint32_t)F << 3) | (uint32_t)(F == 15 ? min(mant, 6) : mant);
+}
+
+// one workgroup per row i: e_i with max |component| < 2^e_i, A8 row = 8-bit form of
+// A_i 2^(8 - e_i) (every component below 256), rows[i] = 2^(e_i - 8)
+__global__ __launch_bounds__(1024) void to_fp8_rows_kernel(const c64* __restrict__ A, int64_t n,
+                                                           uint16_t* __restrict__ A8, float* __restrict__ rows) {
+  __shared__ float red[16];
+  const int64_t i = blockIdx.x;
+  const c64* a = A + i * n;
+  float m = 0.f;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) m = fmaxf(m, fmaxf(fabsf(a[j].x), fabsf(a[j].y)));
+  m = block_max_1024(m, red);
+  int e = 0;
+  if (m > 0.f && isfinite(m)) frexpf(m, &e);
+  e = min(max(e, -100), 100);
+  const float s = ldexpf(1.f, 8 - e);
+  if (threadIdx.x == 0) rows[i] = ldexpf(1.f, e - 8);
+  uint16_t* o = A8 + i * n;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
+    o[j] = (uint16_t)(encode8(s * a[j].x) | (encode8(s * a[j].y) << 8));
 }
 
 // E[r][i] = 1 if i == c0 + r else 0 (unit vectors of columns c0 .. c0 + nb - 1)
@@ -291,6 +418,8 @@ constexpr int KSPLIT = 16;
 constexpr int TILES = 2;     // row tiles of 16 per wavefront
 constexpr int KSPLIT16 = 4;  // FP16 form: contraction split and row tiles per wavefront
 constexpr int TILES16 = 4;
+constexpr int KSPLIT8 = 8;  // 8-bit form (4 .. 16 measure alike)
+constexpr int TILES8 = 4;
 
 }  // namespace
 
@@ -301,7 +430,8 @@ void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl) {
   const int64_t n = C.n();
   REQUIRE(!C.fine && C.dofs == 16, "the direct coarsest solve needs a coarse level with 16 dofs per site");
   REQUIRE(n <= 65536, "the coarsest level is too large for an explicit inverse (n > 65536)");
-  REQUIRE(n % (16 * KSPLIT) == 0 && n % (16 * TILES) == 0 && n % (32 * KSPLIT16) == 0 && n % (16 * TILES16) == 0,
+  REQUIRE(n % (16 * KSPLIT) == 0 && n % (16 * TILES) == 0 && n % (32 * KSPLIT16) == 0 && n % (16 * TILES16) == 0 &&
+              n % (32 * KSPLIT8) == 0 && n % (16 * TILES8) == 0,
           "the coarsest dimension must be a multiple of 256");
   struct Restore {
     dmlmc_hier* H;
@@ -331,6 +461,8 @@ void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl) {
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   H->coarse_dinv16.release();
+  H->coarse_dinv8.release();
+  H->coarse_dinv8_rows.release();
   H->coarse_dinv_n = n;
 }
 
@@ -364,26 +496,45 @@ void build_coarse_direct16(dmlmc_hier* H) {
   H->coarse_dinv16_unscale = std::ldexp(1.f, e);
 }
 
+void build_coarse_direct8(dmlmc_hier* H) {
+  dmlmc_ctx* ctx = H->ctx;
+  const int64_t n = H->coarse_dinv_n;
+  REQUIRE(n > 0, "the FP32 coarsest inverse must be built first");
+  H->coarse_dinv8.alloc(sizeof(uint16_t) * (size_t)n * n);
+  H->coarse_dinv8_rows.alloc(sizeof(float) * (size_t)n);
+  hipLaunchKernelGGL(to_fp8_rows_kernel, dim3((unsigned)n), dim3(1024), 0, ctx->stream, H->coarse_dinv.as<c64>(), n,
+                     H->coarse_dinv8.as<uint16_t>(), H->coarse_dinv8_rows.as<float>());
+  LAUNCH_CHECK();
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+}
+
 void apply_coarse_direct(dmlmc_hier* H, const c64* B, c64* Y, int nrhs) {
   dmlmc_ctx* ctx = H->ctx;
   const int64_t n = H->coarse_dinv_n;
   REQUIRE(((uintptr_t)B | (uintptr_t)Y) % 16 == 0, "direct coarsest solve needs 16-byte aligned vectors");
   const int64_t m = (int64_t)nrhs * n;
-  if (H->coarse_direct_mode == 2) {
-    REQUIRE(H->coarse_dinv16.p != nullptr, "the FP16 coarsest inverse is not built");
+  if (H->coarse_direct_mode == 2 || H->coarse_direct_mode == 3) {
+    const bool b8 = H->coarse_direct_mode == 3;
+    REQUIRE(b8 ? H->coarse_dinv8.p != nullptr : H->coarse_dinv16.p != nullptr,
+            "the reduced-precision coarsest inverse is not built");
     const int L = (int)H->lv.size();
     uint32_t* B16 = (uint32_t*)hier_buf(H, "cd_B16", L, sizeof(uint32_t) * (size_t)m);
     float* rs = (float*)hier_buf(H, "cd_rs", L, sizeof(float) * (size_t)nrhs);
-    c64* part = (c64*)hier_buf(H, "cd_part16", L, sizeof(c64) * (size_t)KSPLIT16 * m);
-    KTimer kt(ctx, "coarse_direct16", 4.0 * n * n + 16.0 * m);
+    const int KS = b8 ? KSPLIT8 : KSPLIT16;
+    c64* part = (c64*)hier_buf(H, "cd_part16", L, sizeof(c64) * (size_t)KS * m);
+    KTimer kt(ctx, b8 ? "coarse_direct8" : "coarse_direct16", (b8 ? 2.0 : 4.0) * n * n + 16.0 * m);
     hipLaunchKernelGGL(dense16_rhs_kernel, dim3((unsigned)nrhs), dim3(1024), 0, ctx->stream, B, n,
-                       H->coarse_dinv16_unscale, B16, rs);
+                       b8 ? 1.f : H->coarse_dinv16_unscale, B16, rs);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(dense16_apply_kernel<TILES16>, dim3((unsigned)ceil_div(n / (16 * TILES16), 4), KSPLIT16),
-                       dim3(256), 0, ctx->stream, H->coarse_dinv16.as<uint32_t>(), B16, part, n, nrhs, KSPLIT16);
+    if (b8)
+      hipLaunchKernelGGL(dense8_apply_kernel<TILES8>, dim3((unsigned)ceil_div(n / (16 * TILES8), 4), KSPLIT8),
+                         dim3(256), 0, ctx->stream, H->coarse_dinv8.as<uint32_t>(), B16, part, n, nrhs, KSPLIT8);
+    else
+      hipLaunchKernelGGL(dense16_apply_kernel<TILES16>, dim3((unsigned)ceil_div(n / (16 * TILES16), 4), KSPLIT16),
+                         dim3(256), 0, ctx->stream, H->coarse_dinv16.as<uint32_t>(), B16, part, n, nrhs, KSPLIT16);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(dense16_reduce_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, ctx->stream, part,
-                       KSPLIT16, n, m, rs, Y);
+    hipLaunchKernelGGL(dense16_reduce_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, ctx->stream, part, KS,
+                       n, m, rs, b8 ? H->coarse_dinv8_rows.as<float>() : (const float*)nullptr, Y);
     LAUNCH_CHECK();
     return;
   }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdmlmc.so
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
-DIRECT_OFF, DIRECT_FP32, DIRECT_FP16 = 0, 1, 2
+DIRECT_OFF, DIRECT_FP32, DIRECT_FP16, DIRECT_FP8 = 0, 1, 2, 3
 OP_D, OP_RESTRICT, OP_PROLONG, OP_SMOOTH, OP_VCYCLE, OP_DEFL_C, OP_DEFL_P, OP_GAMMA5_D = 0, 1, 2, 3, 4, 6, 7, 8
 
 EXPORTED = [
@@ -346,7 +346,7 @@ class Hierarchy:
 
     def coarsest_direct(self, defl: Optional["Deflation"] = None, enable=True):
         """Explicit-inverse coarsest solve (computed on first use): enable True or
-        DIRECT_FP32, DIRECT_FP16, or False / DIRECT_OFF (see dmlmc_coarsest_direct)."""
+        DIRECT_FP32, DIRECT_FP16, DIRECT_FP8, or False / DIRECT_OFF (see dmlmc_coarsest_direct)."""
         mode = DIRECT_FP32 if enable is True else (DIRECT_OFF if enable is False else int(enable))
         self.ctx.check(lib().dmlmc_coarsest_direct(self.ctx.h, self.h, defl.h if defl is not None else None, mode))
 

@@ -117,14 +117,15 @@ def test_sample_parity(gpu, name, prec_name, rtol, tol):
             assert abs(got[i] - s) / scale < tol, (l, i, got[i], s)
 
 
-@pytest.mark.parametrize("mode_name,vtol,maxit", [("fp32", 1e-4, 10), ("fp16", 5e-3, 16)])
+@pytest.mark.parametrize("mode_name,vtol,maxit", [("fp32", 1e-4, 10), ("fp16", 5e-3, 16), ("fp8", 6e-2, 40)])
 def test_direct_coarsest_solve(gpu, mode_name, vtol, maxit):
-    """Explicit-inverse coarsest solve, applied in complex FP32 or FP16: the V-cycle of the
-    coarsest level is D_L^-1 to that precision (FP16: 2^-11 rounding of the inverse and of
-    the scaled RHS, FP32 accumulation), solves still reach their FP64 tolerance (in a few
+    """Explicit-inverse coarsest solve, applied in complex FP32, FP16 or the 8-bit form: the
+    V-cycle of the coarsest level is D_L^-1 to that precision (FP16: 2^-11 rounding of the
+    inverse and of the scaled RHS; 8-bit: 2^-4 relative rounding of each entry after its
+    row scaling; FP32 accumulation), solves still reach their FP64 tolerance (in a few
     iterations at the coarsest level), and samples match the checker's."""
     torch, dm, ctx = gpu
-    mode = dm.DIRECT_FP32 if mode_name == "fp32" else dm.DIRECT_FP16
+    mode = {"fp32": dm.DIRECT_FP32, "fp16": dm.DIRECT_FP16, "fp8": dm.DIRECT_FP8}[mode_name]
     name = "schwinger128"
     W, lv, H = _gpu_hier(gpu, name)
     L = len(lv)
@@ -164,8 +165,9 @@ def test_direct_fp16_scaling_and_mode_switch(gpu):
     """FP16 coarsest inverse: each RHS is scaled by its own power of two, so the relative
     accuracy does not depend on its magnitude (1e-30 .. 1e30, where an unscaled FP16 copy
     would flush to zero or overflow), a zero RHS gives zero, and the result is linear
-    in the RHS up to the rounding; switching FP16 -> FP32 -> FP16 reuses the inverses and
-    the V-cycles follow the current mode (recorded iterations are keyed by it)."""
+    in the RHS up to the rounding; the 8-bit form likewise, to its precision; switching
+    FP16 -> FP32 -> 8-bit -> FP16 reuses the inverses and the V-cycles follow the current
+    mode (recorded iterations are keyed by it)."""
     torch, dm, ctx = gpu
     name = "schwinger128"
     W, lv, H = _gpu_hier(gpu, name)
@@ -179,14 +181,15 @@ def test_direct_fp16_scaling_and_mode_switch(gpu):
     bs = b * mags[None, :]
     xs = spla.splu(D.tocsc()).solve(b)
     out = {}
-    for mode in (dm.DIRECT_FP16, dm.DIRECT_FP32, dm.DIRECT_FP16):
+    tol = {dm.DIRECT_FP16: 5e-3, dm.DIRECT_FP32: 1e-4, dm.DIRECT_FP8: 6e-2}
+    for mode in (dm.DIRECT_FP16, dm.DIRECT_FP32, dm.DIRECT_FP8, dm.DIRECT_FP16):
         H.coarsest_direct(d, mode)
         x = torch.empty((4, n), dtype=torch.complex64, device="cuda:0")
         H.apply(dm.OP_VCYCLE, L, to_dev(torch, bs, torch.complex64), x, dm.MIXED)
         xh = to_host(x)
         assert np.all(xh[:, 3] == 0)
         errs = [rel_err(xh[:, j] / mags[j], xs[:, j]) for j in range(3)]
-        assert max(errs) < (5e-3 if mode == dm.DIRECT_FP16 else 1e-4), (mode, errs)
+        assert max(errs) < tol[mode], (mode, errs)
         out.setdefault(mode, []).append(xh)
         X, st = H.solve(L, to_dev(torch, b), prec=dm.MIXED, rtol=1e-10)
         res = np.linalg.norm(b - D @ to_host(X), axis=0) / np.linalg.norm(b, axis=0)
