@@ -339,8 +339,9 @@ dmlmc_status dmlmc_apply(dmlmc_ctx *ctx, const dmlmc_hier *h, int op, int level,
 /* dmlmc_apply with the vectors' strides given: RHS r of in at r * ld_in, of out at
  * r * ld_out (complex entries; 0 stands for n of the vector's level).  Entries between n
  * and the stride are neither read nor written.  Strides must be even and at least n;
- * DMLMC_OP_SMOOTH and DMLMC_OP_VCYCLE need ld_in == ld_out, the DMLMC_OP_DEFL_* operators
- * unpadded vectors.  Errors: as dmlmc_apply. */
+ * DMLMC_OP_SMOOTH and DMLMC_OP_VCYCLE need ld_in == ld_out (and DMLMC_OP_VCYCLE on the
+ * coarsest level unpadded vectors), the DMLMC_OP_DEFL_* operators unpadded vectors.
+ * Errors: as dmlmc_apply. */
 dmlmc_status dmlmc_apply_strided(dmlmc_ctx *ctx, const dmlmc_hier *h, int op, int level, const void *in,
                                  int64_t ld_in, void *out, int64_t ld_out, int nrhs, dmlmc_precision prec,
                                  uint64_t arg);
