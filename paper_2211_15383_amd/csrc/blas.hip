@@ -18,6 +18,14 @@ __global__ void fill_zero_kernel(T* __restrict__ p, size_t count) {
   for (; i < count; i += stride) p[i] = T{};
 }
 
+// p[r * ld + i] = 0 for i < n, row r = blockIdx.y (the entries between n and ld untouched)
+template <typename T>
+__global__ void fill_zero_rows_kernel(T* __restrict__ p, int64_t n, int64_t ld) {
+  T* row = p + (int64_t)blockIdx.y * ld;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    row[i] = T{};
+}
+
 template <typename To, typename From>
 __global__ void cast_kernel(const Cx<From>* __restrict__ x, Cx<To>* __restrict__ y, int64_t n, int64_t ldx,
                             int64_t ldy) {
@@ -206,6 +214,13 @@ void launch_fill_zero(dmlmc_ctx* ctx, T* p, size_t count) {
   LAUNCH_CHECK();
 }
 
+template <typename T>
+void launch_fill_zero_rows(dmlmc_ctx* ctx, T* p, int64_t n, int nrhs, int64_t ld) {
+  if (n == 0 || nrhs == 0) return;
+  hipLaunchKernelGGL((fill_zero_rows_kernel<T>), dim3(grid_for(n), nrhs), dim3(256), 0, ctx->stream, p, n, ld);
+  LAUNCH_CHECK();
+}
+
 template <typename To, typename From>
 void launch_cast(dmlmc_ctx* ctx, const Cx<From>* x, Cx<To>* y, int64_t n, int nrhs, int64_t ldx, int64_t ldy) {
   hipLaunchKernelGGL((cast_kernel<To, From>), dim3(grid_for(n), nrhs), dim3(256), 0, ctx->stream, x, y, n, ldx, ldy);
@@ -317,6 +332,8 @@ void launch_fill_value(dmlmc_ctx* ctx, double* p, size_t count, double v) {
 template void launch_fill_zero<c64>(dmlmc_ctx*, c64*, size_t);
 template void launch_fill_zero<c128>(dmlmc_ctx*, c128*, size_t);
 template void launch_fill_zero<double>(dmlmc_ctx*, double*, size_t);
+template void launch_fill_zero_rows<c64>(dmlmc_ctx*, c64*, int64_t, int, int64_t);
+template void launch_fill_zero_rows<c128>(dmlmc_ctx*, c128*, int64_t, int, int64_t);
 template void launch_cast<float, double>(dmlmc_ctx*, const c128*, c64*, int64_t, int, int64_t, int64_t);
 template void launch_cast<double, float>(dmlmc_ctx*, const c64*, c128*, int64_t, int, int64_t, int64_t);
 template void launch_cast<double, double>(dmlmc_ctx*, const c128*, c128*, int64_t, int, int64_t, int64_t);

@@ -292,6 +292,9 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
 // BLAS-like (blas.hip)
 template <typename T>
 void launch_fill_zero(dmlmc_ctx* ctx, T* p, size_t count);
+// zeroes entries 0 .. n-1 of nrhs rows at stride ld (the entries between n and ld untouched)
+template <typename T>
+void launch_fill_zero_rows(dmlmc_ctx* ctx, T* p, int64_t n, int nrhs, int64_t ld);
 void launch_fill_value(dmlmc_ctx* ctx, double* p, size_t count, double v);
 template <typename To, typename From>
 void launch_cast(dmlmc_ctx* ctx, const Cx<From>* x, Cx<To>* y, int64_t n, int nrhs, int64_t ldx, int64_t ldy);

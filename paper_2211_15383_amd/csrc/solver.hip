@@ -323,7 +323,7 @@ void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs, int64_t ld
   Cx<R>* xc = (Cx<R>*)hier_buf(H, f32 ? "vc_x32" : "vc_x64", l + 1, sizeof(Cx<R>) * (size_t)nrhs * ldc);
   if (H->nu_pre > 0) {
     Cx<R>* r = (Cx<R>*)hier_buf(H, f32 ? "vc_r32" : "vc_r64", l, sizeof(Cx<R>) * (size_t)nrhs * ld);
-    launch_fill_zero<Cx<R>>(ctx, x, (size_t)(nrhs - 1) * ld + n);
+    launch_fill_zero_rows<Cx<R>>(ctx, x, n, nrhs, ld);
     smooth<R>(H, l, x, b, nrhs, H->nu_pre, ld);
     apply_op<R>(ctx, L, x, r, nrhs, false, ld);
     launch_xmy<R>(ctx, b, r, n, nrhs, ld, ld);

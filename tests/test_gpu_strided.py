@@ -96,3 +96,30 @@ def test_strided_apply_rejects_bad_strides(gpu):
     yL = torch.zeros(2, nL + 2, dtype=torch.complex64, device="cuda:0")
     with pytest.raises(dm.DmlmcError):  # coarsest-level vectors are unpadded
         H.apply(dm.OP_VCYCLE, L, xL, yL, dm.MIXED, 0, ld_in=nL + 2, ld_out=nL + 2)
+
+
+def test_strided_vcycle_with_presmoothing(gpu):
+    """With pre-smoothing the V-cycle starts its top-level iterate from zero; on padded
+    rows that zeroing covers the level's entries only, so the pads still hold their NaN and
+    the result equals the unpadded call bit for bit."""
+    torch, dm, ctx = gpu
+    W, lv, H = _hier(gpu, "schwinger128")
+    L = len(lv)
+    base = H.solver_params()
+    gen = torch.Generator().manual_seed(99)
+    try:
+        H.solver_params(nu_pre=1)
+        for prec, dt in ((dm.FP64, torch.complex128), (dm.MIXED, torch.complex64)):
+            for l in range(1, L):
+                n, ld = H.n(l), H.work_stride(l)
+                x = torch.randn(7, n, dtype=dt, generator=gen).to("cuda:0")
+                ref = torch.zeros(7, n, dtype=dt, device="cuda:0")
+                H.apply(dm.OP_VCYCLE, l, x, ref, prec)
+                ap = _padded(torch, x, ld)
+                outp = _padded(torch, torch.zeros(7, n, dtype=dt, device="cuda:0"), ld)
+                H.apply(dm.OP_VCYCLE, l, ap, outp, prec, 0, ld_in=ld, ld_out=ld)
+                torch.cuda.synchronize()
+                assert torch.equal(outp[:, :n], ref), (prec, l)
+                assert bool(torch.isnan(outp[:, n:].real).all()), (prec, l, "pad written")
+    finally:
+        H.solver_params(nu_pre=base["nu_pre"])
