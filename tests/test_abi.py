@@ -41,6 +41,11 @@ def test_invalid_arguments_without_device():
     assert lib.dmlmc_level_info(None, 1, None, None, None) == dmlmc.EINVAL
     assert lib.dmlmc_deflation_info(None, None, None, None) == dmlmc.EINVAL
     assert lib.dmlmc_set_deflation(None, None) == dmlmc.EINVAL
+    ld = C.c_int64(-1)
+    assert lib.dmlmc_work_stride(None, 1, C.byref(ld)) == dmlmc.EINVAL and ld.value == -1
+    assert lib.dmlmc_apply(None, None, dmlmc.OP_D, 1, None, None, 1, dmlmc.MIXED, 0) == dmlmc.EINVAL
+    assert lib.dmlmc_apply_strided(None, None, dmlmc.OP_D, 1, None, 0, None, 0, 1, dmlmc.MIXED, 0) == dmlmc.EINVAL
+    assert lib.dmlmc_coarsest_direct(None, None, None, 3) == dmlmc.EINVAL
     # destroy/free accept NULL
     lib.dmlmc_destroy(None)
     lib.dmlmc_free_hierarchy(None)
