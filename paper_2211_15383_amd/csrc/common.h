@@ -276,6 +276,10 @@ void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs
 // r = b - D x in one pass (the refinement residual)
 template <typename R>
 void apply_residual(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, const Cx<R>* b, Cx<R>* r, int nrhs);
+// r = b - D x computed in FP64 and stored in complex FP32 (x, b at stride ldx, r at ldr;
+// 0: the level size): the first Krylov vector of a complex-FP32 refinement cycle
+void apply_residual_to32(dmlmc_ctx* ctx, const Level& L, const c128* x, const c128* b, c64* r, int nrhs,
+                         int64_t ldx = 0, int64_t ldr = 0);
 template <typename R>
 void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nrhs, int color,
                 int mr_iters, int64_t ld = 0);

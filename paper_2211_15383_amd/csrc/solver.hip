@@ -340,10 +340,12 @@ void vcycle(dmlmc_hier* H, int l, const Cx<R>* b, Cx<R>* x, int nrhs, int64_t ld
 // Solves A e = r approximately (one cycle of at most m iterations, stopping when every
 // residual estimate is <= target[r]) and adds e to x; r, x in FP64, rnorm2 = ||r||^2 per
 // RHS (device, as the refinement loop has just computed it).  RP: precision of the
-// operator inside the cycle and of the preconditioner.  Returns the number of iterations.
+// operator inside the cycle and of the preconditioner.  With u0_ready (complex FP32 only)
+// the caller has already stored r in complex FP32 as the first basis vector (unnormalised,
+// at the work stride) and r is not read.  Returns the number of iterations.
 template <typename RP>
 int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128* x, int nrhs, int m,
-                 const std::vector<double>& target, std::vector<double>& res_host) {
+                 const std::vector<double>& target, std::vector<double>& res_host, bool u0_ready = false) {
   dmlmc_ctx* ctx = H->ctx;
   const Level& L = H->lv[l - 1];
   const int64_t n = L.n();
@@ -369,9 +371,14 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128
     U = (c64*)hier_buf(H, "fg_U32", l, sizeof(c64) * (size_t)(m + 1) * vstride);
     scale = (double*)hier_buf(H, "fg_sc", l, sizeof(double) * (size_t)(m + 1) * nrhs);
     wr = (Cx<RP>*)hier_buf(H, "fg_wr32", l, sizeof(Cx<RP>) * (size_t)vstride);
-    // U_0 = r / ||r|| (scale 1), so that no basis vector holds residual-sized entries
-    launch_scale_store<float>(ctx, r, k.invb, U, n, nrhs, n, ldw);
-    launch_fill_value(ctx, scale, nrhs, 1.0);
+    if (u0_ready) {
+      // U_0 = r as the caller stored it, its scale 1 / ||r||
+      HIPCHK(hipMemcpyAsync(scale, k.invb, sizeof(double) * nrhs, hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+      // U_0 = r / ||r|| (scale 1)
+      launch_scale_store<float>(ctx, r, k.invb, U, n, nrhs, n, ldw);
+      launch_fill_value(ctx, scale, nrhs, 1.0);
+    }
   } else {
     V = (c128*)hier_buf(H, "fg_V", l, sizeof(c128) * (size_t)(m + 1) * vstride);
     w = (c128*)hier_buf(H, "fg_w", l, sizeof(c128) * (size_t)vstride);
@@ -419,13 +426,23 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
   dmlmc_ctx* ctx = H->ctx;
   const Level& L = H->lv[l - 1];
   const int64_t n = L.n();
-  c128* Rr = (c128*)hier_buf(H, "sv_R", l, sizeof(c128) * (size_t)nrhs * n);
+  const bool mixed = prec == DMLMC_MIXED;
+  const int m = std::max(2, H->restart);
+  // mixed: the residual goes straight into the first basis vector of the complex-FP32
+  // cycle (the whole basis is sized here, so the cycle's request never reallocates it);
+  // FP64: an FP64 residual vector
+  const int64_t ldw = work_ld(H, l);
+  c64* U0 = mixed ? (c64*)hier_buf(H, "fg_U32", l, sizeof(c64) * (size_t)(m + 1) * nrhs * ldw) : nullptr;
+  c128* Rr = mixed ? nullptr : (c128*)hier_buf(H, "sv_R", l, sizeof(c128) * (size_t)nrhs * n);
   double* nrm = (double*)hier_buf(H, "sv_nrm", l, sizeof(double) * nrhs);
   std::vector<double> bn(nrhs), rn(nrhs), target(nrhs), est;
   launch_norms2<double>(ctx, B, n, nrhs, n, nrm);
   HIPCHK(hipMemcpyAsync(bn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
   launch_fill_zero<c128>(ctx, X, (size_t)nrhs * n);
-  launch_cast<double, double>(ctx, B, Rr, n, nrhs, n, n);
+  if (mixed)
+    launch_cast<float, double>(ctx, B, U0, n, nrhs, n, ldw);  // r = b at x = 0
+  else
+    launch_cast<double, double>(ctx, B, Rr, n, nrhs, n, n);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (int q = 0; q < nrhs; ++q) {
     if (!std::isfinite(bn[q])) throw DmlmcError(DMLMC_ENUMERIC, "NaN/Inf in the right-hand side");
@@ -433,7 +450,6 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
     rn[q] = bn[q];
   }
   SolveResult out;
-  const int m = std::max(2, H->restart);
   const double inner_rel = (prec == DMLMC_MIXED) ? H->inner_rtol : 0.0;
   while (true) {
     bool all = true;
@@ -451,16 +467,23 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
     if (out.iters >= maxiter) break;
     for (int q = 0; q < nrhs; ++q) target[q] = std::max(0.5 * rtol * bn[q], inner_rel * rn[q]);
     int it;
-    // each cycle adds its correction to X; then r = b - D x (one operator pass) and
-    // ||r||^2 in FP64
-    if (prec == DMLMC_MIXED)
-      it = fgmres_cycle<float>(H, l, Rr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
+    // each cycle adds its correction to X; then r = b - D x (one operator pass, FP64
+    // arithmetic; stored in complex FP32 as the next cycle's first basis vector in the
+    // mixed form) and ||r||^2 (FP64 sums)
+    if (mixed)
+      it = fgmres_cycle<float>(H, l, nullptr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target,
+                               est, true);
     else
       it = fgmres_cycle<double>(H, l, Rr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
     out.iters += it;
     out.ir_steps += 1;
-    apply_residual<double>(ctx, L, X, B, Rr, nrhs);
-    launch_norms2<double>(ctx, Rr, n, nrhs, n, nrm);
+    if (mixed) {
+      apply_residual_to32(ctx, L, X, B, U0, nrhs, n, ldw);
+      launch_norms2<float>(ctx, U0, n, nrhs, ldw, nrm);
+    } else {
+      apply_residual<double>(ctx, L, X, B, Rr, nrhs);
+      launch_norms2<double>(ctx, Rr, n, nrhs, n, nrm);
+    }
     HIPCHK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int q = 0; q < nrhs; ++q) {

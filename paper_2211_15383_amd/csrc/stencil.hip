@@ -67,9 +67,9 @@ __device__ __forceinline__ int64_t xcd_block() {
 
 // Thread per site, RHS [r0, r1) in sequence; the five spinors of RHS r + 1 are requested
 // before RHS r is computed, so a thread always has a full set of loads in flight.
-template <typename R, bool G5>
+template <typename R, bool G5, typename RO = R>
 __global__ __launch_bounds__(256) void wilson_kernel(const Cx<R>* __restrict__ U, const Cx<R>* __restrict__ in,
-                                                     Cx<R>* __restrict__ out, int Lx, int Lt, R diag, int nrhs,
+                                                     Cx<RO>* __restrict__ out, int Lx, int Lt, R diag, int nrhs,
                                                      int rb, int64_t ldx, int64_t ldy,
                                                      const Cx<R>* __restrict__ sub) {
   const int64_t V = (int64_t)Lx * Lt;
@@ -106,26 +106,26 @@ __global__ __launch_bounds__(256) void wilson_kernel(const Cx<R>* __restrict__ U
     o.s0 = diag * c0.s0 - half * a0;
     o.s1 = diag * c0.s1 - half * a1;
     if (G5) o.s1 = cmk(-o.s1.x, -o.s1.y);
-    if (sub) {  // residual form: out = sub - D in
-      const Spinor<R> bb = reinterpret_cast<const Spinor<R>*>(sub + r * ldy)[s];
+    if (sub) {  // residual form: out = sub - D in (sub laid out as in)
+      const Spinor<R> bb = reinterpret_cast<const Spinor<R>*>(sub + r * ldx)[s];
       o.s0 = bb.s0 - o.s0;
       o.s1 = bb.s1 - o.s1;
     }
-    // the result is not re-read by this launch: non-temporal store
-    R* of = reinterpret_cast<R*>(out + r * ldy + 2 * s);
-    __builtin_nontemporal_store(o.s0.x, of);
-    __builtin_nontemporal_store(o.s0.y, of + 1);
-    __builtin_nontemporal_store(o.s1.x, of + 2);
-    __builtin_nontemporal_store(o.s1.y, of + 3);
+    // the result is not re-read by this launch: non-temporal store (rounded to RO)
+    RO* of = reinterpret_cast<RO*>(out + r * ldy + 2 * s);
+    __builtin_nontemporal_store((RO)o.s0.x, of);
+    __builtin_nontemporal_store((RO)o.s0.y, of + 1);
+    __builtin_nontemporal_store((RO)o.s1.x, of + 2);
+    __builtin_nontemporal_store((RO)o.s1.y, of + 3);
   }
 }
 
 // Coarse block stencil: y_s = sum_dir A[s][dir] x_{s+dir}; blocks column-major
 // (A[s][dir][j * d + i] = row i, column j).  Thread per (site, row), RB right-hand sides
 // per thread so that every block entry is loaded once per RB vectors.
-template <typename R, int RB, bool G5>
+template <typename R, int RB, bool G5, typename RO = R>
 __global__ __launch_bounds__(256) void coarse_kernel(const Cx<R>* __restrict__ A, const Cx<R>* __restrict__ in,
-                                                     Cx<R>* __restrict__ out, int Lx, int Lt, int d, int spb,
+                                                     Cx<RO>* __restrict__ out, int Lx, int Lt, int d, int spb,
                                                      int nrhs, int64_t ldx, int64_t ldy,
                                                      const Cx<R>* __restrict__ sub) {
   const int64_t V = (int64_t)Lx * Lt;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void coarse_kernel(const Cx<R>* __restrict__ A
   for (int q = 0; q < RB; ++q) {
     if (q < nr) {
       const Cx<R> v = neg ? cmk(-acc[q].x, -acc[q].y) : acc[q];
-      out[(r0 + q) * ldy + s * d + i] = sub ? sub[(r0 + q) * ldy + s * d + i] - v : v;
+      out[(r0 + q) * ldy + s * d + i] = ccast<RO>(sub ? sub[(r0 + q) * ldx + s * d + i] - v : v);
     }
   }
 }
@@ -560,9 +560,9 @@ __device__ __forceinline__ void cmfma64(f64x4& dre, f64x4& dim, c128 a, c128 x) 
   dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, x.x, dim, 0, 0, 0);
 }
 
-template <bool G5>
+template <bool G5, typename RO = double>
 __global__ __launch_bounds__(256) void coarse16_f64_mfma_kernel(const c128* __restrict__ A,
-                                                                const c128* __restrict__ in, c128* __restrict__ out,
+                                                                const c128* __restrict__ in, Cx<RO>* __restrict__ out,
                                                                 int Lx, int Lt, int nrhs, int64_t ldx, int64_t ldy,
                                                                 const c128* __restrict__ sub) {
   const int64_t V = (int64_t)Lx * Lt;
@@ -600,10 +600,11 @@ __global__ __launch_bounds__(256) void coarse16_f64_mfma_kernel(const c128* __re
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t ia = (int64_t)ra * ldy + s * 16 + 4 * kq + q, ib = (int64_t)rb * ldy + s * 16 + 4 * kq + q;
+      const int64_t e = s * 16 + 4 * kq + q;
       const c128 ya = cmk(sg * are[q], sg * aim[q]), yb = cmk(sg * bre[q], sg * bim[q]);
-      if (va) out[ia] = sub ? sub[ia] - ya : ya;  // residual form: out = sub - D in
-      if (vb) out[ib] = sub ? sub[ib] - yb : yb;
+      // residual form: out = sub - D in (sub laid out as in)
+      if (va) out[(int64_t)ra * ldy + e] = ccast<RO>(sub ? sub[(int64_t)ra * ldx + e] - ya : ya);
+      if (vb) out[(int64_t)rb * ldy + e] = ccast<RO>(sub ? sub[(int64_t)rb * ldx + e] - yb : yb);
     }
   }
 }
@@ -978,6 +979,40 @@ void apply_residual(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, const Cx<R>*
     launch_wilson<R>(ctx, L, x, r, nrhs, L.n(), L.n(), false, b);
   else
     launch_coarse<R>(ctx, L, x, r, nrhs, L.n(), L.n(), false, b);
+}
+
+void apply_residual_to32(dmlmc_ctx* ctx, const Level& L, const c128* x, const c128* b, c64* r, int nrhs, int64_t ldx,
+                         int64_t ldr) {
+  if (ldx <= 0) ldx = L.n();
+  if (ldr <= 0) ldr = L.n();
+  REQUIRE(ldx >= L.n() && ldr >= L.n() && ldx % 2 == 0 && ldr % 2 == 0,
+          "residual vectors need even strides of at least the level size");
+  const int64_t V = L.sites();
+  // reads x and b (FP64), writes r (complex FP32)
+  const double vec_bytes = (double)nrhs * L.n() * (2 * sizeof(c128) + sizeof(c64));
+  if (L.fine) {
+    const int rb = std::min(8, rhs_block_for(V, nrhs));
+    dim3 grid((unsigned)ceil_div(V, 256), (unsigned)ceil_div(nrhs, rb));
+    KTimer kt(ctx, "wilson", vec_bytes + (double)V * 2 * sizeof(c128));
+    hipLaunchKernelGGL((wilson_kernel<double, false, float>), grid, dim3(256), 0, ctx->stream, L.U64.as<c128>(), x,
+                       r, L.Lx, L.Lt, L.m0 + 2.0, nrhs, rb, ldx, ldr, b);
+    LAUNCH_CHECK();
+    return;
+  }
+  const int d = L.dofs;
+  KTimer kt(ctx, "coarse", vec_bytes + (double)V * 5 * d * d * sizeof(c128));
+  if (d == 16 && nrhs >= 8) {
+    hipLaunchKernelGGL((coarse16_f64_mfma_kernel<false, float>), dim3((unsigned)ceil_div(V, 4)), dim3(256), 0,
+                       ctx->stream, L.A64.as<c128>(), x, r, L.Lx, L.Lt, nrhs, ldx, ldr, b);
+    LAUNCH_CHECK();
+    return;
+  }
+  constexpr int RB = 4;
+  const int spb = std::max(1, 256 / d);
+  dim3 grid((unsigned)ceil_div(V, spb), (unsigned)ceil_div(nrhs, RB));
+  hipLaunchKernelGGL((coarse_kernel<double, RB, false, float>), grid, dim3((unsigned)(spb * d)), 0, ctx->stream,
+                     L.A64.as<c128>(), x, r, L.Lx, L.Lt, d, spb, nrhs, ldx, ldr, b);
+  LAUNCH_CHECK();
 }
 
 template <typename R>
