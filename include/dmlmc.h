@@ -346,6 +346,23 @@ dmlmc_status dmlmc_apply_strided(dmlmc_ctx *ctx, const dmlmc_hier *h, int op, in
                                  int64_t ld_in, void *out, int64_t ld_out, int nrhs, dmlmc_precision prec,
                                  uint64_t arg);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): out = in - W (W^H in) for nrhs
+ * unpadded complex128 vectors [nrhs][n] of the deflation's level (n = n_level), computed
+ * exactly as dmlmc_apply(DMLMC_OP_DEFL_P, DMLMC_MIXED) computes it (complex-FP32 matrix-core
+ * products, FP64 sums across K-chunks).  It calls no device allocation: the K-chunk
+ * partials and the coefficients W^H in live in a 16 MiB array that each GPU holds from
+ * library load until the process ends; a call needs 16 * k * nrhs * (ceil(n / 256) + 1)
+ * bytes of it (n = 16384, k = 128: up to 124 RHS).  All calls on one GPU share that array,
+ * so calls that overlap in time on one GPU (other contexts or threads) race and must be
+ * serialised by the caller; nothing in it needs to persist between calls.  in and out are
+ * device buffers owned by the caller and must not overlap; d need not be attached.
+ * Returns after the context stream is synchronised.  Errors: EINVAL (NULL arguments,
+ * nrhs < 1, overlapping buffers, a size beyond the array), ESTATE (d from another
+ * context), EHIP. */
+dmlmc_status dmlmc_deflate_project_noalloc(dmlmc_ctx *ctx, const dmlmc_defl *d, const void *in, void *out,
+                                           int nrhs);
+
 /* Writes the real Z2 noise vectors of samples sample0 .. sample0 + nrhs - 1 of level
  * `level` (length n each, [nrhs][n], device, complex128 for DMLMC_FP64 / complex64 for
  * DMLMC_MIXED): entry j = 1 - 2 * bit (j % 64) of SM(SM(SM(SM(seed) + level) + i) + j / 64)

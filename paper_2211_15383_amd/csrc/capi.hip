@@ -6,6 +6,7 @@
 #include "defl.h"
 #include "dense.h"
 #include "mlmc.h"
+#include "noalloc.h"
 #include "setup.h"
 #include "solver.h"
 
@@ -113,6 +114,7 @@ dmlmc_status dmlmc_create(dmlmc_ctx** out, int device, void* hip_stream) {
       HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
       ctx->own_stream = true;
     }
+    ctx->noalloc_scratch = noalloc_scratch_address();
   });
   if (st != DMLMC_OK) {
     delete ctx;
@@ -672,6 +674,21 @@ dmlmc_status dmlmc_apply_strided(dmlmc_ctx* ctx, const dmlmc_hier* h, int op, in
         REQUIRE(false, "unknown operator");
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+dmlmc_status dmlmc_deflate_project_noalloc(dmlmc_ctx* ctx, const dmlmc_defl* d, const void* in, void* out,
+                                           int nrhs) {
+  if (!ctx) return DMLMC_EINVAL;
+  return guarded(ctx, [&]() {
+    REQUIRE(d != nullptr, "deflation is NULL");
+    if (d->ctx != ctx) throw DmlmcError(DMLMC_ESTATE, "deflation belongs to another context");
+    REQUIRE(in != nullptr && out != nullptr && nrhs >= 1, "NULL vector or nrhs < 1");
+    const size_t bytes = sizeof(c128) * (size_t)d->n * nrhs;
+    const char* a = (const char*)in;
+    const char* b = (const char*)out;
+    REQUIRE(a + bytes <= b || b + bytes <= a, "in and out overlap");
+    deflate_project_noalloc(ctx, d, in, out, nrhs);
   });
 }
 

@@ -145,6 +145,7 @@ struct dmlmc_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
   DevBuf scratch_dots;   // reduction partials
   DevBuf scratch_small;  // small per-RHS device results
+  void* noalloc_scratch = nullptr;  // device address of the allocation-free entry point's array
 };
 
 // RAII bracket around one launch of a timed kernel class.

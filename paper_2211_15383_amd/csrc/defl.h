@@ -34,6 +34,12 @@ void defl_coeffs_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, int b,
                       DevBuf& scratch);
 void defl_project_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, c128* Y, int b, int64_t ldx, int64_t ldy,
                        const c128* C);
+// Y = X - W (W^H X) for b unpadded RHS ([b][n], X and Y disjoint) on the matrix cores, as
+// defl_coeffs_mfma + defl_project_mfma, with the K-chunk partials and C placed in `part`
+// (defl_project_scratch_entries complex128 entries, fully overwritten): no allocation and no
+// timing events.
+size_t defl_project_scratch_entries(const dmlmc_defl* D, int b);
+void defl_project_mfma_into(hipStream_t stream, const dmlmc_defl* D, const c128* X, c128* Y, int b, c128* part);
 // b -> (r, e0) with C = W^H b, r = b - W C = b - D e0, e0 = X Lambda^-1 C (exact inverse on
 // the deflation space), for a deflated coarsest-level solve; FP32 matrix cores for MIXED.
 void defl_coarse_split(dmlmc_hier* H, const dmlmc_defl* D, const c128* b, int nrhs, c128* r, c128* e0,

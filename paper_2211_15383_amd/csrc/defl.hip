@@ -184,6 +184,25 @@ void defl_coeffs_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, int b,
   LAUNCH_CHECK();
 }
 
+size_t defl_project_scratch_entries(const dmlmc_defl* D, int b) {
+  return (size_t)(ceil_div(D->n, KC) + 1) * D->k * b;
+}
+
+void defl_project_mfma_into(hipStream_t stream, const dmlmc_defl* D, const c128* X, c128* Y, int b, c128* part) {
+  const int nchunks = (int)ceil_div(D->n, KC);
+  c128* C = part + (size_t)nchunks * D->k * b;
+  dim3 gc(nchunks, (unsigned)ceil_div(D->k, 16), (unsigned)ceil_div(b, 16));
+  hipLaunchKernelGGL(defl_c_mfma_kernel, gc, dim3(64), 0, stream, D->W32.as<c64>(), D->k, X, b, D->n, D->n, part);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(defl_c_reduce_kernel, dim3((unsigned)ceil_div((int64_t)D->k * b, 256)), dim3(256), 0, stream,
+                     part, nchunks, D->k, b, C);
+  LAUNCH_CHECK();
+  dim3 gp((unsigned)ceil_div(D->n, 16), (unsigned)ceil_div(b, 16));
+  hipLaunchKernelGGL(defl_p_mfma_kernel, gp, dim3(64), 0, stream, D->W32.as<c64>(), D->k, C, X, Y, b, D->n, D->n,
+                     D->n, 1.0);
+  LAUNCH_CHECK();
+}
+
 void defl_project_mfma(dmlmc_ctx* ctx, const dmlmc_defl* D, const c128* X, c128* Y, int b, int64_t ldx, int64_t ldy,
                        const c128* C) {
   KTimer kt(ctx, "defl_gemm", 8.0 * D->n * D->k * b);

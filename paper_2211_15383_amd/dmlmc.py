@@ -30,7 +30,7 @@ EXPORTED = [
     "dmlmc_hutchinson_trace",
     "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_set_solver_params",
     "dmlmc_get_solver_params", "dmlmc_timing_enable", "dmlmc_timing_select", "dmlmc_tune_rhs_block",
-    "dmlmc_coarsest_direct",
+    "dmlmc_coarsest_direct", "dmlmc_deflate_project_noalloc",
     "dmlmc_timing_reset", "dmlmc_timing_get",
 ]
 
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_timing_reset": (i32, [vp]),
         "dmlmc_timing_select": (i32, [vp, C.c_char_p]),
         "dmlmc_coarsest_direct": (i32, [vp, vp, vp, i32]),
+        "dmlmc_deflate_project_noalloc": (i32, [vp, vp, vp, vp, i32]),
         "dmlmc_tune_rhs_block": (i32, [vp, vp, vp, C.POINTER(i32), i32, i32, dbl, C.c_uint64, C.POINTER(i32),
                                        C.POINTER(dbl)]),
         "dmlmc_timing_get": (i32, [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
@@ -396,6 +397,13 @@ class Deflation:
         if st != OK:
             raise DmlmcError(st, "deflation_info")
         return {"iters": it.value, "degree_sum": deg.value, "max_residual": res.value}
+
+    def project_noalloc(self, x, out):
+        """out = x - W (W^H x) through dmlmc_deflate_project_noalloc (complex128 [nrhs][n]
+        tensors on the device; the library allocates nothing for it)."""
+        self.hier.ctx.check(lib().dmlmc_deflate_project_noalloc(self.hier.ctx.h, self.h, C.c_void_p(_ptr(x)),
+                                                                C.c_void_p(_ptr(out)), x.shape[0]))
+        return out
 
     def export(self):
         n = self.hier.n(self.level)

@@ -38,6 +38,7 @@ def test_invalid_arguments_without_device():
     assert b"device" in lib.dmlmc_last_error(None)
     assert lib.dmlmc_build_hierarchy(None, None, None, None) == dmlmc.EINVAL
     assert lib.dmlmc_solve_multi_rhs(None, None, 1, None, None, None, 1, 1, 0, 1e-10, 10, None) == dmlmc.EINVAL
+    assert lib.dmlmc_deflate_project_noalloc(None, None, None, None, 1) == dmlmc.EINVAL
     assert lib.dmlmc_level_info(None, 1, None, None, None) == dmlmc.EINVAL
     assert lib.dmlmc_deflation_info(None, None, None, None) == dmlmc.EINVAL
     assert lib.dmlmc_set_deflation(None, None) == dmlmc.EINVAL
