@@ -81,16 +81,32 @@ def sigma_min(theta: np.ndarray, m: float, method: str = "auto") -> float:
     return float(np.min(np.abs(vals)))
 
 
-def m0_rule(theta: np.ndarray, m_start: float = 0.1, step: float = 0.005, target: float = TARGET):
-    """Returns (m0, sigma_min(m0), kind) with kind "crossing" or "minimum"."""
-    m_prev, s_prev = m_start, sigma_min(theta, m_start)
+def scan_points(m_start: float, step: float, count: int):
+    """The first `count` masses the scan of m0_rule visits, computed as it computes them."""
+    out, m = [m_start], m_start
+    for _ in range(count - 1):
+        m = m - step
+        out.append(m)
+    return out
+
+
+def m0_rule(theta: np.ndarray, m_start: float = 0.1, step: float = 0.005, target: float = TARGET,
+            sigma_fn=None):
+    """Returns (m0, sigma_min(m0), kind) with kind "crossing" or "minimum".
+
+    sigma_fn: optional callable m -> sigma_min(theta, m) used instead of computing each
+    value here (for instance a table filled in parallel, or a recorded one)."""
+    def smin(m):
+        return sigma_min(theta, m) if sigma_fn is None else sigma_fn(m)
+
+    m_prev, s_prev = m_start, smin(m_start)
     if s_prev < target:
         raise ValueError("sigma_min already below target at the scan start")
     history = [(m_prev, s_prev)]
     rises = 0
     while True:
         m_cur = m_prev - step
-        s_cur = sigma_min(theta, m_cur)
+        s_cur = smin(m_cur)
         history.append((m_cur, s_cur))
         if s_cur < target:
             m_hi, s_hi, m_lo, s_lo = m_prev, s_prev, m_cur, s_cur
@@ -104,7 +120,7 @@ def m0_rule(theta: np.ndarray, m_start: float = 0.1, step: float = 0.005, target
                 elif side == -1:
                     f_hi *= 0.5
                 m_new = m_hi - f_hi * (m_hi - m_lo) / (f_hi - f_lo)
-                s_new = sigma_min(theta, m_new)
+                s_new = smin(m_new)
                 if s_new >= target:
                     m_hi, s_hi = m_new, s_new
                     side = 1
@@ -123,15 +139,15 @@ def m0_rule(theta: np.ndarray, m_start: float = 0.1, step: float = 0.005, target
     a, b = history[i][0] + step, history[i][0] - step
     g = (np.sqrt(5.0) - 1.0) / 2.0
     c, d = b + g * (a - b), a - g * (a - b)
-    fc, fd = sigma_min(theta, c), sigma_min(theta, d)
+    fc, fd = smin(c), smin(d)
     while abs(a - b) > 1e-5:
         if fc < fd:
             b, d, fd = d, c, fc
             c = b + g * (a - b)
-            fc = sigma_min(theta, c)
+            fc = smin(c)
         else:
             a, c, fc = c, d, fd
             d = a - g * (a - b)
-            fd = sigma_min(theta, d)
+            fd = smin(d)
     m = 0.5 * (a + b)
-    return m, sigma_min(theta, m), "minimum"
+    return m, smin(m), "minimum"

@@ -91,6 +91,7 @@ def test_deflation_products(gpu, name, k):
 @pytest.mark.parametrize("name,prec_name,rtol,tol", [("schwinger16", "fp64", 1e-13, 1e-10),
                                                      ("schwinger16", "mixed", 1e-10, 1e-6),
                                                      ("rect24x16", "fp64", 1e-13, 1e-10),
+                                                     ("schwinger128", "fp64", 1e-13, 1e-10),
                                                      ("schwinger128", "mixed", 1e-10, 1e-6)])
 def test_sample_parity(gpu, name, prec_name, rtol, tol):
     torch, dm, ctx = gpu

@@ -166,3 +166,33 @@ def test_brute_force_deflated_hutchinson():
         h = mlmc.hutchinson_sample(lv, solver, None, 7, i)
         _, t1, _ = mlmc.difference_sample(lv, solver, 7, 1, i)
         assert h == t1
+
+
+def test_adaptive_loop_hand_computed():
+    """The adaptive branch of mlmc.run on synthetic samples whose variances are known in
+    closed form.  Level 1 draws 10 + (-1)^i, level 2 draws 100 + 3 (-1)^i, so after an
+    even number n of samples the means are exactly 10 and 100 and the sample variances
+    n/(n-1) and 9 n/(n-1); costs (4, 1); eps |T| = 0.1 with T = 110.
+    Round 1 (n0 = 8): err^2 T^2 = (8/7)/8 + (72/7)/8 = 10/7 > 0.01, so
+    N_l = ceil(0.01^-1 sqrt(V_l/C_l) (sqrt(V_1 C_1) + sqrt(V_2 C_2))) with V = (8/7, 72/7):
+    sqrt(2/7) (sqrt(32/7) + sqrt(72/7)) / 0.01 = 285.7.. -> 286 -> 288 (blocks of 4) and
+    sqrt(72/7) (...) / 0.01 = 1714.2.. -> 1715 -> 1716.  Round 2: 1/287 + 9/1715 <= 0.01,
+    stop."""
+    calls = []
+
+    def fn(l, ids):
+        calls.append((l, ids.start, ids.stop))
+        sign = np.where(np.arange(ids.start, ids.stop) % 2 == 0, 1.0, -1.0)
+        return (10.0 + sign) if l == 1 else (100.0 + 3.0 * sign)
+
+    T = 110.0
+    r = mlmc.run(fn, 2, [4.0, 1.0], 0.1 / T, 8, 4, 0.0)
+    s = (math.sqrt(32 / 7) + math.sqrt(72 / 7)) / 0.01
+    assert math.ceil(math.sqrt(2 / 7) * s) == 286 and math.ceil(math.sqrt(72 / 7) * s) == 1715
+    assert r.N == [288, 1716]
+    assert calls == [(1, 0, 8), (2, 0, 8), (1, 8, 288), (2, 8, 1716)]
+    assert r.trace == pytest.approx(T, rel=1e-15)
+    assert r.rel_err == pytest.approx(math.sqrt(1 / 287 + 9 / 1715) / T, rel=1e-13)
+    # with the cap below the allocation, the loop stops at the cap
+    r2 = mlmc.run(fn, 2, [4.0, 1.0], 0.1 / T, 8, 4, 0.0, max_samples=100)
+    assert r2.N == [100, 100]

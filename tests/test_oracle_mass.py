@@ -3,14 +3,26 @@
 * The shift-invert path (nested-dissection LU + Lanczos) gives the same sigma_min as a
   dense eigensolve of Gamma5 D.
 * Stored masses satisfy the rule they were fixed by: a local minimum of sigma_min(m), or
-  sigma_min within 1e-3 of 1e-2.
+  sigma_min within 1e-3 of 1e-2; sigma_min recomputed at the stored mass.
+* Records that carry the rule's evaluations (every (m, sigma_min) it asked for, from the
+  scan start +0.1 on) replay to the stored mass exactly, and the scan points before the
+  crossing all have sigma_min >= 1e-2 (so the crossing found is the first on the grid).
+* The 128^2 workload's mass by running the whole rule from +0.1 (about a minute).
+* Optional (DMLMC_SLOW_1024=1, several minutes and ~10 GB): sigma_min of the 1024^2
+  workload recomputed at its stored mass and at the scan start.
 """
 import json
+import os
 
 import numpy as np
 import pytest
 from oracle import mass
 from paper_2211_15383_amd.inputs import M0_FILE, WORKLOADS, link_angles
+
+
+def _records():
+    with open(M0_FILE) as f:
+        return json.load(f)
 
 
 def test_shift_invert_matches_dense():
@@ -25,10 +37,18 @@ def test_nested_dissection_is_permutation():
     assert np.array_equal(np.sort(s), np.arange(40 * 24))
 
 
-@pytest.mark.parametrize("name", ["schwinger16", "tiny8x16", "rect24x16"])
+def test_scan_points_follow_the_rule():
+    pts = mass.scan_points(0.1, 0.005, 33)
+    m = 0.1
+    for p in pts[1:]:
+        m = m - 0.005
+        assert p == m
+    assert abs(pts[-1] + 0.06) < 1e-15
+
+
+@pytest.mark.parametrize("name", ["schwinger16", "tiny8x16", "rect24x16", "schwinger128"])
 def test_stored_m0_satisfies_rule(name):
-    with open(M0_FILE) as f:
-        rec = json.load(f)[name]
+    rec = _records()[name]
     theta = WORKLOADS[name].theta()
     s0 = mass.sigma_min(theta, rec["m0"])
     assert abs(s0 - rec["sigma_min"]) < 1e-12
@@ -38,3 +58,48 @@ def test_stored_m0_satisfies_rule(name):
         assert s0 > mass.TARGET
         for dm in (-1e-3, 1e-3):
             assert mass.sigma_min(theta, rec["m0"] + dm) >= s0 - 1e-9
+
+
+def _replay(rec):
+    table = {m: s for m, s in rec["evaluations"]}
+
+    def fn(m):
+        if m not in table:
+            raise KeyError(f"the rule asked for sigma_min({m!r}), which the record does not hold")
+        return table[m]
+
+    return mass.m0_rule(np.zeros((2, 1, 1)), m_start=rec["m_start"], sigma_fn=fn)
+
+
+@pytest.mark.parametrize("name", sorted(n for n, r in json.load(open(M0_FILE)).items() if "evaluations" in r))
+def test_recorded_rule_replays_to_stored_mass(name):
+    rec = _records()[name]
+    assert rec["m_start"] == 0.1
+    m0, s0, kind = _replay(rec)
+    assert (m0, s0, kind) == (rec["m0"], rec["sigma_min"], rec["kind"])
+    if kind == "crossing":
+        # the grid points the scan passed before the crossing
+        grid = mass.scan_points(0.1, 0.005, 400)
+        table = {m: s for m, s in rec["evaluations"]}
+        below = [m for m in grid if m in table and table[m] < mass.TARGET]
+        first = max(below)
+        passed = [m for m in grid if m > first]
+        assert all(m in table and table[m] >= mass.TARGET for m in passed)
+        assert rec["m0"] > first
+
+
+def test_schwinger128_rule_from_scan_start():
+    rec = _records()["schwinger128"]
+    m0, s0, kind = mass.m0_rule(WORKLOADS["schwinger128"].theta())
+    assert kind == rec["kind"] == "minimum"
+    assert abs(m0 - rec["m0"]) < 1e-12
+    assert s0 > mass.TARGET
+
+
+@pytest.mark.skipif(os.environ.get("DMLMC_SLOW_1024") != "1", reason="set DMLMC_SLOW_1024=1 (minutes, ~10 GB)")
+def test_schwinger1024_sigma_min_recomputed():
+    rec = _records()["schwinger1024"]
+    theta = WORKLOADS["schwinger1024"].theta()
+    table = {m: s for m, s in rec["evaluations"]}
+    for m in (rec["m0"], 0.1):
+        assert abs(mass.sigma_min(theta, m) - table[m]) < 1e-9 * table[m]
