@@ -6,9 +6,12 @@ plus the achieved HBM bandwidth of the stencil kernels.
 
 One step = one complete MGMLMC estimate to relative error eps = 1e-2 (all levels: noise,
 deflation projections, multigrid-preconditioned solves, sample dots, accumulation and
-allocation) with identical sample sets in both precisions.  Setup (hierarchy, coarsest
-eigensolve) is timed separately, like the paper's "eig.+direct" column.  Prints one JSON
-line on stdout; progress goes to stderr.
+allocation) with identical sample sets in both precisions.  The timed steps carry no
+timing events, so the recorded HIP graphs of the FGMRES iterations are replayed; the
+dominant kernel's launch times come from a second pass over the same steps with events
+around that kernel only.  Setup (hierarchy, coarsest eigensolve, explicit coarsest
+inverse) is timed separately, like the paper's "eig.+direct" column, and added in the
+setup-plus-trace totals.  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -119,6 +122,36 @@ def kernel_rates(torch, dm, ctx, H, nlev: int, b: int, reps: int = 10):
                                       "GBps": by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
         del x, y, xc, yc
     ctx.timing(False)
+    torch.cuda.synchronize()
+    return out
+
+
+def matrix_core_rates(torch, dm, ctx, H, D, L: int, b: int, reps: int = 10):
+    """The deflation products (C = W^H X, X - W C: complex-FP32 matrix cores) and the coarsest
+    solve of the V-cycle (the explicit inverse applied in complex FP16 when enabled) alone at
+    the coarsest level's shape with b RHS, reps launches after one warm-up."""
+    out = {}
+    n = H.n(L)
+    x = torch.randn(b, n, dtype=torch.complex128, device="cuda:0")
+    y = torch.empty_like(x)
+    c = torch.empty(b, D.k, dtype=torch.complex128, device="cuda:0")
+    x32 = x.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    H.set_deflation(D)
+    ctx.timing_select(None)
+    ctx.timing(True)
+    for name, cls, op, a, o in (("defl_coeffs", "defl_gemm", dm.OP_DEFL_C, x, c),
+                                ("defl_project", "defl_gemm", dm.OP_DEFL_P, x, y),
+                                ("coarsest_solve", "coarse_direct16", dm.OP_VCYCLE, x32, y32)):
+        H.apply(op, L, a, o, dm.MIXED)
+        ctx.timing_reset()
+        for _ in range(reps):
+            H.apply(op, L, a, o, dm.MIXED)
+        nl, ms, work = ctx.timing_get(cls)
+        out[f"{name}_level{L}"] = {"class": cls, "launches": nl, "avg_us": 1e3 * ms / max(1, nl),
+                                   "work_per_launch": work / max(1, nl)}
+    ctx.timing(False)
+    H.set_deflation(None)
     torch.cuda.synchronize()
     return out
 
@@ -237,6 +270,66 @@ def cpu_baseline(name: str, nsamp: int):
         return time.perf_counter() - t0
 
 
+def cpu_baseline_fullsize(name: str, N, rtol: float):
+    """The CPU checker as it stands on the benchmark's own 1024^2 workload, timed on a
+    bounded subset and scaled to one estimate with the sample counts N of the GPU run.
+
+    The checker cannot rebuild the library's inverse-iteration hierarchy at this size, so
+    it uses the same lattice, mass and aggregation with its Z4 start vectors as test
+    vectors (its parity hierarchy).  Timed: one level-2 solve (FGMRES + V-cycle to rtol;
+    a level-2 solve occurs in two terms of every sample of levels 1 and 2) and one LU
+    solve each at levels 3 and 4 (after their factorisation).  Not timed: the hierarchy,
+    every factorisation and V-cycle setup (setup, reported separately), and the level-1 LU
+    solves, whose factorisation alone takes minutes; the result is therefore a lower
+    bound of the checker's time per estimate."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import multigrid as omg, noise as onoise, solvers
+    from paper_2211_15383_amd.inputs import WORKLOADS, load_m0
+
+    W = WORKLOADS[name]
+    t0 = time.perf_counter()
+    dims = W.level_dims()
+    tv = [omg.start_vectors(W.mg_seed, l + 1, n, dims[l][0] * dims[l][1] * dims[l][2]) for l, n in enumerate(W.ntv)]
+    lv = omg.build_hierarchy(W.theta(), load_m0(name), W.aggs, W.ntv, 0, W.mg_seed, import_tv=tv)
+    t_hier = time.perf_counter() - t0
+    L = len(lv)
+    hs = solvers.HybridSolver(lv, rtol=rtol)
+    t0 = time.perf_counter()
+    for l in range(2, L + 1):
+        hs.prepare(l)
+    t_prep = time.perf_counter() - t0
+    per_solve = {}
+    for l in range(2, L + 1):
+        x = onoise.z2_noise(W.noise_seed, l, 0, lv[l - 1].n).astype(np.complex128)
+        t0 = time.perf_counter()
+        hs.solve(l, x)
+        per_solve[l] = time.perf_counter() - t0
+        log(f"cpu baseline 1024^2: one level-{l} solve {per_solve[l]:.2f} s")
+    # sample l < L solves on levels l and l + 1; the coarsest sample on level L
+    per_sample = {l: per_solve.get(l, 0.0) + (per_solve[l + 1] if l < L else 0.0) for l in range(1, L + 1)}
+    est = sum(N[l - 1] * per_sample[l] for l in range(1, L + 1))
+    threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"{name}: one level-2 FGMRES+V-cycle solve to {rtol:g} and one LU solve at levels 3 and 4, "
+                      f"timed on the parity hierarchy (Z4 test vectors) and scaled to one estimate with "
+                      f"N = {list(N)}; level-1 solves and all setup excluded (lower bound)",
+            "per_solve_s": per_solve, "setup_s": {"hierarchy": t_hier, "factorisations_and_vcycle": t_prep},
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,11 +340,19 @@ def main():
                     help="coarsest solve inside the complex-FP32 V-cycles: explicit inverse applied in "
                          "FP16, FP32 or the 8-bit form, or the iterative deflated GMRES")
     ap.add_argument("--skip-fp64", action="store_true", help="skip the FP64 single-RHS baseline run")
-    ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU checker baseline")
+    ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU checker baselines")
+    ap.add_argument("--skip-direct-off", action="store_true",
+                    help="skip the estimate with the iterative coarsest solve (no explicit inverse)")
+    ap.add_argument("--converge-eps", type=float, default=1e-4,
+                    help="tolerance of the extra convergence run, where the stopping rule sets N (0: skip)")
     ap.add_argument("--cpu-workload", default="schwinger128")
     ap.add_argument("--cpu-samples", type=int, default=128, help="samples per level of the CPU baseline")
     ap.add_argument("--skip-kernel-rates", action="store_true",
                     help="skip the per-kernel runs at the real shapes after the timed steps")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="after the setup, only run each hot kernel alone at the workload's shapes (stencil, "
+                         "transfers, smoothers on levels 1-2, deflation products, coarsest apply) and print "
+                         "their timings: a short program for profiler counter runs")
     ap.add_argument("--methods", default=None, metavar="WORKLOAD",
                     help="also time plain / skipped-level / difference-deflated MGMLMC on WORKLOAD")
     ap.add_argument("--methods-eps", type=float, default=1e-3)
@@ -296,6 +397,16 @@ def main():
     t_inv = time.perf_counter() - t0
     log(f"coarsest inverse (n = {H.n(L)}, {args.direct}) in {t_inv:.2f} s")
 
+    if args.kernels_only:
+        copy_gbps = copy_ceiling(torch)  # also the profiler's calibration: 1 GiB read + 1 GiB written
+        kr = kernel_rates(torch, dmlmc, ctx, H, min(L, 3), W.rhs_block)
+        kr.update(matrix_core_rates(torch, dmlmc, ctx, H, D, L, W.rhs_block))
+        kr["copy_1GiB"] = {"GBps": copy_gbps, "avg_us": 2 * (1 << 30) / copy_gbps / 1e3}
+        for k, v in kr.items():
+            log(f"kernel {k}: {v['avg_us']:.1f} us")
+        print(json.dumps({"workload": W.name, "kernels": kr}), flush=True)
+        return
+
     n0 = [W.n0] * L
 
     def run(prec, block):
@@ -315,10 +426,8 @@ def main():
     log(f"breakdown pass: {r.seconds:.3f} s (all kernel classes bracketed by events)")
     dom = max(HBM_CLASSES, key=lambda c: tb[c]["ms"])
 
-    # timed steps: events only around the dominant class
-    ctx.timing_select([dom])
-    ctx.timing(True)
-    ctx.timing_reset()
+    # timed steps: no events, so every complex-FP32 FGMRES iteration after the first two of
+    # each shape is replayed from its recorded HIP graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
@@ -329,9 +438,34 @@ def main():
             f"level s {[round(c, 3) for c in r.cost_s]}")
     torch.cuda.synchronize()
     t_mixed = (time.perf_counter() - t0) / args.steps
+
+    # roofline pass: the same steps again with events around the dominant class only (runs
+    # with events launch directly instead of replaying graphs)
+    ctx.timing_select([dom])
+    ctx.timing(True)
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run(dmlmc.MIXED, W.rhs_block)
+    torch.cuda.synchronize()
+    t_events = (time.perf_counter() - t0) / args.steps
     tm = timers(ctx, (dom,))
     ctx.timing(False)
     ctx.timing_select(None)
+    log(f"roofline pass: {t_events:.3f} s per estimate with events around {dom}")
+
+    conv = None
+    if args.converge_eps > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = dmlmc.mlmc_trace(H, D, args.converge_eps, W.noise_seed, n0, W.rhs_block, prec=dmlmc.MIXED,
+                              rtol=W.rtol)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        conv = {"eps": args.converge_eps, "seconds": tc, "N": rc.N, "rel_err": rc.rel_err, "trace": rc.trace,
+                "level_seconds": rc.cost_s}
+        log(f"convergence run eps {args.converge_eps:g}: {tc:.3f} s, N {rc.N}, rel_err {rc.rel_err:.3e}")
     copy_gbps = copy_ceiling(torch)
     log(f"copy kernel ceiling {copy_gbps:.0f} GB/s")
     kr = {} if args.skip_kernel_rates else kernel_rates(torch, dmlmc, ctx, H, min(L, 3), W.rhs_block)
@@ -350,7 +484,32 @@ def main():
         t64 = time.perf_counter() - t0
         log(f"fp64 single-RHS: trace {r64.trace:.4f} rel_err {r64.rel_err:.3e} N {r64.N} in {t64:.2f} s")
         rel = abs(r64.trace - results[-1].trace) / abs(r64.trace)
-        fp64 = {"seconds": t64, "trace": r64.trace, "N": r64.N, "trace_rel_diff_vs_mixed": rel}
+        fp64 = {"seconds": t64, "trace": r64.trace, "N": r64.N, "trace_rel_diff_vs_mixed": rel,
+                "level_seconds": r64.cost_s}
+        if conv is not None:
+            # the FP64 single-RHS time of the convergence run's counts, from its per-sample
+            # time per level in the run above (not measured)
+            conv["fp64_single_rhs_s_extrapolated"] = sum(
+                r64.cost_s[l] / r64.N[l] * conv["N"][l] for l in range(L))
+
+    direct_off = None
+    if direct_mode != dmlmc.DIRECT_OFF and not args.skip_direct_off:
+        H.coarsest_direct(D, dmlmc.DIRECT_OFF)  # frees the inverse: done after every run that uses it
+        run(dmlmc.MIXED, W.rhs_block)  # warm-up: records the graphs of this configuration
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps_off = max(1, min(args.steps, 3))
+        for _ in range(steps_off):
+            r_off = run(dmlmc.MIXED, W.rhs_block)
+        torch.cuda.synchronize()
+        t_off = (time.perf_counter() - t0) / steps_off
+        gain = t_off - t_mixed
+        direct_off = {"seconds": t_off, "coarsest_solve": "deflated fixed-count GMRES", "iters": r_off.iters,
+                      "trace_rel_diff_vs_direct": abs(r_off.trace - results[-1].trace) / abs(r_off.trace),
+                      "inverse_setup_s": t_inv, "saving_per_estimate_s": gain,
+                      "break_even_estimates": (t_inv / gain) if gain > 0 else None}
+        log(f"iterative coarsest solve: {t_off:.3f} s per estimate (iters {r_off.iters}); the explicit inverse "
+            f"saves {gain:.3f} s per estimate against {t_inv:.2f} s of setup")
 
     # dominant HBM-bound kernel class, measured inside the timed region
     d = tm[dom]
@@ -374,19 +533,20 @@ def main():
         methods = method_comparison(torch, dmlmc, ctx, args.methods, args.methods_eps, args.methods_k, hk,
                                     diff=not args.methods_no_diff)
 
-    cpu = None
+    cpu = cpu128 = None
     if not args.skip_cpu:
+        log(f"cpu baseline: checker on {W.name}, bounded subset")
+        cpu = cpu_baseline_fullsize(W.name, results[-1].N, W.rtol)
+        log(f"cpu baseline {W.name}: >= {cpu['value']:.1f} s per estimate (extrapolated)")
         nsamp = args.cpu_samples
         log(f"cpu baseline: checker on {args.cpu_workload}, {nsamp} samples per level")
         sec = cpu_baseline(args.cpu_workload, nsamp)
         gsec = gpu_same_sample(torch, dmlmc, ctx, args.cpu_workload, nsamp)
-        cpu = {"value": sec, "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_workload} (128^2, 3 levels, k=32): {nsamp} samples per level with "
-                         f"direct sparse-LU solves, setup excluded; the 1024^2 workload is out of the "
-                         f"checker's reach (one sparse factorisation of its 2M-unknown operator takes "
-                         f"minutes)",
-               "gpu_same_sample_s": gsec}
-        log(f"cpu baseline {sec:.2f} s; the GPU on the same samples {gsec:.3f} s")
+        cpu128 = {"value": sec, "unit": "s", "cores": 1, "kind": "oracle",
+                  "sample": f"{args.cpu_workload} (128^2, 3 levels, k=32): {nsamp} samples per level with "
+                            f"direct sparse-LU solves, setup excluded, measured in full",
+                  "gpu_same_sample_s": gsec}
+        log(f"cpu baseline {args.cpu_workload} {sec:.2f} s; the GPU on the same samples {gsec:.3f} s")
 
     coarsest = {"fp16": "explicit inverse applied in complex FP16 (FP32 accumulation)",
                 "fp32": "explicit inverse applied in complex FP32",
@@ -403,17 +563,31 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64+f64",
+        "dtype": "c64+f64 (complex-FP16 operands: coarse Gauss-Seidel blocks, coarsest inverse)",
         "data": "synthetic",
         "config": {"workload": f"{W.name}: {W.Lx}x{W.Lt} Wilson-Schwinger, 4 levels (4x4,4x4,2x2 aggregates, "
                                f"8 tv/chirality), k={W.k_defl} coarsest deflation, coarsest solve {coarsest}, "
                                f"eps={W.eps}, rtol={W.rtol}, "
                                f"{W.n0} initial samples/level, RHS block {W.rhs_block}",
                    "m0": m0, "setup_hierarchy_s": t_hier, "setup_eigensolve_s": t_eig,
-                   "setup_coarsest_inverse_s": t_inv, "coarsest_solve": coarsest},
+                   "setup_coarsest_inverse_s": t_inv, "coarsest_solve": coarsest,
+                   "precision": "complex FP32 V-cycles, operators and Krylov basis inside FP64 refinement "
+                                "(FP64 Arnoldi, residuals and sample dots); the coarse Gauss-Seidel blocks and "
+                                "the coarsest inverse are read as complex FP16 (FP32 accumulation)",
+                   "graphs": "timed steps replay recorded HIP graphs (no events in them)"},
+        "estimate_with_events_s": t_events,
         "fp64_single_rhs_s": fp64["seconds"] if fp64 else None,
         "speedup_vs_fp64": (fp64["seconds"] / t_mixed) if fp64 else None,
         "fp64_run": fp64,
+        "setup_plus_trace_s": {
+            "mixed": t_hier + t_eig + t_inv + t_mixed,
+            "fp64_single_rhs": (t_hier + t_eig + fp64["seconds"]) if fp64 else None,
+            "mixed_only_setup": {"coarsest_inverse_s": t_inv},
+            "shared_setup": {"hierarchy_s": t_hier, "eigensolve_s": t_eig},
+            "speedup": ((t_hier + t_eig + fp64["seconds"]) / (t_hier + t_eig + t_inv + t_mixed)) if fp64 else None,
+        },
+        "direct_off": direct_off,
+        "convergence_run": conv,
         "trace": results[-1].trace,
         "rel_err": results[-1].rel_err,
         "N": results[-1].N,
@@ -433,6 +607,7 @@ def main():
                      "kernel_class": dom, "launches": d["launches"], "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": avg_bytes, "traffic_summary": traffic_src},
         "cpu_baseline": cpu,
+        "cpu_baseline_128": cpu128,
     }
     if methods is not None:
         out["methods"] = methods

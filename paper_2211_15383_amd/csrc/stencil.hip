@@ -2,7 +2,7 @@
 //   * fine Wilson-Schwinger stencil (spin-projected hops, links folded with the
 //     antiperiodic sign), multi-RHS;
 //   * coarse nearest-neighbour block stencil (dense d x d blocks, column-major);
-//   * SAP smoother on 4x4 (or 2x2) site blocks with local minimal-residual iterations,
+//   * SAP smoother on 8x4, 4x4 or 2x2 site blocks with local minimal-residual iterations,
 //     red/black over blocks, residual b - D x fused in;
 //   * red/black point-block Gauss-Seidel on coarse levels (exact inverse self blocks);
 //   * restriction P^H and prolongation P on (aggregate, chirality) blocks.
@@ -642,10 +642,16 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
   if constexpr (H16) {
     const uint32_t* A = static_cast<const uint32_t*>(Av);
     const uint32_t* Ainv = static_cast<const uint32_t*>(Ainvv);
+    // the blocks are read once per launch: non-temporal loads
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     uint4 a[4];
 #pragma unroll
-    for (int dir = 0; dir < 4; ++dir) a[dir] = *reinterpret_cast<const uint4*>(A + (s * 4 + dir) * 256 + row * 16 + 4 * kq);
-    const uint4 ai = *reinterpret_cast<const uint4*>(Ainv + s * 256 + row * 16 + 4 * kq);
+    for (int dir = 0; dir < 4; ++dir) {
+      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(A + (s * 4 + dir) * 256 + row * 16 + 4 * kq));
+      a[dir] = make_uint4(v.x, v.y, v.z, v.w);
+    }
+    const u32x4 vi = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(Ainv + s * 256 + row * 16 + 4 * kq));
+    const uint4 ai = make_uint4(vi.x, vi.y, vi.z, vi.w);
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
       const int ra = r0 + row;
       const bool va = ra < nrhs;
@@ -731,14 +737,15 @@ struct AggMap {
   }
 };
 
-// One wavefront per (aggregate, group of mtw <= 4 16-entry tiles), all RHS, two RHS tiles
-// at a time; the group's interpolation quads (and, when adding, the old fine values) are
-// all requested before the first product.
+// One wavefront per (aggregate, group of MT 16-entry tiles), all RHS, two 16-RHS tiles at
+// a time; the group's interpolation quads (and, when adding, the old fine values) are all
+// requested before the first product.
+template <int MT>
 __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restrict__ P, const c64* __restrict__ ec,
-                                                             c64* __restrict__ xf, AggMap g, int64_t Vc, int mtw,
-                                                             int nrhs, int add, int64_t ldf, int64_t ldc) {
+                                                             c64* __restrict__ xf, AggMap g, int64_t Vc, int nrhs,
+                                                             int add, int64_t ldf, int64_t ldc) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int groups = g.E / 16 / mtw;
+  const int groups = g.E / 16 / MT;
   const int64_t wave = xcd_block() * 4 + w;
   const int64_t cs = wave / groups;
   if (cs >= Vc) return;  // wave-uniform
@@ -746,18 +753,15 @@ __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restri
   const int row = lane & 15, kq = lane >> 4;
   // coarse dof 4 kq + t has chirality kq / 2 and test vector 4 (kq % 2) + t
   const int cj = kq >> 1, k0 = 4 * (kq & 1);
-  Quad a[4];
-  int64_t fo[4];
+  Quad a[MT];
+  int64_t fo[MT];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    fo[u] = 0;
-    if (u < mtw) {  // wave-uniform
-      const int mt = grp * mtw + u;
-      int ce;
-      const int64_t pr = g.prow(cs, 16 * mt + row, ce);
-      a[u] = select_quad(ce == cj, load_quad_nt(P + pr + k0));
-      fo[u] = g.fine_offset(cs, 16 * mt + 4 * kq);
-    }
+  for (int u = 0; u < MT; ++u) {
+    const int mt = grp * MT + u;
+    int ce;
+    const int64_t pr = g.prow(cs, 16 * mt + row, ce);
+    a[u] = select_quad(ce == cj, load_quad_nt(P + pr + k0));
+    fo[u] = g.fine_offset(cs, 16 * mt + 4 * kq);
   }
   for (int r0 = 0; r0 < nrhs; r0 += 32) {
     const int ra = r0 + row, rb = r0 + 16 + row;
@@ -766,43 +770,40 @@ __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restri
     // rows beyond nrhs load a valid row and are zeroed (no divergent loads)
     const Quad ea = select_quad(va, load_quad(ec + (int64_t)min(ra, nrhs - 1) * ldc + cs * 16 + 4 * kq));
     const Quad eb = select_quad(vb, load_quad(ec + (int64_t)min(rb, nrhs - 1) * ldc + cs * 16 + 4 * kq));
-    Quad xa[4], xb[4];
+    Quad xa[MT], xb[MT];
     if (add) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u < mtw) {
-          xa[u] = load_quad(xf + oa + fo[u]);
-          xb[u] = load_quad(xf + ob + fo[u]);
-        }
+      for (int u = 0; u < MT; ++u) {
+        xa[u] = load_quad(xf + oa + fo[u]);
+        xb[u] = load_quad(xf + ob + fo[u]);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (u < mtw) {  // wave-uniform
-        f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
-        block_mfma(are, aim, a[u], ea);
-        block_mfma(bre, bim, a[u], eb);
-        if (add) {
+    for (int u = 0; u < MT; ++u) {
+      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
+      block_mfma(are, aim, a[u], ea);
+      block_mfma(bre, bim, a[u], eb);
+      if (add) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            are[v] += xa[u].v[v].x;
-            aim[v] += xa[u].v[v].y;
-            bre[v] += xb[u].v[v].x;
-            bim[v] += xb[u].v[v].y;
-          }
+        for (int v = 0; v < 4; ++v) {
+          are[v] += xa[u].v[v].x;
+          aim[v] += xa[u].v[v].y;
+          bre[v] += xb[u].v[v].x;
+          bim[v] += xb[u].v[v].y;
         }
-        if (va) store_quad(xf + oa + fo[u], are, aim, 1.f);
-        if (vb) store_quad(xf + ob + fo[u], bre, bim, 1.f);
       }
+      if (va) store_quad(xf + oa + fo[u], are, aim, 1.f);
+      if (vb) store_quad(xf + ob + fo[u], bre, bim, 1.f);
     }
   }
 }
 
 // WPA wavefronts per aggregate (WPA = min(4, E / 16)), 4 / WPA aggregates per workgroup:
 // the aggregate's 16-entry tiles are dealt round-robin to its wavefronts, each of which
-// requests the loads of up to four tiles before multiplying; the partial 16 x 32 results
+// requests the loads of up to UT tiles before multiplying; the partial 16 x 32 results
 // of the wavefronts meet in LDS.  Every wavefront reaches the barriers.
+template <int UT>
 __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restrict__ P, const c64* __restrict__ xf,
                                                               c64* __restrict__ yc, AggMap g, int64_t Vc, int nrhs,
                                                               int wpa, int64_t ldf, int64_t ldc) {
@@ -821,10 +822,10 @@ __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restr
     const bool va = ra < nrhs, vb = rb < nrhs;
     f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are, bre = are, bim = are;
     const int64_t oa = (int64_t)min(ra, nrhs - 1) * ldf, ob = (int64_t)min(rb, nrhs - 1) * ldf;
-    for (int kt0 = sub; kt0 < ntile; kt0 += 4 * wpa) {
-      Quad a[4], xa[4], xb[4];
+    for (int kt0 = sub; kt0 < ntile; kt0 += UT * wpa) {
+      Quad a[UT], xa[UT], xb[UT];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < UT; ++u) {
         const int kt = kt0 + u * wpa;
         if (kt >= ntile) continue;  // wave-uniform
 #pragma unroll
@@ -841,7 +842,7 @@ __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restr
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < UT; ++u) {
         if (kt0 + u * wpa < ntile) {  // wave-uniform
           block_mfma(are, aim, a[u], select_quad(va, xa[u]));
           block_mfma(bre, bim, a[u], select_quad(vb, xb[u]));
@@ -1023,12 +1024,21 @@ void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nr
   const Cx<R>* U = std::is_same<R, float>::value ? (const Cx<R>*)L.U32.p : (const Cx<R>*)L.U64.p;
   const int64_t V = L.sites();
   const int rb = std::min(4, rhs_block_for(V, nrhs));  // 4 RHS per thread: more workgroups in flight
-  KTimer kt(ctx, "sap", (double)nrhs * V * 2 * sizeof(Cx<R>) * 2.5 + (double)V * sizeof(Cx<R>));
-  // 4x4 blocks when the block checkerboard has even extents (no two neighbouring blocks
-  // share a colour, also across the periodic boundary), else 2x2 blocks (the fine extents
-  // are multiples of 4, so 2x2 block counts are even).
+  // algorithmic bytes of one colour: x of every site (the colour's own and its halo) read
+  // once, b read and x written on the colour's sites (two vector passes), and the links
+  KTimer kt(ctx, "sap", (double)nrhs * V * 2 * sizeof(Cx<R>) * 2 + (double)V * 2 * sizeof(Cx<R>));
+  // 8x4 blocks when the block checkerboard has even extents (no two neighbouring blocks
+  // share a colour, also across the periodic boundary): a block row of one RHS is then
+  // 8 sites x 2 spins = one 128-byte line in complex FP32, so a colour's sweep touches
+  // only its own lines besides the halo.  Else 4x4, else 2x2 blocks (the fine extents are
+  // multiples of 4, so 2x2 block counts are even).
   REQUIRE(L.Lx % 4 == 0 && L.Lt % 4 == 0, "SAP needs fine extents divisible by 4");
-  if (L.Lx % 8 == 0 && L.Lt % 8 == 0) {
+  if (L.Lx % 16 == 0 && L.Lt % 8 == 0) {
+    const int nblk = (L.Lx / 8) * (L.Lt / 4) / 2;  // blocks of one colour
+    dim3 grid((unsigned)ceil_div(nblk, 8), (unsigned)ceil_div(nrhs, rb));
+    hipLaunchKernelGGL((sap_kernel<R, 8, 4>), grid, dim3(256), 0, ctx->stream, U, x, b, L.Lx, L.Lt,
+                       (R)(L.m0 + 2.0), nrhs, rb, color, mr_iters, ld);
+  } else if (L.Lx % 8 == 0 && L.Lt % 8 == 0) {
     const int nblk = (L.Lx / 4) * (L.Lt / 4) / 2;  // blocks of one colour
     dim3 grid((unsigned)ceil_div(nblk, 16), (unsigned)ceil_div(nrhs, rb));
     hipLaunchKernelGGL((sap_kernel<R, 4, 4>), grid, dim3(256), 0, ctx->stream, U, x, b, L.Lx, L.Lt,
@@ -1100,8 +1110,13 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
     REQUIRE(((uintptr_t)xf | (uintptr_t)yc) % 16 == 0, "matrix-core restriction needs 16-byte aligned vectors");
     const AggMap g = agg_map(L);
     const int wpa = g.E / 16 >= 4 ? 4 : 1;  // wavefronts per aggregate
-    hipLaunchKernelGGL(restrict16_mfma_kernel, dim3((unsigned)ceil_div(Vc, 4 / wpa)), dim3(256), 0, ctx->stream,
-                       (const c64*)P, (const c64*)xf, (c64*)yc, g, Vc, nrhs, wpa, ldf, ldc);
+    const dim3 grid((unsigned)ceil_div(Vc, 4 / wpa));
+    if (g.E / 16 / wpa <= 2)
+      hipLaunchKernelGGL(restrict16_mfma_kernel<2>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)xf,
+                         (c64*)yc, g, Vc, nrhs, wpa, ldf, ldc);
+    else
+      hipLaunchKernelGGL(restrict16_mfma_kernel<4>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)xf,
+                         (c64*)yc, g, Vc, nrhs, wpa, ldf, ldc);
     LAUNCH_CHECK();
     return;
   }
@@ -1130,9 +1145,16 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
     const int tiles = g.E / 16;
     const int mtw = tiles % 4 == 0 ? std::min(4, tiles) : (tiles % 2 == 0 ? 2 : 1);
     const int64_t Vc = nc / 16;
-    const int64_t waves = Vc * (tiles / mtw);
-    hipLaunchKernelGGL(prolong16_mfma_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, ctx->stream,
-                       (const c64*)P, (const c64*)ec, (c64*)xf, g, Vc, mtw, nrhs, add ? 1 : 0, ldf, ldc);
+    const dim3 grid((unsigned)ceil_div(Vc * (tiles / mtw), 4));
+    if (mtw == 4)
+      hipLaunchKernelGGL(prolong16_mfma_kernel<4>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                         (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
+    else if (mtw == 2)
+      hipLaunchKernelGGL(prolong16_mfma_kernel<2>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                         (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
+    else
+      hipLaunchKernelGGL(prolong16_mfma_kernel<1>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                         (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
     LAUNCH_CHECK();
     return;
   }
