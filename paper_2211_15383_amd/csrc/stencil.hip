@@ -614,10 +614,20 @@ __global__ __launch_bounds__(256) void coarse16_f64_mfma_kernel(const c128* __re
 // other colour (even extents), so the sweep over one colour is order-independent.  The
 // residual fragment stays in registers as the B operand of the inverse-block product.
 // H16: the four hop blocks and the inverse self block are read from their complex-FP16
-// copies (16 bytes per lane quad instead of 32), kept packed in registers and widened to
-// FP32 just before each product, and the RHS are taken one 16-wide tile at a time, so the
-// wavefront needs few enough registers for four waves per SIMD; the products and the
-// vectors stay complex FP32.
+// copies (16 bytes per lane quad instead of 32) and kept packed in registers, and the RHS
+// are taken one 16-wide tile at a time.  The hop products run on the FP16 matrix cores
+// (the neighbour vectors rounded to complex FP16 after a per-RHS power-of-two scaling, FP32
+// accumulation): two instructions per block instead of sixteen FP32 ones, which were half
+// of the sweep's time.  The inverse self block is widened to FP32 and applied to the FP32
+// residual.  The vectors stay complex FP32.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ half8 as_half8(u32x4 v) { return __builtin_bit_cast(half8, v); }
+__device__ __forceinline__ uint32_t pack_half2(float re, float im) {
+  const _Float16 a = (_Float16)re, b = (_Float16)im;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
 __device__ __forceinline__ c64 half2_to_c64(uint32_t w) {
   const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
   const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
@@ -643,7 +653,6 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
     const uint32_t* A = static_cast<const uint32_t*>(Av);
     const uint32_t* Ainv = static_cast<const uint32_t*>(Ainvv);
     // the blocks are read once per launch: non-temporal loads
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     uint4 a[4];
 #pragma unroll
     for (int dir = 0; dir < 4; ++dir) {
@@ -661,15 +670,37 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
       for (int dir = 0; dir < 4; ++dir) xa[dir] = load_quad(x + oa + sites[dir] * 16);
       Quad qa = load_quad(b + oa - 4 * kq + own);
       __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
+      // hop products on the FP16 matrix cores: the neighbour quads of RHS `row` are scaled
+      // by a power of two that brings their largest component to [2^14, 2^15) (the same
+      // scale for the four lanes of the RHS), rounded to complex FP16 and multiplied by
+      // the stored complex-FP16 blocks with FP32 accumulation, then scaled back.  One
+      // v_mfma_f32_16x16x32_f16 contracts a whole block row: A = the block words as read
+      // (re, im interleaved), B = (re, -im) for the real part and (im, re) for the
+      // imaginary part of the product.
+      float mx = 0.f;
+#pragma unroll
+      for (int dir = 0; dir < 4; ++dir)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mx = fmaxf(mx, fmaxf(fabsf(xa[dir].v[q].x), fabsf(xa[dir].v[q].y)));
+      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      const int ex = mx > 0.f ? __builtin_amdgcn_frexp_expf(mx) : 0;  // mx = f 2^ex, f in [0.5, 1)
+      const float sc = ldexpf(1.f, 15 - ex), unsc = ldexpf(1.f, ex - 15);
       f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
 #pragma unroll
       for (int dir = 0; dir < 4; ++dir) {
-        const uint32_t wv[4] = {a[dir].x, a[dir].y, a[dir].z, a[dir].w};
+        u32x4 w = {0u, 0u, 0u, 0u};
+        if (va) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cmfma(are, aim, half2_to_c64(wv[q]), va ? xa[dir].v[q] : cmk(0.f, 0.f));
+          for (int q = 0; q < 4; ++q) w[q] = pack_half2(sc * xa[dir].v[q].x, sc * xa[dir].v[q].y);
+        }
+        const half8 b_re = as_half8(w ^ 0x80000000u), b_im = as_half8((w >> 16) | (w << 16));
+        const half8 m8 = as_half8(u32x4{a[dir].x, a[dir].y, a[dir].z, a[dir].w});
+        are = __builtin_amdgcn_mfma_f32_16x16x32_f16(m8, b_re, are, 0, 0, 0);
+        aim = __builtin_amdgcn_mfma_f32_16x16x32_f16(m8, b_im, aim, 0, 0, 0);
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) qa.v[v] = cmk(qa.v[v].x - are[v], qa.v[v].y - aim[v]);
+      for (int v = 0; v < 4; ++v) qa.v[v] = cmk(qa.v[v].x - unsc * are[v], qa.v[v].y - unsc * aim[v]);
       f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere;
       const uint32_t wi[4] = {ai.x, ai.y, ai.z, ai.w};
 #pragma unroll
