@@ -162,6 +162,9 @@ dmlmc_status dmlmc_export_deflation(dmlmc_ctx *ctx, const dmlmc_defl *d, void *X
  * V-cycle, its smoother and coarse solves and the operator inside the Krylov solver run
  * in complex FP32; an outer FP64 iterative refinement recomputes the residual in FP64.
  * When proj != NULL (a deflation of this level) B is replaced by (I - W W^H) B.
+ * A right-hand side whose root-mean-square entry lies outside 2^-8 .. 2^8 is solved as
+ * 2^-e B_r (2^e its root mean square, exact in every precision) and its solution scaled
+ * back, so the complex-FP32 bulk neither underflows nor overflows.
  * B, X: device complex128, [nrhs][ld]; X is overwritten (initial guess zero).
  * maxiter bounds the total Krylov iterations per RHS.  Errors: EINVAL (level, nrhs < 1,
  * ld < n_level, null pointers), ENOCONV (rtol not met; X holds the last iterate),

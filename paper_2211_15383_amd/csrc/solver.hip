@@ -63,6 +63,16 @@ __global__ void scale_store_kernel(const c128* __restrict__ w, const double* __r
   }
 }
 
+// v[r] *= s[r] in place (FP64)
+__global__ void scale_inplace_kernel(c128* v, const double* __restrict__ s, int64_t n) {
+  const int r = blockIdx.y;
+  const double f = s[r];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const c128 a = v[r * n + p];
+    v[r * n + p] = cmk(a.x * f, a.y * f);
+  }
+}
+
 // x (RX) = sum_i y[r][i] Z_i (RZ)
 template <typename RZ, typename RX>
 __global__ void combine_kernel(const Cx<RZ>* __restrict__ Z, int k, const c128* __restrict__ y, int ym,
@@ -438,6 +448,34 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
   std::vector<double> bn(nrhs), rn(nrhs), target(nrhs), est;
   launch_norms2<double>(ctx, B, n, nrhs, n, nrm);
   HIPCHK(hipMemcpyAsync(bn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  // A right-hand side whose entries are far from unit size (root mean square beyond
+  // 2^+-8) is solved as 2^-e b with 2^e its root mean square, and the solution scaled
+  // back: a power of two is exact in every precision, and the complex-FP32 bulk (whose
+  // squares would underflow below ~1e-19 or overflow above ~1e19) then sees unit-sized
+  // vectors.  Z2 noise (entries +-1) is never rescaled.
+  std::vector<double> rescale(nrhs, 1.0);
+  bool any_rescale = false;
+  for (int q = 0; q < nrhs; ++q) {
+    if (!std::isfinite(bn[q])) throw DmlmcError(DMLMC_ENUMERIC, "NaN/Inf in the right-hand side");
+    if (bn[q] > 0.0) {
+      const int e = (int)std::lround(0.5 * std::log2(bn[q] / (double)n));
+      if (std::abs(e) > 8) {
+        rescale[q] = std::ldexp(1.0, -e);
+        any_rescale = true;
+      }
+    }
+  }
+  if (any_rescale) {
+    double* sdev = (double*)hier_buf(H, "sv_rsc", l, sizeof(double) * nrhs);
+    c128* Bs = (c128*)hier_buf(H, "sv_Bs", l, sizeof(c128) * (size_t)nrhs * n);
+    HIPCHK(hipMemcpyAsync(sdev, rescale.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, ctx->stream));
+    launch_scale_store<double>(ctx, B, sdev, Bs, n, nrhs, n, n);
+    B = Bs;
+    // the norms of the scaled RHS (the first cycle reads them from the device)
+    launch_norms2<double>(ctx, B, n, nrhs, n, nrm);
+    HIPCHK(hipMemcpyAsync(bn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
+  }
   launch_fill_zero<c128>(ctx, X, (size_t)nrhs * n);
   if (mixed)
     launch_cast<float, double>(ctx, B, U0, n, nrhs, n, ldw);  // r = b at x = 0
@@ -445,7 +483,6 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
     launch_cast<double, double>(ctx, B, Rr, n, nrhs, n, n);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (int q = 0; q < nrhs; ++q) {
-    if (!std::isfinite(bn[q])) throw DmlmcError(DMLMC_ENUMERIC, "NaN/Inf in the right-hand side");
     bn[q] = std::sqrt(bn[q]);
     rn[q] = bn[q];
   }
@@ -490,6 +527,14 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
       if (!std::isfinite(rn[q])) throw DmlmcError(DMLMC_ENUMERIC, "NaN/Inf in the FP64 residual");
       rn[q] = std::sqrt(rn[q]);
     }
+  }
+  if (any_rescale) {
+    for (int q = 0; q < nrhs; ++q) rescale[q] = 1.0 / rescale[q];
+    double* sdev = (double*)hier_buf(H, "sv_rsc", l, sizeof(double) * nrhs);
+    HIPCHK(hipMemcpyAsync(sdev, rescale.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(scale_inplace_kernel, dim3(gridn(n), nrhs), dim3(256), 0, ctx->stream, X, sdev, n);
+    LAUNCH_CHECK();
+    HIPCHK(hipStreamSynchronize(ctx->stream));
   }
   return out;
 }

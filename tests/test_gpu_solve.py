@@ -199,3 +199,22 @@ def test_direct_fp16_scaling_and_mode_switch(gpu):
     assert np.array_equal(out[dm.DIRECT_FP16][0], out[dm.DIRECT_FP16][1])
     assert not np.array_equal(out[dm.DIRECT_FP16][0], out[dm.DIRECT_FP32][0])
     H.coarsest_direct(enable=False)
+
+
+@pytest.mark.parametrize("scale", [1e-30, 1e30, 2.0 ** -40])
+def test_mixed_solve_badly_scaled_rhs(gpu, scale):
+    """A right-hand side far from unit size (entries 1e-30, 1e30, 2^-40) is solved to the same
+    relative residual as the unit-sized one, and its solution is the scaled solution: the
+    complex-FP32 bulk must not underflow or overflow (checked by the checker's matvec)."""
+    torch, dm, ctx = gpu
+    W, lv, H = _gpu_hier(gpu, "schwinger128")
+    for l in (1, 2):
+        D = lv[l - 1].D
+        n = D.shape[0]
+        B = np.column_stack([onoise.z2_noise(21, l, i, n) for i in range(3)]).astype(np.complex128)
+        X1, _ = H.solve(l, to_dev(torch, B), prec=dm.MIXED, rtol=1e-10)
+        Xs, st = H.solve(l, to_dev(torch, B * scale), prec=dm.MIXED, rtol=1e-10)
+        Bs = B * scale
+        res = np.linalg.norm(Bs - D @ to_host(Xs), axis=0) / np.linalg.norm(Bs, axis=0)
+        assert res.max() <= 1e-10 * 1.0001, (l, scale, res.max())
+        assert rel_err(to_host(Xs) / scale, to_host(X1)) < 1e-8, (l, scale)
