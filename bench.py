@@ -347,6 +347,8 @@ def main():
                     help="tolerance of the extra convergence run, where the stopping rule sets N (0: skip)")
     ap.add_argument("--cpu-workload", default="schwinger128")
     ap.add_argument("--cpu-samples", type=int, default=128, help="samples per level of the CPU baseline")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in launch rule of every kernel (skip the launch-variant autotuner)")
     ap.add_argument("--skip-kernel-rates", action="store_true",
                     help="skip the per-kernel runs at the real shapes after the timed steps")
     ap.add_argument("--kernels-only", action="store_true",
@@ -396,6 +398,17 @@ def main():
     torch.cuda.synchronize()
     t_inv = time.perf_counter() - t0
     log(f"coarsest inverse (n = {H.n(L)}, {args.direct}) in {t_inv:.2f} s")
+    tuned = None
+    t_tune = 0.0
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        picks = H.tune_kernels(W.rhs_block, reps=10)
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t0
+        tuned = {f"level{l}_{k}": {"value": v, "us": round(bu, 2), "rule_us": round(du, 2)}
+                 for (l, k), (v, bu, du) in sorted(picks.items())}
+        log(f"kernel variants tuned in {t_tune:.2f} s: "
+            + ", ".join(f"L{l} {k}={v} ({du:.1f} -> {bu:.1f} us)" for (l, k), (v, bu, du) in sorted(picks.items())))
 
     if args.kernels_only:
         copy_gbps = copy_ceiling(torch)  # also the profiler's calibration: 1 GiB read + 1 GiB written
@@ -570,7 +583,8 @@ def main():
                                f"eps={W.eps}, rtol={W.rtol}, "
                                f"{W.n0} initial samples/level, RHS block {W.rhs_block}",
                    "m0": m0, "setup_hierarchy_s": t_hier, "setup_eigensolve_s": t_eig,
-                   "setup_coarsest_inverse_s": t_inv, "coarsest_solve": coarsest,
+                   "setup_coarsest_inverse_s": t_inv, "setup_kernel_tuning_s": t_tune, "kernel_variants": tuned,
+                   "coarsest_solve": coarsest,
                    "precision": "complex FP32 V-cycles, operators and Krylov basis inside FP64 refinement "
                                 "(FP64 Arnoldi, residuals and sample dots); the coarse Gauss-Seidel blocks and "
                                 "the coarsest inverse are read as complex FP16 (FP32 accumulation)",
@@ -580,11 +594,11 @@ def main():
         "speedup_vs_fp64": (fp64["seconds"] / t_mixed) if fp64 else None,
         "fp64_run": fp64,
         "setup_plus_trace_s": {
-            "mixed": t_hier + t_eig + t_inv + t_mixed,
+            "mixed": t_hier + t_eig + t_inv + t_tune + t_mixed,
             "fp64_single_rhs": (t_hier + t_eig + fp64["seconds"]) if fp64 else None,
-            "mixed_only_setup": {"coarsest_inverse_s": t_inv},
+            "mixed_only_setup": {"coarsest_inverse_s": t_inv, "kernel_tuning_s": t_tune},
             "shared_setup": {"hierarchy_s": t_hier, "eigensolve_s": t_eig},
-            "speedup": ((t_hier + t_eig + fp64["seconds"]) / (t_hier + t_eig + t_inv + t_mixed)) if fp64 else None,
+            "speedup": ((t_hier + t_eig + fp64["seconds"]) / (t_hier + t_eig + t_inv + t_tune + t_mixed)) if fp64 else None,
         },
         "direct_off": direct_off,
         "convergence_run": conv,

@@ -315,6 +315,40 @@ dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_def
                                   const int *candidates, int ncand, dmlmc_precision prec, double rtol,
                                   uint64_t noise_seed, int *best, double *sec_per_sample);
 
+/* ---------------------------------------------------------------- launch-variant autotuner
+ * The hot complex-FP32 kernels of the V-cycles each come in launch variants that divide
+ * the same work differently over threads and wavefronts; the arithmetic of every output
+ * entry is the same in all of them, so a choice changes timing only, never a result bit.
+ * Kernel ids and their values (0 always selects the built-in rule):
+ *   DMLMC_KV_WILSON_RB     fine stencil, RHS per thread: 1, 2, 4, 8
+ *   DMLMC_KV_COARSE_SPLIT  coarse block stencil (16 dofs/site): wavefronts per site, 1 or 2
+ *   DMLMC_KV_SAP_RB        SAP colour sweep, RHS per thread: 1, 2, 4, 8
+ *   DMLMC_KV_GS_SPLIT      coarse Gauss-Seidel (FP16 blocks): wavefronts per site, 1 or 2
+ *   DMLMC_KV_RESTRICT_UT   matrix-core restriction: tiles per batch of loads, 1, 2, 4
+ *   DMLMC_KV_PROLONG_MT    matrix-core prolongation: tiles per wavefront, 1, 2, 4 (a value
+ *                          that does not divide the level's tile count falls back to the rule)
+ * dmlmc_tune_kernels times, on every level of h, each variant of each kernel that runs
+ * there at that level's real shape (nrhs right-hand sides at the solver's work stride,
+ * reps launches per variant after one warm-up, HIP events on the context stream) and
+ * keeps the fastest (ties keep the rule).  Choices are cached in the process by (GPU
+ * architecture, kernel, level shape, nrhs, stride); cache_path (nullable) names a text
+ * file read before and rewritten after tuning ("key value" per line), so a later process
+ * reuses them without timing.  picks (nullable, host int [levels][DMLMC_KV_COUNT])
+ * receives each choice (-1: the kernel does not run on that level); best_us and
+ * default_us (nullable, host double, same shape) the time per launch of the choice and
+ * of the rule (both 0 when the choice came from the cache).  Temporary vectors are
+ * allocated and freed inside the call.  Errors: EINVAL (nrhs not in 1..512, reps not in
+ * 1..1000, cache file not writable), EHIP. */
+enum { DMLMC_KV_WILSON_RB = 0, DMLMC_KV_COARSE_SPLIT = 1, DMLMC_KV_SAP_RB = 2, DMLMC_KV_GS_SPLIT = 3,
+       DMLMC_KV_RESTRICT_UT = 4, DMLMC_KV_PROLONG_MT = 5, DMLMC_KV_COUNT = 6 };
+dmlmc_status dmlmc_tune_kernels(dmlmc_ctx *ctx, dmlmc_hier *h, int nrhs, int reps, const char *cache_path,
+                                int *picks, double *best_us, double *default_us);
+/* Sets (or reads) one kernel's variant on one level (1-based) by hand; EINVAL for an
+ * unknown kernel id, a level out of range or a value not listed above.  Recorded HIP
+ * graphs of earlier launches are re-recorded on their next use. */
+dmlmc_status dmlmc_set_kernel_variant(dmlmc_hier *h, int level, int kernel, int value);
+dmlmc_status dmlmc_get_kernel_variant(const dmlmc_hier *h, int level, int kernel, int *value);
+
 /* ---------------------------------------------------------------- single operators
  * Applies one operator of level `level` to nrhs device vectors (for parity checks and
  * kernel timing).  in/out: device, complex128 when prec = DMLMC_FP64 and complex64

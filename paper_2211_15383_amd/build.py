@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libdmlmc.so")
 ARCH = "gfx950"
 
 SOURCES = ["stencil.hip", "blas.hip", "gram.hip", "solver.hip", "setup.hip", "defl.hip", "tsgemm.hip", "dense.hip", "mlmc.hip",
-           "noalloc.hip", "capi.hip", "eigh_host.cpp"]
+           "noalloc.hip", "tune.hip", "capi.hip", "eigh_host.cpp"]
 
 
 def hipcc() -> str:

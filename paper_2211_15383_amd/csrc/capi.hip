@@ -9,6 +9,7 @@
 #include "noalloc.h"
 #include "setup.h"
 #include "solver.h"
+#include "tune.h"
 
 namespace {
 
@@ -525,6 +526,29 @@ dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx* ctx, dmlmc_hier* h, const dmlmc_def
     }
     *best = tune_rhs_block(h, coarsest, candidates, ncand, prec, rtol, noise_seed, sec_per_sample);
   });
+}
+
+dmlmc_status dmlmc_tune_kernels(dmlmc_ctx* ctx, dmlmc_hier* h, int nrhs, int reps, const char* cache_path, int* picks,
+                                double* best_us, double* default_us) {
+  if (!ctx) return DMLMC_EINVAL;
+  return guarded(ctx, [&]() {
+    check_hier(ctx, h);
+    REQUIRE(nrhs >= 1 && nrhs <= 512, "nrhs must be in 1..512");
+    REQUIRE(reps >= 1 && reps <= 1000, "reps must be in 1..1000");
+    static_assert(DMLMC_KV_COUNT == KV_COUNT, "kernel variant ids of the header and the library differ");
+    tune_kernels(h, nrhs, reps, cache_path, picks, best_us, default_us);
+  });
+}
+
+dmlmc_status dmlmc_set_kernel_variant(dmlmc_hier* h, int level, int kernel, int value) {
+  if (!h) return DMLMC_EINVAL;
+  return guarded(h->ctx, [&]() { set_kernel_variant(h, level, kernel, value); });
+}
+
+dmlmc_status dmlmc_get_kernel_variant(const dmlmc_hier* h, int level, int kernel, int* value) {
+  if (!h || !value || level < 1 || level > (int)h->lv.size() || kernel < 0 || kernel >= KV_COUNT) return DMLMC_EINVAL;
+  *value = h->lv[level - 1].kv[kernel];
+  return DMLMC_OK;
 }
 
 dmlmc_status dmlmc_set_deflation(dmlmc_hier* h, const dmlmc_defl* d) {

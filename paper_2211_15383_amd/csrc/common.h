@@ -160,8 +160,22 @@ struct KTimer {
 void timing_collect(dmlmc_ctx* ctx);
 
 // ------------------------------------------------------------------ hierarchy objects
+// Launch variants of the tuned kernels.  A variant changes only how a launch divides its
+// work over threads and wavefronts, never the arithmetic of any output entry, so every
+// variant gives bitwise the same results.  Value 0 takes the built-in rule.
+enum KernelVariant {
+  KV_WILSON_RB = 0,  // fine stencil: RHS per thread (1, 2, 4, 8)
+  KV_COARSE_SPLIT,   // complex-FP32 coarse stencil, d = 16: wavefronts per site (1: both 16-RHS tiles, 2: one each)
+  KV_SAP_RB,         // SAP colour sweep: RHS per thread (1, 2, 4, 8)
+  KV_GS_SPLIT,       // complex-FP16-block Gauss-Seidel, d = 16: wavefronts per site (1, 2)
+  KV_RESTRICT_UT,    // matrix-core restriction: 16-entry tiles whose loads a wavefront issues at once (1, 2, 4)
+  KV_PROLONG_MT,     // matrix-core prolongation: 16-entry tiles per wavefront (1, 2, 4; dividing the tile count)
+  KV_COUNT
+};
+
 struct Level {
   int l = 1;              // 1-based
+  int kv[KV_COUNT] = {};  // launch variants (KernelVariant), 0 = built-in rule
   int Lx = 0, Lt = 0, dofs = 2;
   bool fine = true;
   double m0 = 0.0;

@@ -8,6 +8,7 @@
 //   * restriction P^H and prolongation P on (aggregate, chirality) blocks.
 // Vectors are RHS-major: entry i of RHS r is at r * ld + i; complex interleaved.
 #include "common.h"
+#include "tune.h"
 
 namespace {
 
@@ -395,7 +396,6 @@ __global__ __launch_bounds__(256) void prolong_kernel(const Cx<R>* __restrict__ 
   const int64_t site = tid / df;
   const int x = (int)(site % Lxf), t = (int)(site / Lxf);
   const int Lxc = Lxf / ax;
-  const int64_t Vc = (int64_t)Lxc * (Ltf / at);
   const int64_t cs = (int64_t)(x / ax) + (int64_t)Lxc * (t / at);
   const int h = df / 2;
   const int c = dof / h, j = dof % h;
@@ -449,13 +449,19 @@ struct Quad {
   c64 v[4];
 };
 
-// Coarse blocks and interpolation blocks are streamed once per launch: non-temporal loads
-// keep them from displacing the vectors' neighbour re-reads in the caches.
+// Interpolation blocks (and the Gauss-Seidel blocks) are streamed once per launch:
+// non-temporal loads keep them from displacing the vectors' neighbour re-reads in the
+// caches.  (The coarse stencil reads its blocks with ordinary loads: non-temporal ones
+// made its level-2 launch slower, 288 -> 320 us at 1024^2, measured.)  Two 16-byte loads;
+// p is 16-byte aligned.
 __device__ __forceinline__ Quad load_quad_nt(const c64* __restrict__ p) {
-  const float* f = reinterpret_cast<const float*>(p);
+  const f32x4* q = reinterpret_cast<const f32x4*>(p);
+  const f32x4 u = __builtin_nontemporal_load(q), w = __builtin_nontemporal_load(q + 1);
   Quad r;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) r.v[v] = cmk(__builtin_nontemporal_load(f + 2 * v), __builtin_nontemporal_load(f + 2 * v + 1));
+  r.v[0] = cmk(u[0], u[1]);
+  r.v[1] = cmk(u[2], u[3]);
+  r.v[2] = cmk(w[0], w[1]);
+  r.v[3] = cmk(w[2], w[3]);
   return r;
 }
 
@@ -482,13 +488,12 @@ __device__ __forceinline__ void store_quad(c64* __restrict__ p, f32x4 re, f32x4 
 }
 
 // Non-temporal form for results that the same launch does not read again.
+// (two 16-byte stores, so that the four lanes of a 128-byte line write it whole)
 __device__ __forceinline__ void store_quad_nt(c64* __restrict__ p, f32x4 re, f32x4 im) {
-  float* f = reinterpret_cast<float*>(p);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    __builtin_nontemporal_store(re[v], f + 2 * v);
-    __builtin_nontemporal_store(im[v], f + 2 * v + 1);
-  }
+  f32x4* q = reinterpret_cast<f32x4*>(p);
+  const f32x4 u = {re[0], im[0], re[1], im[1]}, w = {re[2], im[2], re[3], im[3]};
+  __builtin_nontemporal_store(u, q);
+  __builtin_nontemporal_store(w, q + 1);
 }
 
 // D += A X for one 16 x 16 block (a: lane's A row quarter, x: lane's B quarter).
@@ -505,22 +510,44 @@ __device__ __forceinline__ Quad select_quad(bool keep, const Quad& q) {
   return r;
 }
 
-// y_s = sum_dir A[s][dir] x_{s+dir} (optionally Gamma5 y), one site per wavefront, all
-// RHS in pairs of 16-wide tiles.  Every load of a tile pair is issued before the first
-// product (rows beyond nrhs load a valid row and are zeroed), so the wavefront has all
-// its memory requests in flight at once.
-template <bool G5>
+// y_s = sum_dir A[s][dir] x_{s+dir} (optionally Gamma5 y).  SPLIT = 1: one site per
+// wavefront, all RHS in pairs of 16-wide tiles; SPLIT = 2: two wavefronts per site (the
+// same workgroup), each taking every other 16-wide tile.  Every load of a pass is issued
+// before the first product (rows beyond nrhs load a valid row and are zeroed), so the
+// wavefront has all its memory requests in flight at once.  Each output tile is the same
+// sequence of products in both forms.
+template <bool G5, int SPLIT>
 __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ in,
                                                             c64* __restrict__ out, int Lx, int Lt, int nrhs,
                                                             int64_t ldx, int64_t ldy) {
   const int64_t V = (int64_t)Lx * Lt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t s = xcd_block() * 4 + w;
+  const int64_t wv = xcd_block() * 4 + w;
+  const int64_t s = wv / SPLIT;
   if (s >= V) return;  // wave-uniform: the MFMAs below always run with a full wavefront
   const int row = lane & 15, kq = lane >> 4;
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
   const float sg = (G5 && kq >= 2) ? -1.f : 1.f;
+  if constexpr (SPLIT == 2) {
+    for (int r0 = 16 * (int)(wv % 2); r0 < nrhs; r0 += 32) {
+      const int ra = r0 + row;
+      const bool va = ra < nrhs;
+      const int64_t oa = (int64_t)min(ra, nrhs - 1) * ldx + 4 * kq;
+      Quad a[5], xa[5];
+#pragma unroll
+      for (int dir = 0; dir < 5; ++dir) {
+        a[dir] = load_quad(A + (s * 5 + dir) * 256 + row * 16 + 4 * kq);
+        xa[dir] = load_quad(in + oa + sites[dir] * 16);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
+#pragma unroll
+      for (int dir = 0; dir < 5; ++dir) block_mfma(are, aim, a[dir], select_quad(va, xa[dir]));
+      if (va) store_quad(out + (int64_t)ra * ldy + s * 16 + 4 * kq, are, aim, sg);
+    }
+    return;
+  }
   for (int r0 = 0; r0 < nrhs; r0 += 32) {
     const int ra = r0 + row, rb = r0 + 16 + row;
     const bool va = ra < nrhs, vb = rb < nrhs;
@@ -634,13 +661,17 @@ __device__ __forceinline__ c64 half2_to_c64(uint32_t w) {
   return cmk((float)re, (float)im);
 }
 
-template <bool H16>
+// SPLIT (H16 only): wavefronts per site; with 2, the two wavefronts of a site (same
+// workgroup) take every other 16-RHS tile, each reading the site's blocks.
+template <bool H16, int SPLIT>
 __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __restrict__ Av,
                                                                const void* __restrict__ Ainvv, c64* __restrict__ x,
                                                                const c64* __restrict__ b, int Lx, int Lt, int nrhs,
                                                                int color, int64_t ld) {
+  static_assert(SPLIT == 1 || (H16 && SPLIT == 2), "two wavefronts per site only with the FP16 blocks");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t k = xcd_block() * 4 + w;
+  const int64_t wv = xcd_block() * 4 + w;
+  const int64_t k = wv / SPLIT;
   const int64_t half = Lx / 2;
   const int64_t t = k / half;
   if (t >= Lt) return;  // wave-uniform
@@ -661,7 +692,7 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
     }
     const u32x4 vi = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(Ainv + s * 256 + row * 16 + 4 * kq));
     const uint4 ai = make_uint4(vi.x, vi.y, vi.z, vi.w);
-    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    for (int r0 = 16 * (int)(wv % SPLIT); r0 < nrhs; r0 += 16 * SPLIT) {
       const int ra = r0 + row;
       const bool va = ra < nrhs;
       const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq;
@@ -928,12 +959,14 @@ inline int rhs_block_for(int64_t threads, int nrhs) {
 
 }  // namespace
 
+bool transfer16_available(const Level& L) { return transfer16_ok(L); }
+
 template <typename R>
 void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx, int64_t ldy,
                    bool gamma5_left, const Cx<R>* sub) {
   const int64_t V = L.sites();
   // at most 8 RHS per thread: more workgroups in flight; links are re-read nrhs / 8 times
-  const int rb = std::min(8, rhs_block_for(V, nrhs));
+  const int rb = L.kv[KV_WILSON_RB] > 0 ? std::min(L.kv[KV_WILSON_RB], nrhs) : std::min(8, rhs_block_for(V, nrhs));
   dim3 grid((unsigned)ceil_div(V, 256), (unsigned)ceil_div(nrhs, rb));
   const Cx<R>* U = std::is_same<R, float>::value ? (const Cx<R>*)L.U32.p : (const Cx<R>*)L.U64.p;
   REQUIRE(!(sub && gamma5_left), "the residual form has no Gamma5");
@@ -961,13 +994,22 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
     REQUIRE(sub == nullptr, "the complex-FP32 matrix-core stencil has no residual form");
     REQUIRE(ldx % 2 == 0 && ldy % 2 == 0 && ((uintptr_t)x | (uintptr_t)y) % 16 == 0,
             "matrix-core coarse stencil needs 16-byte aligned RHS rows");
-    dim3 grid((unsigned)ceil_div(V, 4));
-    if (gamma5_left)
-      hipLaunchKernelGGL((coarse16_mfma_kernel<true>), grid, dim3(256), 0, ctx->stream, (const c64*)A, (const c64*)x,
-                         (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
-    else
-      hipLaunchKernelGGL((coarse16_mfma_kernel<false>), grid, dim3(256), 0, ctx->stream, (const c64*)A, (const c64*)x,
-                         (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    const int split = L.kv[KV_COARSE_SPLIT] == 2 ? 2 : 1;
+    dim3 grid((unsigned)ceil_div(V * split, 4));
+    if (split == 2) {
+      if (gamma5_left)
+        hipLaunchKernelGGL((coarse16_mfma_kernel<true, 2>), grid, dim3(256), 0, ctx->stream, (const c64*)A,
+                           (const c64*)x, (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+      else
+        hipLaunchKernelGGL((coarse16_mfma_kernel<false, 2>), grid, dim3(256), 0, ctx->stream, (const c64*)A,
+                           (const c64*)x, (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    } else if (gamma5_left) {
+      hipLaunchKernelGGL((coarse16_mfma_kernel<true, 1>), grid, dim3(256), 0, ctx->stream, (const c64*)A,
+                         (const c64*)x, (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    } else {
+      hipLaunchKernelGGL((coarse16_mfma_kernel<false, 1>), grid, dim3(256), 0, ctx->stream, (const c64*)A,
+                         (const c64*)x, (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    }
     LAUNCH_CHECK();
     return;
   }
@@ -1054,7 +1096,8 @@ void launch_sap(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, int nr
   REQUIRE(ld >= L.n() && ld % 2 == 0, "SAP vectors need an even stride of at least the level size");
   const Cx<R>* U = std::is_same<R, float>::value ? (const Cx<R>*)L.U32.p : (const Cx<R>*)L.U64.p;
   const int64_t V = L.sites();
-  const int rb = std::min(4, rhs_block_for(V, nrhs));  // 4 RHS per thread: more workgroups in flight
+  // 4 RHS per thread (more workgroups in flight) unless tuned
+  const int rb = L.kv[KV_SAP_RB] > 0 ? std::min(L.kv[KV_SAP_RB], nrhs) : std::min(4, rhs_block_for(V, nrhs));
   // algorithmic bytes of one colour: x of every site (the colour's own and its halo) read
   // once, b read and x written on the colour's sites (two vector passes), and the links
   KTimer kt(ctx, "sap", (double)nrhs * V * 2 * sizeof(Cx<R>) * 2 + (double)V * 2 * sizeof(Cx<R>));
@@ -1105,11 +1148,14 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
     const bool h16 = half && L.Ahop16.p && L.Ainv16.p;
     KTimer kt(ctx, "coarse_gs",
               (double)nrhs * (V / 2) * d * 3 * sizeof(Cx<R>) + (double)(V / 2) * 5 * d * d * (h16 ? 4 : sizeof(Cx<R>)));
-    if (h16)
-      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
+    if (h16 && L.kv[KV_GS_SPLIT] == 2)
+      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true, 2>), dim3((unsigned)ceil_div(nsites * 2, 4)), dim3(256), 0,
+                         ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, ld);
+    else if (h16)
+      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true, 1>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
                          ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, ld);
     else
-      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<false>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
+      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<false, 1>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
                          ctx->stream, (const void*)A, (const void*)Ai, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs,
                          color, ld);
     LAUNCH_CHECK();
@@ -1142,7 +1188,11 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
     const AggMap g = agg_map(L);
     const int wpa = g.E / 16 >= 4 ? 4 : 1;  // wavefronts per aggregate
     const dim3 grid((unsigned)ceil_div(Vc, 4 / wpa));
-    if (g.E / 16 / wpa <= 2)
+    const int ut = L.kv[KV_RESTRICT_UT] > 0 ? L.kv[KV_RESTRICT_UT] : (g.E / 16 / wpa <= 2 ? 2 : 4);
+    if (ut == 1)
+      hipLaunchKernelGGL(restrict16_mfma_kernel<1>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)xf,
+                         (c64*)yc, g, Vc, nrhs, wpa, ldf, ldc);
+    else if (ut == 2)
       hipLaunchKernelGGL(restrict16_mfma_kernel<2>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)xf,
                          (c64*)yc, g, Vc, nrhs, wpa, ldf, ldc);
     else
@@ -1174,7 +1224,9 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
     REQUIRE(((uintptr_t)ec | (uintptr_t)xf) % 16 == 0, "matrix-core prolongation needs 16-byte aligned vectors");
     const AggMap g = agg_map(L);
     const int tiles = g.E / 16;
-    const int mtw = tiles % 4 == 0 ? std::min(4, tiles) : (tiles % 2 == 0 ? 2 : 1);
+    const int tuned = L.kv[KV_PROLONG_MT];
+    const int mtw = (tuned > 0 && tiles % tuned == 0) ? tuned
+                                                      : (tiles % 4 == 0 ? std::min(4, tiles) : (tiles % 2 == 0 ? 2 : 1));
     const int64_t Vc = nc / 16;
     const dim3 grid((unsigned)ceil_div(Vc * (tiles / mtw), 4));
     if (mtw == 4)

@@ -22,6 +22,10 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 DIRECT_OFF, DIRECT_FP32, DIRECT_FP16, DIRECT_FP8 = 0, 1, 2, 3
 OP_D, OP_RESTRICT, OP_PROLONG, OP_SMOOTH, OP_VCYCLE, OP_DEFL_C, OP_DEFL_P, OP_GAMMA5_D = 0, 1, 2, 3, 4, 6, 7, 8
+# launch-variant autotuner kernel ids (dmlmc_tune_kernels)
+KV_WILSON_RB, KV_COARSE_SPLIT, KV_SAP_RB, KV_GS_SPLIT, KV_RESTRICT_UT, KV_PROLONG_MT = range(6)
+KV_COUNT = 6
+KV_NAMES = ("wilson_rb", "coarse_split", "sap_rb", "gs_split", "restrict_ut", "prolong_mt")
 
 EXPORTED = [
     "dmlmc_create", "dmlmc_destroy", "dmlmc_last_error", "dmlmc_version", "dmlmc_build_hierarchy",
@@ -31,7 +35,8 @@ EXPORTED = [
     "dmlmc_apply", "dmlmc_set_deflation", "dmlmc_z2_noise", "dmlmc_set_solver_params",
     "dmlmc_get_solver_params", "dmlmc_timing_enable", "dmlmc_timing_select", "dmlmc_tune_rhs_block",
     "dmlmc_coarsest_direct", "dmlmc_deflate_project_noalloc",
-    "dmlmc_timing_reset", "dmlmc_timing_get",
+    "dmlmc_timing_reset", "dmlmc_timing_get", "dmlmc_tune_kernels", "dmlmc_set_kernel_variant",
+    "dmlmc_get_kernel_variant",
 ]
 
 
@@ -113,6 +118,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_tune_rhs_block": (i32, [vp, vp, vp, C.POINTER(i32), i32, i32, dbl, C.c_uint64, C.POINTER(i32),
                                        C.POINTER(dbl)]),
         "dmlmc_timing_get": (i32, [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
+        "dmlmc_tune_kernels": (i32, [vp, vp, i32, i32, C.c_char_p, C.POINTER(i32), C.POINTER(dbl), C.POINTER(dbl)]),
+        "dmlmc_set_kernel_variant": (i32, [vp, i32, i32, i32]),
+        "dmlmc_get_kernel_variant": (i32, [vp, i32, i32, C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -344,6 +352,35 @@ class Hierarchy:
         self.ctx.check(lib().dmlmc_tune_rhs_block(self.ctx.h, self.h, defl.h if defl is not None else None, cand,
                                                   len(candidates), prec, rtol, noise_seed, C.byref(best), secs))
         return best.value, {c: secs[i] for i, c in enumerate(candidates)}
+
+    def tune_kernels(self, nrhs: int, reps: int = 10, cache_path: Optional[str] = None):
+        """Launch-variant autotuner (see dmlmc_tune_kernels); returns {(level, kernel name):
+        (choice, us of the choice, us of the built-in rule)} for the kernels run on each level."""
+        L = self.nlevels
+        picks = (C.c_int32 * (L * KV_COUNT))()
+        best = (C.c_double * (L * KV_COUNT))()
+        dflt = (C.c_double * (L * KV_COUNT))()
+        path = cache_path.encode() if cache_path else None
+        self.ctx.check(lib().dmlmc_tune_kernels(self.ctx.h, self.h, nrhs, reps, path, picks, best, dflt))
+        out = {}
+        for l in range(L):
+            for k, name in enumerate(KV_NAMES):
+                i = l * KV_COUNT + k
+                if picks[i] >= 0:
+                    out[(l + 1, name)] = (picks[i], best[i], dflt[i])
+        return out
+
+    def set_kernel_variant(self, level: int, kernel: int, value: int):
+        st = lib().dmlmc_set_kernel_variant(self.h, level, kernel, value)
+        if st != OK:
+            raise DmlmcError(st, f"set_kernel_variant({level}, {kernel}, {value})")
+
+    def kernel_variant(self, level: int, kernel: int) -> int:
+        v = C.c_int32()
+        st = lib().dmlmc_get_kernel_variant(self.h, level, kernel, C.byref(v))
+        if st != OK:
+            raise DmlmcError(st, f"kernel_variant({level}, {kernel})")
+        return v.value
 
     def coarsest_direct(self, defl: Optional["Deflation"] = None, enable=True):
         """Explicit-inverse coarsest solve (computed on first use): enable True or

@@ -99,3 +99,13 @@ def test_recorded_traffic_lookup():
     got, src = b.recorded_traffic("coarse_gs", alg)
     assert got == float(m.group(2)) and src.startswith("hbm_traffic_")
     assert b.recorded_traffic("coarse_gs", alg * 1.02) == (None, None)
+
+
+def test_kernel_variant_calls_reject_bad_arguments():
+    """The launch-variant calls validate their handles before any device work."""
+    from paper_2211_15383_amd import dmlmc
+    lib = dmlmc.load()
+    v = C.c_int32()
+    assert lib.dmlmc_set_kernel_variant(None, 1, 0, 1) == dmlmc.EINVAL
+    assert lib.dmlmc_get_kernel_variant(None, 1, 0, C.byref(v)) == dmlmc.EINVAL
+    assert lib.dmlmc_tune_kernels(None, None, 32, 10, None, None, None, None) == dmlmc.EINVAL

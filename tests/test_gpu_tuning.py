@@ -98,3 +98,60 @@ def test_smoothing_parameters(gpu):
             dev = np.max(np.abs(r.samples[l] - base.samples[l]))
             assert dev <= 1e-7 * np.max(np.abs(base.samples[l])), (fine, coarse, inner, half, l, dev)
     H.solver_params(**p0)
+
+
+def test_kernel_variants_leave_samples_bitwise_identical(gpu, tmp_path):
+    """Launch variants (RHS per thread, wavefronts per site, tiles per wavefront) change how
+    work is divided, not what is computed: estimates with every variant forced on every
+    level, and with the autotuner's picks, give bitwise the samples of the built-in rule;
+    the tuner reports a choice for each kernel on each level where it runs and writes
+    its cache file, which a second tuning reads back without timing."""
+    torch, dm, ctx = gpu
+    name = "schwinger128"
+    W, m0, lv = oracle_hierarchy(name)
+    H = dm.Hierarchy(ctx, W.theta(), m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                     import_tv=[l.V for l in lv[:-1]])
+    ref = oracle_deflation(name, W.k_defl)
+    d = dm.Deflation(H, len(lv), W.k_defl, import_X=ref.X, import_lambda=ref.lam)
+    L = len(lv)
+    kw = dict(prec=dm.MIXED, rtol=W.rtol, fixed_counts=True, max_samples=[32] * L, keep_samples=True)
+    base = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [32] * L, 32, **kw)
+    forced = [
+        {dm.KV_WILSON_RB: 1, dm.KV_COARSE_SPLIT: 2, dm.KV_SAP_RB: 1, dm.KV_GS_SPLIT: 2, dm.KV_RESTRICT_UT: 1,
+         dm.KV_PROLONG_MT: 1},
+        {dm.KV_WILSON_RB: 8, dm.KV_COARSE_SPLIT: 1, dm.KV_SAP_RB: 8, dm.KV_GS_SPLIT: 1, dm.KV_RESTRICT_UT: 4,
+         dm.KV_PROLONG_MT: 2},
+        {dm.KV_WILSON_RB: 2, dm.KV_SAP_RB: 2, dm.KV_RESTRICT_UT: 2, dm.KV_PROLONG_MT: 4},
+    ]
+    for case in forced:
+        for l in range(1, L + 1):
+            for k, v in case.items():
+                H.set_kernel_variant(l, k, v)
+                assert H.kernel_variant(l, k) == v
+        print(f"[variants] forced {case}", flush=True)
+        r = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [32] * L, 32, **kw)
+        for l in range(L):
+            assert np.array_equal(r.samples[l], base.samples[l]), (case, l)
+    with pytest.raises(dm.DmlmcError):
+        H.set_kernel_variant(1, dm.KV_SAP_RB, 3)
+    with pytest.raises(dm.DmlmcError):
+        H.set_kernel_variant(L + 1, dm.KV_SAP_RB, 1)
+    cache = str(tmp_path / "variants.txt")
+    picks = H.tune_kernels(32, reps=3, cache_path=cache)
+    print(f"[variants] tuned {picks}", flush=True)
+    kinds = {k for (_, k) in picks}
+    assert {"wilson_rb", "sap_rb", "coarse_split", "gs_split", "restrict_ut", "prolong_mt"} <= kinds
+    for (l, k), (v, best, rule) in picks.items():
+        assert H.kernel_variant(l, dm.KV_NAMES.index(k)) == v
+        assert best > 0 and rule > 0 and best <= rule
+    lines = open(cache).read().split("\n")
+    assert sum(1 for s in lines if s.strip()) == len(picks)
+    r = dm.mlmc_trace(H, d, 1e-2, W.noise_seed, [32] * L, 32, **kw)
+    for l in range(L):
+        assert np.array_equal(r.samples[l], base.samples[l])
+    # a second hierarchy of the same shapes takes the cached choices without timing them
+    H2 = dm.Hierarchy(ctx, W.theta(), m0, W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                      import_tv=[l.V for l in lv[:-1]])
+    again = H2.tune_kernels(32, reps=3, cache_path=cache)
+    assert {key: v[0] for key, v in again.items()} == {key: v[0] for key, v in picks.items()}
+    assert all(v[1] == 0.0 and v[2] == 0.0 for v in again.values())
