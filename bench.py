@@ -9,7 +9,8 @@ deflation projections, multigrid-preconditioned solves, sample dots, accumulatio
 allocation) with identical sample sets in both precisions.  The timed steps carry no
 timing events, so the recorded HIP graphs of the FGMRES iterations are replayed; the
 dominant kernel's launch times come from a second pass over the same steps with events
-around that kernel only.  Setup (hierarchy, coarsest eigensolve, explicit coarsest
+around that kernel only (one event pair around each run of its back-to-back launches, such
+as the colour sweeps of a smoother: launch time = run time / launches in the run).  Setup (hierarchy, coarsest eigensolve, explicit coarsest
 inverse) is timed separately, like the paper's "eig.+direct" column, and added in the
 setup-plus-trace totals.  Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -349,6 +350,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=128, help="samples per level of the CPU baseline")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch rule of every kernel (skip the launch-variant autotuner)")
+    ap.add_argument("--tune-cache", default=None, metavar="FILE",
+                    help="launch-variant choices: read from FILE if it holds them, else tuned and written there "
+                         "(profiler runs of the same build then launch the same kernels)")
     ap.add_argument("--skip-kernel-rates", action="store_true",
                     help="skip the per-kernel runs at the real shapes after the timed steps")
     ap.add_argument("--kernels-only", action="store_true",
@@ -402,7 +406,7 @@ def main():
     t_tune = 0.0
     if not args.no_tune:
         t0 = time.perf_counter()
-        picks = H.tune_kernels(W.rhs_block, reps=10)
+        picks = H.tune_kernels(W.rhs_block, reps=10, cache_path=args.tune_cache)
         torch.cuda.synchronize()
         t_tune = time.perf_counter() - t0
         tuned = {f"level{l}_{k}": {"value": v, "us": round(bu, 2), "rule_us": round(du, 2)}

@@ -278,8 +278,11 @@ dmlmc_status dmlmc_deflate_difference(dmlmc_ctx *ctx, dmlmc_hier *h, int a, int 
  * and so the preconditioner of solves at the coarsest level) apply the explicit inverse
  * D_L^-1 instead of the fixed-count GMRES; the paper's coarsest level is likewise solved
  * directly.  The inverse is computed once, column by column from multi-RHS solves of
- * D_L X = I refined in FP64 to 1e-10 (coarsest, if given, deflates their V-cycles), and
- * kept in complex FP32: n_L^2 * 8 bytes (2.1 GB at n_L = 16384).
+ * D_L X = I (1024 columns per solve) refined in FP64 to a residual of 1e-8 for
+ * enable = 1 and 1e-6 for the FP16 and 8-bit copies, far below the rounding of the copy
+ * applied (coarsest, if given, deflates their V-cycles); an inverse built to the looser
+ * tolerance is rebuilt when enable = 1 asks for the tighter one.  It is kept in complex
+ * FP32: n_L^2 * 8 bytes (2.1 GB at n_L = 16384).
  *   enable = 1: applied in FP32 on the matrix cores (exact to FP32 rounding);
  *   enable = 2: applied from a complex-FP16 copy (n_L^2 * 4 more bytes, made on first
  *               use; one power-of-two scale for the matrix and one per RHS, FP32
@@ -323,14 +326,15 @@ dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_def
  *   DMLMC_KV_WILSON_RB     fine stencil, RHS per thread: 1, 2, 4, 8
  *   DMLMC_KV_COARSE_SPLIT  coarse block stencil (16 dofs/site): wavefronts per site, 1 or 2
  *   DMLMC_KV_SAP_RB        SAP colour sweep, RHS per thread: 1, 2, 4, 8
- *   DMLMC_KV_GS_SPLIT      coarse Gauss-Seidel (FP16 blocks): wavefronts per site, 1 or 2
+ *   DMLMC_KV_GS_SPLIT      coarse Gauss-Seidel (FP16 blocks): wavefronts per site, 1 or 2;
+ *                          3: one wavefront per site with two 16-RHS tiles' loads in flight
  *   DMLMC_KV_RESTRICT_UT   matrix-core restriction: tiles per batch of loads, 1, 2, 4
  *   DMLMC_KV_PROLONG_MT    matrix-core prolongation: tiles per wavefront, 1, 2, 4 (a value
  *                          that does not divide the level's tile count falls back to the rule)
  * dmlmc_tune_kernels times, on every level of h, each variant of each kernel that runs
  * there at that level's real shape (nrhs right-hand sides at the solver's work stride,
  * reps launches per variant after one warm-up, HIP events on the context stream) and
- * keeps the fastest (ties keep the rule).  Choices are cached in the process by (GPU
+ * keeps the fastest if it beats the built-in rule by more than 2 % (else the rule).  Choices are cached in the process by (GPU
  * architecture, kernel, level shape, nrhs, stride); cache_path (nullable) names a text
  * file read before and rewritten after tuning ("key value" per line), so a later process
  * reuses them without timing.  picks (nullable, host int [levels][DMLMC_KV_COUNT])

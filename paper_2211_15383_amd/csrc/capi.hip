@@ -2,6 +2,7 @@
 // error translation (no exception crosses the ABI) and kernel-class timing.
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 
 #include "defl.h"
 #include "dense.h"
@@ -48,9 +49,12 @@ void check_level(const dmlmc_hier* h, int level) {
 }  // namespace
 
 // ---------------------------------------------------------------- timing
-KTimer::KTimer(dmlmc_ctx* c, const char* k, double b) : ctx(c), cls(k), bytes(b) {
-  if (!ctx || !ctx->timing) return;
-  if (!ctx->timing_only.empty() && !ctx->timing_only.count(k)) return;
+namespace {
+bool class_timed(const dmlmc_ctx* ctx, const char* k) {
+  return ctx && ctx->timing && (ctx->timing_only.empty() || ctx->timing_only.count(k));
+}
+
+void take_events(dmlmc_ctx* ctx, hipEvent_t& e0, hipEvent_t& e1) {
   if (!ctx->event_pool.empty()) {
     e0 = ctx->event_pool.back().first;
     e1 = ctx->event_pool.back().second;
@@ -59,6 +63,17 @@ KTimer::KTimer(dmlmc_ctx* c, const char* k, double b) : ctx(c), cls(k), bytes(b)
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
   }
+}
+}  // namespace
+
+KTimer::KTimer(dmlmc_ctx* c, const char* k, double b) : ctx(c), cls(k), bytes(b) {
+  if (!class_timed(ctx, k)) return;
+  if (ctx->group_cls && std::strcmp(ctx->group_cls, k) == 0) {
+    ctx->group_bytes += b;
+    ctx->group_launches += 1;
+    return;
+  }
+  take_events(ctx, e0, e1);
   HIPCHK(hipEventRecord(e0, ctx->stream));
 }
 
@@ -68,6 +83,30 @@ KTimer::~KTimer() {
   TimerClass& t = ctx->timers[cls];
   t.pending.emplace_back(e0, e1);
   t.pending_bytes.push_back(bytes);
+  t.pending_launches.push_back(1);
+}
+
+KTimerGroup::KTimerGroup(dmlmc_ctx* c, const char* k) : ctx(c), cls(k) {
+  if (!class_timed(ctx, k) || ctx->group_cls) return;
+  take_events(ctx, e0, e1);
+  ctx->group_cls = k;
+  ctx->group_bytes = 0.0;
+  ctx->group_launches = 0;
+  HIPCHK(hipEventRecord(e0, ctx->stream));
+}
+
+KTimerGroup::~KTimerGroup() {
+  if (!e0) return;
+  (void)hipEventRecord(e1, ctx->stream);
+  ctx->group_cls = nullptr;
+  if (ctx->group_launches == 0) {
+    ctx->event_pool.emplace_back(e0, e1);
+    return;
+  }
+  TimerClass& t = ctx->timers[cls];
+  t.pending.emplace_back(e0, e1);
+  t.pending_bytes.push_back(ctx->group_bytes);
+  t.pending_launches.push_back(ctx->group_launches);
 }
 
 void timing_collect(dmlmc_ctx* ctx) {
@@ -78,12 +117,13 @@ void timing_collect(dmlmc_ctx* ctx) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, t.pending[i].first, t.pending[i].second));
       t.ms += ms;
-      t.launches += 1;
+      t.launches += t.pending_launches[i];
       t.bytes += t.pending_bytes[i];
       ctx->event_pool.push_back(t.pending[i]);
     }
     t.pending.clear();
     t.pending_bytes.clear();
+    t.pending_launches.clear();
   }
 }
 
@@ -501,7 +541,18 @@ dmlmc_status dmlmc_coarsest_direct(dmlmc_ctx* ctx, dmlmc_hier* h, const dmlmc_de
       h->coarse_dinv_n = 0;
       return;
     }
-    if (h->coarse_dinv_n == 0) build_coarse_direct(h, coarsest);
+    // column tolerance: well below the rounding of the copy that is applied (FP32: 1e-8;
+    // the FP16 and 8-bit copies round at ~5e-4 and ~6e-2): the inverse is a preconditioner
+    // component, so its accuracy only moves iteration counts
+    const double rtol = enable == 1 ? 1e-8 : 1e-6;
+    if (h->coarse_dinv_n != 0 && h->coarse_dinv_rtol > rtol) {
+      h->coarse_dinv.release();
+      h->coarse_dinv16.release();
+      h->coarse_dinv8.release();
+      h->coarse_dinv8_rows.release();
+      h->coarse_dinv_n = 0;
+    }
+    if (h->coarse_dinv_n == 0) build_coarse_direct(h, coarsest, rtol);
     if (enable == 2 && h->coarse_dinv16.p == nullptr) build_coarse_direct16(h);
     if (enable == 3 && h->coarse_dinv8.p == nullptr) build_coarse_direct8(h);
     h->coarse_direct_mode = enable;

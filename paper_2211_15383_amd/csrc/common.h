@@ -132,6 +132,7 @@ struct TimerClass {
   double bytes = 0.0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<double> pending_bytes;
+  std::vector<int64_t> pending_launches;
 };
 
 struct dmlmc_ctx {
@@ -146,6 +147,10 @@ struct dmlmc_ctx {
   DevBuf scratch_dots;   // reduction partials
   DevBuf scratch_small;  // small per-RHS device results
   void* noalloc_scratch = nullptr;  // device address of the allocation-free entry point's array
+  // open KTimerGroup: launches of this class are counted into it instead of timed alone
+  const char* group_cls = nullptr;
+  double group_bytes = 0.0;
+  int64_t group_launches = 0;
 };
 
 // RAII bracket around one launch of a timed kernel class.
@@ -157,6 +162,17 @@ struct KTimer {
   KTimer(dmlmc_ctx* c, const char* k, double b);
   ~KTimer();
 };
+// One event pair around a run of back-to-back launches of one class (the colour sweeps of
+// a smoother): each KTimer of that class inside only adds its launch and bytes, so the
+// class's launch time is the run's elapsed time over its launches, without an event pair
+// between every two launches.
+struct KTimerGroup {
+  dmlmc_ctx* ctx;
+  const char* cls;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  KTimerGroup(dmlmc_ctx* c, const char* k);
+  ~KTimerGroup();
+};
 void timing_collect(dmlmc_ctx* ctx);
 
 // ------------------------------------------------------------------ hierarchy objects
@@ -167,7 +183,7 @@ enum KernelVariant {
   KV_WILSON_RB = 0,  // fine stencil: RHS per thread (1, 2, 4, 8)
   KV_COARSE_SPLIT,   // complex-FP32 coarse stencil, d = 16: wavefronts per site (1: both 16-RHS tiles, 2: one each)
   KV_SAP_RB,         // SAP colour sweep: RHS per thread (1, 2, 4, 8)
-  KV_GS_SPLIT,       // complex-FP16-block Gauss-Seidel, d = 16: wavefronts per site (1, 2)
+  KV_GS_SPLIT,       // complex-FP16-block Gauss-Seidel, d = 16: 1, 2 wavefronts per site; 3: tile pairs in flight
   KV_RESTRICT_UT,    // matrix-core restriction: 16-entry tiles whose loads a wavefront issues at once (1, 2, 4)
   KV_PROLONG_MT,     // matrix-core prolongation: 16-entry tiles per wavefront (1, 2, 4; dividing the tile count)
   KV_COUNT
@@ -231,6 +247,7 @@ struct dmlmc_hier {
   DevBuf coarse_dinv8;
   DevBuf coarse_dinv8_rows;
   int64_t coarse_dinv_n = 0;
+  double coarse_dinv_rtol = 0.0;  // residual tolerance of the column solves it was built with
   float coarse_dinv16_unscale = 1.f;
   int coarse_direct_mode = 0;
   // recorded FGMRES iterations (preconditioner + operator + Gram-Schmidt) of the

@@ -5,7 +5,7 @@
 
 // Computes D_L^-1 column by column (multi-RHS solves, the coarsest deflation defl in the
 // V-cycles if given) into H->coarse_dinv.
-void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl);
+void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl, double rtol);
 // Rounds the FP32 inverse to complex FP16 (one power-of-two scale) into H->coarse_dinv16.
 void build_coarse_direct16(dmlmc_hier* H);
 // Rounds the FP32 inverse to 8-bit floats (sign, 4 exponent bits with bias 7, 3 mantissa

@@ -423,7 +423,7 @@ constexpr int TILES8 = 4;
 
 }  // namespace
 
-void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl) {
+void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl, double rtol) {
   dmlmc_ctx* ctx = H->ctx;
   const int L = (int)H->lv.size();
   const Level& C = H->lv[L - 1];
@@ -445,7 +445,7 @@ void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl) {
   if (defl) H->coarse_defl = defl;
   H->coarse_direct_mode = 0;  // the columns are computed with the iterative coarsest solve
   H->coarse_dinv.alloc(sizeof(c64) * (size_t)n * n);
-  constexpr int NB = 512;
+  constexpr int NB = 1024;
   c128* E = (c128*)hier_buf(H, "cd_E", L, sizeof(c128) * (size_t)NB * n);
   c128* X = (c128*)hier_buf(H, "cd_X", L, sizeof(c128) * (size_t)NB * n);
   for (int64_t c0 = 0; c0 < n; c0 += NB) {
@@ -453,7 +453,7 @@ void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl) {
     hipLaunchKernelGGL(unit_block_kernel, dim3((unsigned)ceil_div(n * nb, 256)), dim3(256), 0, ctx->stream, E, n, c0,
                        nb);
     LAUNCH_CHECK();
-    SolveResult r = solve_level(H, L, E, X, nb, DMLMC_MIXED, 1e-10, 5000);
+    SolveResult r = solve_level(H, L, E, X, nb, DMLMC_MIXED, rtol, 5000);
     if (!r.converged) throw DmlmcError(DMLMC_ENOCONV, "a column solve of the coarsest inverse did not converge");
     hipLaunchKernelGGL(store_columns_kernel, dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(nb, 32)), dim3(256), 0,
                        ctx->stream, X, n, c0, nb, H->coarse_dinv.as<c64>());
@@ -464,6 +464,7 @@ void build_coarse_direct(dmlmc_hier* H, const dmlmc_defl* defl) {
   H->coarse_dinv8.release();
   H->coarse_dinv8_rows.release();
   H->coarse_dinv_n = n;
+  H->coarse_dinv_rtol = rtol;
 }
 
 void build_coarse_direct16(dmlmc_hier* H) {

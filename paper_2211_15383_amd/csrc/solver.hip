@@ -305,6 +305,7 @@ int64_t work_ld(const dmlmc_hier* H, int l) {
 template <typename R>
 void smooth(dmlmc_hier* H, int l, Cx<R>* x, const Cx<R>* b, int nrhs, int sweeps, int64_t ld) {
   const Level& L = H->lv[l - 1];
+  KTimerGroup group(H->ctx, L.fine ? "sap" : "coarse_gs");  // the colour sweeps run back to back
   for (int s = 0; s < sweeps; ++s) {
     for (int color = 0; color < 2; ++color) {
       if (L.fine)

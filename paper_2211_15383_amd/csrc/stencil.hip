@@ -487,15 +487,6 @@ __device__ __forceinline__ void store_quad(c64* __restrict__ p, f32x4 re, f32x4 
   q[1] = w;
 }
 
-// Non-temporal form for results that the same launch does not read again.
-// (two 16-byte stores, so that the four lanes of a 128-byte line write it whole)
-__device__ __forceinline__ void store_quad_nt(c64* __restrict__ p, f32x4 re, f32x4 im) {
-  f32x4* q = reinterpret_cast<f32x4*>(p);
-  const f32x4 u = {re[0], im[0], re[1], im[1]}, w = {re[2], im[2], re[3], im[3]};
-  __builtin_nontemporal_store(u, q);
-  __builtin_nontemporal_store(w, q + 1);
-}
-
 // D += A X for one 16 x 16 block (a: lane's A row quarter, x: lane's B quarter).
 __device__ __forceinline__ void block_mfma(f32x4& dre, f32x4& dim, const Quad& a, const Quad& x) {
 #pragma unroll
@@ -661,17 +652,62 @@ __device__ __forceinline__ c64 half2_to_c64(uint32_t w) {
   return cmk((float)re, (float)im);
 }
 
-// SPLIT (H16 only): wavefronts per site; with 2, the two wavefronts of a site (same
-// workgroup) take every other 16-RHS tile, each reading the site's blocks.
+// One 16-RHS tile of the FP16-block sweep at one site: xa = the four neighbour quads and
+// qa = the b quad of RHS row `row` (lane quarter kq); writes x of the site when va.
+// Hop products on the FP16 matrix cores: the neighbour quads of the RHS are scaled by a
+// power of two that brings their largest component to [2^14, 2^15) (the same scale for
+// the four lanes of the RHS), rounded to complex FP16 and multiplied by the stored
+// complex-FP16 blocks with FP32 accumulation, then scaled back.  One
+// v_mfma_f32_16x16x32_f16 contracts a whole block row: A = the block words as read (re,
+// im interleaved), B = (re, -im) for the real part and (im, re) for the imaginary part
+// of the product.  The inverse self block is widened to FP32 and applied to the FP32
+// residual.
+__device__ __forceinline__ void gs16_tile(const uint4 (&a)[4], const uint4& ai, const Quad (&xa)[4], Quad qa, bool va,
+                                          c64* __restrict__ xo) {
+  float mx = 0.f;
+#pragma unroll
+  for (int dir = 0; dir < 4; ++dir)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) mx = fmaxf(mx, fmaxf(fabsf(xa[dir].v[q].x), fabsf(xa[dir].v[q].y)));
+  mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+  mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+  const int ex = mx > 0.f ? __builtin_amdgcn_frexp_expf(mx) : 0;  // mx = f 2^ex, f in [0.5, 1)
+  const float sc = ldexpf(1.f, 15 - ex), unsc = ldexpf(1.f, ex - 15);
+  f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
+#pragma unroll
+  for (int dir = 0; dir < 4; ++dir) {
+    u32x4 w = {0u, 0u, 0u, 0u};
+    if (va) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = pack_half2(sc * xa[dir].v[q].x, sc * xa[dir].v[q].y);
+    }
+    const half8 b_re = as_half8(w ^ 0x80000000u), b_im = as_half8((w >> 16) | (w << 16));
+    const half8 m8 = as_half8(u32x4{a[dir].x, a[dir].y, a[dir].z, a[dir].w});
+    are = __builtin_amdgcn_mfma_f32_16x16x32_f16(m8, b_re, are, 0, 0, 0);
+    aim = __builtin_amdgcn_mfma_f32_16x16x32_f16(m8, b_im, aim, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) qa.v[v] = cmk(qa.v[v].x - unsc * are[v], qa.v[v].y - unsc * aim[v]);
+  f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere;
+  const uint32_t wi[4] = {ai.x, ai.y, ai.z, ai.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cmfma(ere, eim, half2_to_c64(wi[q]), va ? qa.v[q] : cmk(0.f, 0.f));
+  if (va) store_quad(xo, ere, eim, 1.f);
+}
+
+// SPLIT (FP16 blocks only): 1 = one wavefront per site, its 16-RHS tiles in sequence;
+// 2 = two wavefronts per site (same workgroup), each taking every other tile and reading
+// the site's blocks; 3 = one wavefront per site, the loads of two tiles in flight together.
 template <bool H16, int SPLIT>
 __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __restrict__ Av,
                                                                const void* __restrict__ Ainvv, c64* __restrict__ x,
                                                                const c64* __restrict__ b, int Lx, int Lt, int nrhs,
                                                                int color, int64_t ld) {
-  static_assert(SPLIT == 1 || (H16 && SPLIT == 2), "two wavefronts per site only with the FP16 blocks");
+  static_assert(SPLIT == 1 || (H16 && (SPLIT == 2 || SPLIT == 3)), "split forms only with the FP16 blocks");
+  constexpr int WPS = SPLIT == 2 ? 2 : 1;  // wavefronts per site
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t wv = xcd_block() * 4 + w;
-  const int64_t k = wv / SPLIT;
+  const int64_t k = wv / WPS;
   const int64_t half = Lx / 2;
   const int64_t t = k / half;
   if (t >= Lt) return;  // wave-uniform
@@ -692,51 +728,35 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
     }
     const u32x4 vi = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(Ainv + s * 256 + row * 16 + 4 * kq));
     const uint4 ai = make_uint4(vi.x, vi.y, vi.z, vi.w);
-    for (int r0 = 16 * (int)(wv % SPLIT); r0 < nrhs; r0 += 16 * SPLIT) {
-      const int ra = r0 + row;
-      const bool va = ra < nrhs;
-      const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq;
-      Quad xa[4];
+    if constexpr (SPLIT == 3) {
+      for (int r0 = 0; r0 < nrhs; r0 += 32) {
+        const int ra = r0 + row, rb = r0 + 16 + row;
+        const bool va = ra < nrhs, vb = rb < nrhs;
+        const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq, ob = (int64_t)min(rb, nrhs - 1) * ld + 4 * kq;
+        Quad xa[4], xb[4];
 #pragma unroll
-      for (int dir = 0; dir < 4; ++dir) xa[dir] = load_quad(x + oa + sites[dir] * 16);
-      Quad qa = load_quad(b + oa - 4 * kq + own);
-      __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
-      // hop products on the FP16 matrix cores: the neighbour quads of RHS `row` are scaled
-      // by a power of two that brings their largest component to [2^14, 2^15) (the same
-      // scale for the four lanes of the RHS), rounded to complex FP16 and multiplied by
-      // the stored complex-FP16 blocks with FP32 accumulation, then scaled back.  One
-      // v_mfma_f32_16x16x32_f16 contracts a whole block row: A = the block words as read
-      // (re, im interleaved), B = (re, -im) for the real part and (im, re) for the
-      // imaginary part of the product.
-      float mx = 0.f;
-#pragma unroll
-      for (int dir = 0; dir < 4; ++dir)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) mx = fmaxf(mx, fmaxf(fabsf(xa[dir].v[q].x), fabsf(xa[dir].v[q].y)));
-      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-      const int ex = mx > 0.f ? __builtin_amdgcn_frexp_expf(mx) : 0;  // mx = f 2^ex, f in [0.5, 1)
-      const float sc = ldexpf(1.f, 15 - ex), unsc = ldexpf(1.f, ex - 15);
-      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
-#pragma unroll
-      for (int dir = 0; dir < 4; ++dir) {
-        u32x4 w = {0u, 0u, 0u, 0u};
-        if (va) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) w[q] = pack_half2(sc * xa[dir].v[q].x, sc * xa[dir].v[q].y);
+        for (int dir = 0; dir < 4; ++dir) {
+          xa[dir] = load_quad(x + oa + sites[dir] * 16);
+          xb[dir] = load_quad(x + ob + sites[dir] * 16);
         }
-        const half8 b_re = as_half8(w ^ 0x80000000u), b_im = as_half8((w >> 16) | (w << 16));
-        const half8 m8 = as_half8(u32x4{a[dir].x, a[dir].y, a[dir].z, a[dir].w});
-        are = __builtin_amdgcn_mfma_f32_16x16x32_f16(m8, b_re, are, 0, 0, 0);
-        aim = __builtin_amdgcn_mfma_f32_16x16x32_f16(m8, b_im, aim, 0, 0, 0);
+        const Quad qa = load_quad(b + oa - 4 * kq + own);
+        const Quad qb = load_quad(b + ob - 4 * kq + own);
+        __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
+        gs16_tile(a, ai, xa, qa, va, x + (int64_t)ra * ld + own);
+        gs16_tile(a, ai, xb, qb, vb, x + (int64_t)rb * ld + own);
       }
+    } else {
+      for (int r0 = 16 * (int)(wv % WPS); r0 < nrhs; r0 += 16 * WPS) {
+        const int ra = r0 + row;
+        const bool va = ra < nrhs;
+        const int64_t oa = (int64_t)min(ra, nrhs - 1) * ld + 4 * kq;
+        Quad xa[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) qa.v[v] = cmk(qa.v[v].x - unsc * are[v], qa.v[v].y - unsc * aim[v]);
-      f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere;
-      const uint32_t wi[4] = {ai.x, ai.y, ai.z, ai.w};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) cmfma(ere, eim, half2_to_c64(wi[q]), va ? qa.v[q] : cmk(0.f, 0.f));
-      if (va) store_quad(x + (int64_t)ra * ld + own, ere, eim, 1.f);
+        for (int dir = 0; dir < 4; ++dir) xa[dir] = load_quad(x + oa + sites[dir] * 16);
+        const Quad qa = load_quad(b + oa - 4 * kq + own);
+        __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
+        gs16_tile(a, ai, xa, qa, va, x + (int64_t)ra * ld + own);
+      }
     }
   } else {
     const c64* A = static_cast<const c64*>(Av);
@@ -923,8 +943,8 @@ __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restr
         bre += part[w + q][2][lane];
         bim += part[w + q][3][lane];
       }
-      if (va) store_quad_nt(yc + (int64_t)ra * ldc + cs * 16 + 4 * kq, are, aim);
-      if (vb) store_quad_nt(yc + (int64_t)rb * ldc + cs * 16 + 4 * kq, bre, bim);
+      if (va) store_quad(yc + (int64_t)ra * ldc + cs * 16 + 4 * kq, are, aim, 1.f);
+      if (vb) store_quad(yc + (int64_t)rb * ldc + cs * 16 + 4 * kq, bre, bim, 1.f);
     }
     __syncthreads();
   }
@@ -994,7 +1014,8 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
     REQUIRE(sub == nullptr, "the complex-FP32 matrix-core stencil has no residual form");
     REQUIRE(ldx % 2 == 0 && ldy % 2 == 0 && ((uintptr_t)x | (uintptr_t)y) % 16 == 0,
             "matrix-core coarse stencil needs 16-byte aligned RHS rows");
-    const int split = L.kv[KV_COARSE_SPLIT] == 2 ? 2 : 1;
+    // built-in rule: two wavefronts per site on small lattices (1024 sites: 8.9 -> 7.8 us)
+    const int split = L.kv[KV_COARSE_SPLIT] > 0 ? L.kv[KV_COARSE_SPLIT] : (V < 4096 ? 2 : 1);
     dim3 grid((unsigned)ceil_div(V * split, 4));
     if (split == 2) {
       if (gamma5_left)
@@ -1146,10 +1167,18 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
     REQUIRE(((uintptr_t)x | (uintptr_t)b) % 16 == 0 && ld % 2 == 0,
             "matrix-core Gauss-Seidel needs 16-byte aligned vectors");
     const bool h16 = half && L.Ahop16.p && L.Ainv16.p;
+    // built-in rule: two tiles' loads in flight per wavefront where the launch has enough
+    // wavefronts to fill the chip without them (measured at 1024^2: level 2, 32768 sites
+    // per colour, 134 -> 127 us; level 3, 2048 sites, no gain)
+    // (and two wavefronts per site on the smallest launches: 512 sites, 5.8 -> 4.4 us)
+    const int gs_form = L.kv[KV_GS_SPLIT] > 0 ? L.kv[KV_GS_SPLIT] : (nsites >= 16384 ? 3 : (nsites < 1024 ? 2 : 1));
     KTimer kt(ctx, "coarse_gs",
               (double)nrhs * (V / 2) * d * 3 * sizeof(Cx<R>) + (double)(V / 2) * 5 * d * d * (h16 ? 4 : sizeof(Cx<R>)));
-    if (h16 && L.kv[KV_GS_SPLIT] == 2)
+    if (h16 && gs_form == 2)
       hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true, 2>), dim3((unsigned)ceil_div(nsites * 2, 4)), dim3(256), 0,
+                         ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, ld);
+    else if (h16 && gs_form == 3)
+      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true, 3>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
                          ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, ld);
     else if (h16)
       hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true, 1>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
@@ -1188,7 +1217,9 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
     const AggMap g = agg_map(L);
     const int wpa = g.E / 16 >= 4 ? 4 : 1;  // wavefronts per aggregate
     const dim3 grid((unsigned)ceil_div(Vc, 4 / wpa));
-    const int ut = L.kv[KV_RESTRICT_UT] > 0 ? L.kv[KV_RESTRICT_UT] : (g.E / 16 / wpa <= 2 ? 2 : 4);
+    // built-in rule (measured at 1024^2): one tile per batch of loads when an aggregate's
+    // tiles are dealt to four wavefronts (level 2: 96 -> 78 us), else two
+    const int ut = L.kv[KV_RESTRICT_UT] > 0 ? L.kv[KV_RESTRICT_UT] : (wpa == 4 ? 1 : 2);
     if (ut == 1)
       hipLaunchKernelGGL(restrict16_mfma_kernel<1>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)xf,
                          (c64*)yc, g, Vc, nrhs, wpa, ldf, ldc);
