@@ -546,6 +546,7 @@ def main():
 
     methods = None
     if args.methods:
+        ctx.verbose(1)  # the eigensolves of large deflations print one line per iteration
         hk = tuple(int(v) for v in args.methods_hutch_k.split(",") if v.strip())
         methods = method_comparison(torch, dmlmc, ctx, args.methods, args.methods_eps, args.methods_k, hk,
                                     diff=not args.methods_no_diff)

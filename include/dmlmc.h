@@ -444,6 +444,12 @@ typedef struct {
 dmlmc_status dmlmc_set_solver_params(dmlmc_hier *h, const dmlmc_solver_params *p);
 dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p);
 
+/* ---------------------------------------------------------------- progress lines
+ * level > 0: long phases of this context (each outer iteration of the eigensolvers, the
+ * device Rayleigh-Ritz factorisations) print one progress line each to stderr; 0 (the
+ * default): silent. */
+dmlmc_status dmlmc_set_verbose(dmlmc_ctx *ctx, int level);
+
 /* ---------------------------------------------------------------- kernel timing
  * When enabled, the library brackets every launch of the named kernel classes with HIP
  * events on the context stream and accumulates their durations.  Classes:
@@ -455,7 +461,9 @@ dmlmc_status dmlmc_get_solver_params(const dmlmc_hier *h, dmlmc_solver_params *p
  * a class: algorithmic bytes, except flops for "defl_gemm" and "coarse_direct".
  * dmlmc_timing_select restricts the bracketing to a comma-separated list of classes
  * (NULL or "" = every class), so that a timed run carries events only around the kernels
- * it measures.  Unknown names are accepted and simply never match. */
+ * it measures.  Unknown names are accepted and simply never match.  The colour sweeps of
+ * one smoother call ("sap", "coarse_gs") run back to back and are bracketed by one event
+ * pair; each of them counts as one launch of the class, with its own bytes. */
 dmlmc_status dmlmc_timing_enable(dmlmc_ctx *ctx, int enable);
 dmlmc_status dmlmc_timing_select(dmlmc_ctx *ctx, const char *classes);
 dmlmc_status dmlmc_timing_reset(dmlmc_ctx *ctx);

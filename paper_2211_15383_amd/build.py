@@ -22,7 +22,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdmlmc.so")
 ARCH = "gfx950"
 
-SOURCES = ["stencil.hip", "blas.hip", "gram.hip", "solver.hip", "setup.hip", "defl.hip", "tsgemm.hip", "dense.hip", "mlmc.hip",
+SOURCES = ["stencil.hip", "blas.hip", "gram.hip", "solver.hip", "setup.hip", "defl.hip", "tsgemm.hip", "jacobi.hip", "dense.hip", "mlmc.hip",
            "noalloc.hip", "tune.hip", "capi.hip", "eigh_host.cpp"]
 
 

@@ -778,6 +778,12 @@ dmlmc_status dmlmc_work_stride(const dmlmc_hier* h, int level, int64_t* ld) {
   return DMLMC_OK;
 }
 
+dmlmc_status dmlmc_set_verbose(dmlmc_ctx* ctx, int level) {
+  if (!ctx || level < 0) return DMLMC_EINVAL;
+  ctx->verbose = level;
+  return DMLMC_OK;
+}
+
 dmlmc_status dmlmc_timing_enable(dmlmc_ctx* ctx, int enable) {
   if (!ctx) return DMLMC_EINVAL;
   return guarded(ctx, [&]() {

@@ -141,6 +141,7 @@ struct dmlmc_ctx {
   bool own_stream = false;
   std::string err;
   bool timing = false;
+  int verbose = 0;  // > 0: long phases (eigensolver iterations) print progress lines to stderr
   std::set<std::string> timing_only;  // empty: every class
   std::map<std::string, TimerClass> timers;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;

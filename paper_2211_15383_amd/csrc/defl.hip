@@ -9,11 +9,13 @@
 //     and then with Q on its k leading vectors; all FP64 on the device except the small
 //     dense eigenproblems.
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 
 #include "defl.h"
 #include "tsgemm.h"
 #include "eigh_host.h"
+#include "jacobi.h"
 #include "setup.h"
 #include "solver.h"
 
@@ -292,9 +294,59 @@ void rotate(dmlmc_hier* H, const c128* Y, int nsY, const std::vector<std::comple
   HIPCHK(hipStreamSynchronize(ctx->stream));
 }
 
-// Orthonormalise the ns columns of Y by Cholesky QR, twice.  Returns false if a
-// Cholesky factorisation fails.
+// From this order on, the Rayleigh-Ritz and orthonormalisation matrices are factored on
+// the device (parallel Jacobi, jacobi.hip) instead of on the host, whose O(m^3) dense
+// solvers take minutes at the orders of a fine-level deflation with k in the thousands.
+constexpr int DEVICE_RR_MIN = 512;
+
+// Eigenpairs of the Hermitian Gram-type matrix G (device, column-major m x m): w ascending
+// (host), S the eigenvectors (device, column-major, the rotate layout).
+void eigh_device(dmlmc_hier* H, const c128* G, int m, c128* S, std::vector<double>& w) {
+  const JacobiResult jr = jacobi_eigh(H->ctx, G, m, S, w, hier_devbuf(H, "eg_jac", 0), 1e-12, 40);
+  if (!jr.converged) throw DmlmcError(DMLMC_ENUMERIC, "device Jacobi eigensolver did not converge");
+  if (H->ctx->verbose)
+    std::fprintf(stderr, "[dmlmc] device Rayleigh-Ritz of order %d: %d Jacobi sweeps\n", m, jr.sweeps);
+}
+
+// Rayleigh-Ritz step on the device: S (device) and w (host) from M = <A_i, B_r> (na = nb = m)
+void rr_device(dmlmc_hier* H, const c128* A, const c128* B, int m, int64_t n, c128* S, std::vector<double>& w) {
+  c128* G = (c128*)hier_buf(H, "eg_Gd", 0, sizeof(c128) * (size_t)m * m);
+  ts_gram(H->ctx, A, m, B, m, n, G, hier_devbuf(H, "eg_part", 0));
+  eigh_device(H, G, m, S, w);
+}
+
+// S(:, c) *= s[c] (device S, column-major m x m; s on the device)
+__global__ void scale_columns_kernel(c128* __restrict__ S, int m, const double* __restrict__ sc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * m) return;
+  const double f = sc[t / m];
+  S[t] = cmk(S[t].x * f, S[t].y * f);
+}
+
+// Orthonormalise the ns columns of Y, twice: by Cholesky QR (host) below DEVICE_RR_MIN,
+// else by the eigendecomposition of the Gram matrix on the device, Y <- Y U diag(g)^-1/2.
+// Returns false if the Gram matrix is not positive definite.
 bool cholqr2(dmlmc_hier* H, c128*& Y, c128*& T, int ns, int64_t n) {
+  if (ns >= DEVICE_RR_MIN) {
+    dmlmc_ctx* ctx = H->ctx;
+    c128* S = (c128*)hier_buf(H, "eg_Sd", 0, sizeof(c128) * (size_t)ns * ns);
+    double* sc = (double*)hier_buf(H, "eg_sc", 0, sizeof(double) * ns);
+    std::vector<double> g;
+    for (int pass = 0; pass < 2; ++pass) {
+      rr_device(H, Y, Y, ns, n, S, g);
+      if (!(g[0] > 1e-14 * g[ns - 1])) return false;
+      std::vector<double> f(ns);
+      for (int c = 0; c < ns; ++c) f[c] = 1.0 / std::sqrt(g[c]);
+      HIPCHK(hipMemcpyAsync(sc, f.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
+      hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)ceil_div((int64_t)ns * ns, 256)), dim3(256), 0,
+                         ctx->stream, S, ns, sc);
+      LAUNCH_CHECK();
+      ts_rotate(ctx, Y, ns, S, ns, n, T);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      std::swap(Y, T);
+    }
+    return true;
+  }
   for (int pass = 0; pass < 2; ++pass) {
     std::vector<std::complex<double>> G = gram(H, Y, ns, Y, ns, n);  // G[i][r] = <Y_i, Y_r>
     // G = R^H R with R upper; cholesky_lower gives G = L L^H, so R = L^H and Y R^-1 = Y L^-H
@@ -353,19 +405,32 @@ EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout) 
   for (; it < maxit; ++it) {
     // Rayleigh-Ritz with Q^2 on the whole subspace: Y ordered by the Ritz values mu of Q^2
     applyQ(ctx, L, Y, Z, ns);
-    std::vector<std::complex<double>> H2 = gram(H, Z, ns, Z, ns, n);
-    if (eigh_tridiag(ns, H2, mu, S) < 0) throw DmlmcError(DMLMC_ENUMERIC, "Rayleigh-Ritz eigensolve failed");
-    rotate(H, Y, ns, S, ns, T, n);
+    if (ns >= DEVICE_RR_MIN) {
+      c128* Sd = (c128*)hier_buf(H, "eg_Sd", 0, sizeof(c128) * (size_t)ns * ns);
+      rr_device(H, Z, Z, ns, n, Sd, mu);
+      ts_rotate(ctx, Y, ns, Sd, ns, n, T);
+    } else {
+      std::vector<std::complex<double>> H2 = gram(H, Z, ns, Z, ns, n);
+      if (eigh_tridiag(ns, H2, mu, S) < 0) throw DmlmcError(DMLMC_ENUMERIC, "Rayleigh-Ritz eigensolve failed");
+      rotate(H, Y, ns, S, ns, T, n);
+    }
     std::swap(Y, T);
     // Rayleigh-Ritz with Q on the k leading vectors (their span converges to the invariant
     // subspace of the k smallest |lambda|, which Q maps into itself; an RR with Q on the
     // whole subspace would give spurious Ritz values near 0 from pairs +lambda, -lambda'
     // with similar |lambda| at the subspace boundary)
     applyQ(ctx, L, Y, Z, k);
-    std::vector<std::complex<double>> H1 = gram(H, Y, k, Z, k, n);
-    if (eigh_tridiag(k, H1, th1, S1) < 0) throw DmlmcError(DMLMC_ENUMERIC, "Rayleigh-Ritz eigensolve failed");
-    rotate(H, Y, k, S1, k, Q1, n);   // Ritz vectors of Q -> Q1[0..k)
-    rotate(H, Z, k, S1, k, Y0, n);   // Q times them -> Y0[0..k)
+    if (k >= DEVICE_RR_MIN) {
+      c128* Sd = (c128*)hier_buf(H, "eg_Sd", 0, sizeof(c128) * (size_t)ns * ns);
+      rr_device(H, Y, Z, k, n, Sd, th1);
+      ts_rotate(ctx, Y, k, Sd, k, n, Q1);  // Ritz vectors of Q -> Q1[0..k)
+      ts_rotate(ctx, Z, k, Sd, k, n, Y0);  // Q times them -> Y0[0..k)
+    } else {
+      std::vector<std::complex<double>> H1 = gram(H, Y, k, Z, k, n);
+      if (eigh_tridiag(k, H1, th1, S1) < 0) throw DmlmcError(DMLMC_ENUMERIC, "Rayleigh-Ritz eigensolve failed");
+      rotate(H, Y, k, S1, k, Q1, n);   // Ritz vectors of Q -> Q1[0..k)
+      rotate(H, Z, k, S1, k, Y0, n);   // Q times them -> Y0[0..k)
+    }
     double* th = (double*)hier_buf(H, "eg_th", 0, sizeof(double) * k);
     HIPCHK(hipMemcpyAsync(th, th1.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(ritz_res_kernel, dim3((unsigned)ceil_div(n * k, 256)), dim3(256), 0, ctx->stream, Y0, Q1, th, n,
@@ -379,6 +444,9 @@ EigResult eig_coarsest(dmlmc_hier* H, int level, int k, double tol, c128* Xout) 
     double worst = 0.0;
     for (int i = 0; i < k; ++i) worst = std::max(worst, std::sqrt(rn[i]));
     res.max_residual = worst / qnorm;
+    if (ctx->verbose)
+      std::fprintf(stderr, "[dmlmc] eigensolver level %d, k %d, subspace %d: iteration %d, max residual %.3e (tol %.1e)\n",
+                   level, k, ns, it, res.max_residual, tol);
     if (worst <= tol * qnorm) break;
     if (it + 1 == maxit) break;
     // filter interval: damp [a, bq] with a = the largest Ritz value of Q^2 in the subspace

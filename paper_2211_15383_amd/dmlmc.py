@@ -36,7 +36,7 @@ EXPORTED = [
     "dmlmc_get_solver_params", "dmlmc_timing_enable", "dmlmc_timing_select", "dmlmc_tune_rhs_block",
     "dmlmc_coarsest_direct", "dmlmc_deflate_project_noalloc",
     "dmlmc_timing_reset", "dmlmc_timing_get", "dmlmc_tune_kernels", "dmlmc_set_kernel_variant",
-    "dmlmc_get_kernel_variant",
+    "dmlmc_get_kernel_variant", "dmlmc_set_verbose",
 ]
 
 
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dmlmc_timing_get": (i32, [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
         "dmlmc_tune_kernels": (i32, [vp, vp, i32, i32, C.c_char_p, C.POINTER(i32), C.POINTER(dbl), C.POINTER(dbl)]),
         "dmlmc_set_kernel_variant": (i32, [vp, i32, i32, i32]),
+        "dmlmc_set_verbose": (i32, [vp, i32]),
         "dmlmc_get_kernel_variant": (i32, [vp, i32, i32, C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
@@ -198,6 +199,10 @@ class Context:
             pass
 
     # ---------------------------------------------------------------- timing
+    def verbose(self, level: int = 1):
+        """Progress lines of long phases (eigensolver iterations) on stderr (see dmlmc_set_verbose)."""
+        self.check(lib().dmlmc_set_verbose(self.h, level))
+
     def timing(self, enable: bool):
         self.check(lib().dmlmc_timing_enable(self.h, 1 if enable else 0))
 

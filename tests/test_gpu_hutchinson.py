@@ -96,3 +96,35 @@ def test_hutchinson_argument_checks(gpu):
         dm.hutchinson_trace(H, df, 1e-2, 1, 8, 8, fixed_counts=True, coarsest=df)
     with pytest.raises(dm.DmlmcError):
         dm.hutchinson_trace(H, df, 1e-2, 1, 0, 8, fixed_counts=True)
+
+
+def test_fine_level_eigensolver_device_rayleigh_ritz(gpu):
+    """The fine-level eigensolver with a subspace beyond the host Rayleigh-Ritz range
+    (k = 512 of n_1 = 2048 on a 32^2 lattice: subspace 768, so the Rayleigh-Ritz steps and
+    the orthonormalisations factor their matrices with the device Jacobi eigensolver)
+    finds the checker's k smallest |lambda| of Gamma5 D (dense eigh of the whole
+    operator), its deflation trace and eigenpairs to the eigensolver tolerance."""
+    from oracle import multigrid as omg
+    from paper_2211_15383_amd.inputs import link_angles
+
+    torch, dm, ctx = gpu
+    ctx.verbose(1)
+    theta = link_angles(32, 32, 0.3, 7)
+    m0, aggs, ntv = -0.05, ((4, 4),), (8,)
+    lv = omg.build_hierarchy(theta, m0, aggs, ntv, 3, 21)
+    H = dm.Hierarchy(ctx, theta, m0, aggs, ntv, n_inv=3, seed=21, import_tv=[l.V for l in lv[:-1]])
+    k = 512
+    fref = odfl.deflate(lv[0].D, lv[0].gamma5, k)
+    print(f"[device RR] 32^2 fine-level deflation, k {k}", flush=True)
+    dg = dm.Deflation(H, 1, k, eig_rtol=1e-10)
+    X, lam = dg.export()[0], np.asarray(dg.export()[1])
+    assert dg.info()["max_residual"] <= 1e-10
+    assert np.allclose(np.sort(np.abs(lam)), np.sort(np.abs(fref.lam)), rtol=1e-9, atol=0)
+    assert abs(dg.tr_defl - fref.tr_defl) < 1e-8 * abs(fref.tr_defl)
+    # the spans agree: the checker's eigenvectors lie in the device deflation space
+    Xd = np.asarray(X).T if np.asarray(X).shape[0] == k else np.asarray(X)
+    proj = Xd @ (Xd.conj().T @ fref.X)
+    assert np.linalg.norm(proj - fref.X) / np.linalg.norm(fref.X) < 1e-6
+    ctx.verbose(0)
+    dg.close()
+    H.close()
