@@ -315,33 +315,41 @@ void rr_device(dmlmc_hier* H, const c128* A, const c128* B, int m, int64_t n, c1
   eigh_device(H, G, m, S, w);
 }
 
-// S(:, c) *= s[c] (device S, column-major m x m; s on the device)
-__global__ void scale_columns_kernel(c128* __restrict__ S, int m, const double* __restrict__ sc) {
+// T[i][c] = conj(U(i, c)) sc[c] (U device, column-major m x m): the rows of U diag(sc) as
+// vectors, so that their Gram matrix is U diag(sc^2) U^H
+__global__ void scaled_rows_kernel(const c128* __restrict__ U, int m, const double* __restrict__ sc,
+                                   c128* __restrict__ T) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)m * m) return;
-  const double f = sc[t / m];
-  S[t] = cmk(S[t].x * f, S[t].y * f);
+  const int c = (int)(t % m), i = (int)(t / m);
+  const c128 u = U[(int64_t)c * m + i];
+  T[t] = cmk(u.x * sc[c], -u.y * sc[c]);
 }
 
 // Orthonormalise the ns columns of Y, twice: by Cholesky QR (host) below DEVICE_RR_MIN,
-// else by the eigendecomposition of the Gram matrix on the device, Y <- Y U diag(g)^-1/2.
-// Returns false if the Gram matrix is not positive definite.
+// else on the device by the symmetric (Loewdin) form Y <- Y G^-1/2, G = Y^H Y = U diag(g)
+// U^H: the orthonormal basis closest to Y, so that a basis of nearly orthogonal Ritz
+// vectors stays nearly diagonal for the Rayleigh-Ritz step that follows.  Returns false
+// if the Gram matrix is not positive definite.
 bool cholqr2(dmlmc_hier* H, c128*& Y, c128*& T, int ns, int64_t n) {
   if (ns >= DEVICE_RR_MIN) {
     dmlmc_ctx* ctx = H->ctx;
     c128* S = (c128*)hier_buf(H, "eg_Sd", 0, sizeof(c128) * (size_t)ns * ns);
+    c128* Ur = (c128*)hier_buf(H, "eg_Ur", 0, sizeof(c128) * (size_t)ns * ns);
+    c128* Gi = (c128*)hier_buf(H, "eg_Gi", 0, sizeof(c128) * (size_t)ns * ns);
     double* sc = (double*)hier_buf(H, "eg_sc", 0, sizeof(double) * ns);
     std::vector<double> g;
     for (int pass = 0; pass < 2; ++pass) {
       rr_device(H, Y, Y, ns, n, S, g);
       if (!(g[0] > 1e-14 * g[ns - 1])) return false;
       std::vector<double> f(ns);
-      for (int c = 0; c < ns; ++c) f[c] = 1.0 / std::sqrt(g[c]);
+      for (int c = 0; c < ns; ++c) f[c] = std::pow(g[c], -0.25);
       HIPCHK(hipMemcpyAsync(sc, f.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
-      hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)ceil_div((int64_t)ns * ns, 256)), dim3(256), 0,
-                         ctx->stream, S, ns, sc);
+      hipLaunchKernelGGL(scaled_rows_kernel, dim3((unsigned)ceil_div((int64_t)ns * ns, 256)), dim3(256), 0,
+                         ctx->stream, S, ns, sc, Ur);
       LAUNCH_CHECK();
-      ts_rotate(ctx, Y, ns, S, ns, n, T);
+      ts_gram(ctx, Ur, ns, Ur, ns, ns, Gi, hier_devbuf(H, "eg_part", 0));  // G^-1/2, column-major
+      ts_rotate(ctx, Y, ns, Gi, ns, n, T);
       HIPCHK(hipStreamSynchronize(ctx->stream));
       std::swap(Y, T);
     }
