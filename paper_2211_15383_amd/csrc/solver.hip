@@ -64,6 +64,15 @@ __global__ void scale_store_kernel(const c128* __restrict__ w, const double* __r
 }
 
 // v[r] *= s[r] in place (FP64)
+// dst row i = src row idx[i] (rows of n entries, stride n)
+__global__ void gather_rows_kernel(const c128* __restrict__ src, c128* __restrict__ dst, const int* __restrict__ idx,
+                                   int64_t n) {
+  const int r = blockIdx.y;
+  const c128* s = src + (int64_t)idx[r] * n;
+  c128* d = dst + (int64_t)r * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
 __global__ void scale_inplace_kernel(c128* v, const double* __restrict__ s, int64_t n) {
   const int r = blockIdx.y;
   const double f = s[r];
@@ -489,45 +498,106 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
   }
   SolveResult out;
   const double inner_rel = (prec == DMLMC_MIXED) ? H->inner_rtol : 0.0;
+  // Converged right-hand sides leave the refinement: rows 0..na-1 of X and B (and of the
+  // cycle's vectors) hold the active ones, row i being the caller's RHS orig[i]; every
+  // RHS's arithmetic is independent of the others in the block, so this only saves the
+  // further cycles a converged RHS would otherwise run along with the rest.
+  int na = nrhs;
+  std::vector<int> orig(nrhs);
+  for (int q = 0; q < nrhs; ++q) orig[q] = q;
+  bool permuted = false;
+  c128* Bw = nullptr;  // working copy of B once rows move
   while (true) {
-    bool all = true;
+    std::vector<int> act, conv;
     double worst = 0.0;
-    for (int q = 0; q < nrhs; ++q) {
+    for (int q = 0; q < nrhs; ++q) {  // rows from na on keep the residuals they left with
       const double rel = bn[q] > 0.0 ? rn[q] / bn[q] : 0.0;
       worst = std::max(worst, rel);
-      if (rel > rtol) all = false;
+      if (q < na) (rel > rtol ? act : conv).push_back(q);
     }
     out.relres_max = worst;
-    if (all) {
+    if (act.empty()) {
       out.converged = true;
       break;
     }
     if (out.iters >= maxiter) break;
-    for (int q = 0; q < nrhs; ++q) target[q] = std::max(0.5 * rtol * bn[q], inner_rel * rn[q]);
+    if (!conv.empty()) {
+      // move the active rows to the front (stable), the converged ones after them
+      std::vector<int> idx(act);
+      idx.insert(idx.end(), conv.begin(), conv.end());
+      if (!Bw) {
+        Bw = (c128*)hier_buf(H, "sv_Bw", l, sizeof(c128) * (size_t)nrhs * n);
+        HIPCHK(hipMemcpyAsync(Bw, B, sizeof(c128) * (size_t)nrhs * n, hipMemcpyDeviceToDevice, ctx->stream));
+        B = Bw;
+      }
+      int* idev = (int*)hier_buf(H, "sv_idx", l, sizeof(int) * nrhs);
+      c128* tmp = (c128*)hier_buf(H, "sv_tmp", l, sizeof(c128) * (size_t)na * n);
+      HIPCHK(hipMemcpyAsync(idev, idx.data(), sizeof(int) * na, hipMemcpyHostToDevice, ctx->stream));
+      for (c128* M : {X, Bw}) {
+        hipLaunchKernelGGL(gather_rows_kernel, dim3(gridn(n), na), dim3(256), 0, ctx->stream, M, tmp, idev, n);
+        LAUNCH_CHECK();
+        HIPCHK(hipMemcpyAsync(M, tmp, sizeof(c128) * (size_t)na * n, hipMemcpyDeviceToDevice, ctx->stream));
+      }
+      auto permute = [&](auto& v) {
+        auto w = v;
+        for (int i = 0; i < na; ++i) w[i] = v[idx[i]];
+        v = w;
+      };
+      permute(bn);
+      permute(rn);
+      permute(rescale);
+      permute(orig);
+      na = (int)act.size();
+      permuted = true;
+      // the mixed cycle starts from the residual in its first basis vector: rebuild it for
+      // the moved rows
+      if (mixed) {
+        apply_residual_to32(ctx, L, X, B, U0, na, n, ldw);
+        launch_norms2<float>(ctx, U0, n, na, ldw, nrm);
+      } else {
+        apply_residual<double>(ctx, L, X, B, Rr, na);
+        launch_norms2<double>(ctx, Rr, n, na, n, nrm);
+      }
+    }
+    for (int q = 0; q < na; ++q) target[q] = std::max(0.5 * rtol * bn[q], inner_rel * rn[q]);
     int it;
     // each cycle adds its correction to X; then r = b - D x (one operator pass, FP64
     // arithmetic; stored in complex FP32 as the next cycle's first basis vector in the
     // mixed form) and ||r||^2 (FP64 sums)
     if (mixed)
-      it = fgmres_cycle<float>(H, l, nullptr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target,
+      it = fgmres_cycle<float>(H, l, nullptr, nrm, X, na, std::min(m, std::max(1, maxiter - out.iters)), target,
                                est, true);
     else
-      it = fgmres_cycle<double>(H, l, Rr, nrm, X, nrhs, std::min(m, std::max(1, maxiter - out.iters)), target, est);
+      it = fgmres_cycle<double>(H, l, Rr, nrm, X, na, std::min(m, std::max(1, maxiter - out.iters)), target, est);
     out.iters += it;
     out.ir_steps += 1;
     if (mixed) {
-      apply_residual_to32(ctx, L, X, B, U0, nrhs, n, ldw);
-      launch_norms2<float>(ctx, U0, n, nrhs, ldw, nrm);
+      apply_residual_to32(ctx, L, X, B, U0, na, n, ldw);
+      launch_norms2<float>(ctx, U0, n, na, ldw, nrm);
     } else {
-      apply_residual<double>(ctx, L, X, B, Rr, nrhs);
-      launch_norms2<double>(ctx, Rr, n, nrhs, n, nrm);
+      apply_residual<double>(ctx, L, X, B, Rr, na);
+      launch_norms2<double>(ctx, Rr, n, na, n, nrm);
     }
-    HIPCHK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * na, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (int q = 0; q < nrhs; ++q) {
+    for (int q = 0; q < na; ++q) {
       if (!std::isfinite(rn[q])) throw DmlmcError(DMLMC_ENUMERIC, "NaN/Inf in the FP64 residual");
       rn[q] = std::sqrt(rn[q]);
     }
+  }
+  if (permuted) {
+    // rows back to the caller's order: X row orig[i] = current row i
+    std::vector<int> inv(nrhs);
+    for (int i = 0; i < nrhs; ++i) inv[orig[i]] = i;
+    int* idev = (int*)hier_buf(H, "sv_idx", l, sizeof(int) * nrhs);
+    c128* tmp = (c128*)hier_buf(H, "sv_tmp", l, sizeof(c128) * (size_t)nrhs * n);
+    HIPCHK(hipMemcpyAsync(idev, inv.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(gridn(n), nrhs), dim3(256), 0, ctx->stream, X, tmp, idev, n);
+    LAUNCH_CHECK();
+    HIPCHK(hipMemcpyAsync(X, tmp, sizeof(c128) * (size_t)nrhs * n, hipMemcpyDeviceToDevice, ctx->stream));
+    std::vector<double> rs(nrhs);
+    for (int i = 0; i < nrhs; ++i) rs[orig[i]] = rescale[i];
+    rescale = rs;
   }
   if (any_rescale) {
     for (int q = 0; q < nrhs; ++q) rescale[q] = 1.0 / rescale[q];

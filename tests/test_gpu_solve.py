@@ -47,6 +47,36 @@ def test_solve_every_level(gpu, name, prec_name, rtol):
         assert rel_err(Xh, ref) < rtol * 1e4, (l, rel_err(Xh, ref))
 
 
+@pytest.mark.parametrize("prec_name,rtol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_converged_rhs_leave_the_refinement(gpu, prec_name, rtol):
+    """Right-hand sides that reach the tolerance early leave the refinement loop (the
+    others move to the front of the block): a zero RHS (converged before any cycle), one
+    that is D applied to a smooth vector (few cycles) and noise vectors (more cycles) in
+    one block each meet the tolerance, come back in the caller's order, and agree with
+    the same RHS solved alone."""
+    torch, dm, ctx = gpu
+    prec = dm.FP64 if prec_name == "fp64" else dm.MIXED
+    W, lv, H = _gpu_hier(gpu, "schwinger128")
+    D = lv[0].D
+    n = D.shape[0]
+    smooth = np.exp(2j * np.pi * np.arange(n) / n)
+    B = np.column_stack([onoise.z2_noise(5, 1, 0, n), np.zeros(n), D @ smooth, onoise.z2_noise(5, 1, 1, n),
+                         1e-3 * (D @ smooth) + onoise.z2_noise(5, 1, 2, n)]).astype(np.complex128)
+    X, st = H.solve(1, to_dev(torch, B), prec=prec, rtol=rtol, maxiter=3000)
+    Xh = to_host(X)
+    nb = np.linalg.norm(B, axis=0)
+    res = np.linalg.norm(B - D @ Xh, axis=0) / np.where(nb > 0, nb, 1.0)
+    assert st.converged and res.max() <= rtol * 1.0001, res
+    assert np.all(Xh[:, 1] == 0)
+    ref = spla.splu(D.tocsc()).solve(B)
+    for j in range(B.shape[1]):
+        if j == 1:
+            continue
+        Xj, _ = H.solve(1, to_dev(torch, B[:, j:j + 1]), prec=prec, rtol=rtol, maxiter=3000)
+        assert rel_err(to_host(Xj)[:, 0], ref[:, j]) < rtol * 1e4
+        assert rel_err(Xh[:, j], ref[:, j]) < rtol * 1e4, j
+
+
 @pytest.mark.parametrize("name,k", [("schwinger16", 16), ("rect24x16", 6), ("schwinger128", 32)])
 def test_eigensolver_against_dense(gpu, name, k):
     torch, dm, ctx = gpu
