@@ -327,7 +327,9 @@ dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_def
  *   DMLMC_KV_COARSE_SPLIT  coarse block stencil (16 dofs/site): wavefronts per site, 1 or 2
  *   DMLMC_KV_SAP_RB        SAP colour sweep, RHS per thread: 1, 2, 4, 8
  *   DMLMC_KV_GS_SPLIT      coarse Gauss-Seidel (FP16 blocks): wavefronts per site, 1 or 2;
- *                          3: one wavefront per site with two 16-RHS tiles' loads in flight
+ *                          3: one wavefront per site with two 16-RHS tiles' loads in flight;
+ *                          4: one wavefront per site, vectors read and written by whole
+ *                          128-byte lines staged through LDS
  *   DMLMC_KV_RESTRICT_UT   matrix-core restriction: tiles per batch of loads, 1, 2, 4
  *   DMLMC_KV_PROLONG_MT    matrix-core prolongation: tiles per wavefront, 1, 2, 4 (a value
  *                          that does not divide the level's tile count falls back to the rule)

@@ -184,7 +184,8 @@ enum KernelVariant {
   KV_WILSON_RB = 0,  // fine stencil: RHS per thread (1, 2, 4, 8)
   KV_COARSE_SPLIT,   // complex-FP32 coarse stencil, d = 16: wavefronts per site (1: both 16-RHS tiles, 2: one each)
   KV_SAP_RB,         // SAP colour sweep: RHS per thread (1, 2, 4, 8)
-  KV_GS_SPLIT,       // complex-FP16-block Gauss-Seidel, d = 16: 1, 2 wavefronts per site; 3: tile pairs in flight
+  KV_GS_SPLIT,       // complex-FP16-block Gauss-Seidel, d = 16: 1, 2 wavefronts per site; 3: tile pairs in
+                     // flight; 4: whole-line vector loads and stores staged in LDS
   KV_RESTRICT_UT,    // matrix-core restriction: 16-entry tiles whose loads a wavefront issues at once (1, 2, 4)
   KV_PROLONG_MT,     // matrix-core prolongation: 16-entry tiles per wavefront (1, 2, 4; dividing the tile count)
   KV_COUNT

@@ -501,12 +501,42 @@ __device__ __forceinline__ Quad select_quad(bool keep, const Quad& q) {
   return r;
 }
 
+// The 16 RHS rows r0 .. r0+15 (clamped to nrhs - 1) of the 16 complex entries at entry
+// offset `off` of v, read with whole-line loads: each of a lane's two 16-byte loads belongs
+// to a group of 8 lanes covering one 128-byte line (RHS l / 8 and 8 + l / 8, piece l % 8),
+// so each load instruction touches 8 lines instead of 16 half lines.  The two pieces go to
+// the wavefront's LDS rows (144 bytes apart, so that the read-back below is free of bank
+// conflicts); LDS operations of one wavefront complete in order.
+__device__ __forceinline__ void stage_rows(const c64* __restrict__ v, int64_t ld, int r0, int nrhs, int64_t off,
+                                           int lane, float4* __restrict__ rows) {
+  const int rr = lane >> 3, pc = lane & 7;
+  const int ra = min(r0 + rr, nrhs - 1), rb = min(r0 + 8 + rr, nrhs - 1);
+  const float4 A = *reinterpret_cast<const float4*>(v + (int64_t)ra * ld + off + 2 * pc);
+  const float4 B = *reinterpret_cast<const float4*>(v + (int64_t)rb * ld + off + 2 * pc);
+  rows[rr * 9 + pc] = A;
+  rows[(8 + rr) * 9 + pc] = B;
+}
+
+// the quad of lane (row, kq) from staged rows: entries 4 kq .. 4 kq + 3 of RHS row
+__device__ __forceinline__ Quad staged_quad(const float4* __restrict__ rows, int lane) {
+  const int row = lane & 15, kq = lane >> 4;
+  const float4 u = rows[row * 9 + 2 * kq], w = rows[row * 9 + 2 * kq + 1];
+  Quad q;
+  q.v[0] = cmk(u.x, u.y);
+  q.v[1] = cmk(u.z, u.w);
+  q.v[2] = cmk(w.x, w.y);
+  q.v[3] = cmk(w.z, w.w);
+  return q;
+}
+
 // y_s = sum_dir A[s][dir] x_{s+dir} (optionally Gamma5 y).  SPLIT = 1: one site per
 // wavefront, all RHS in pairs of 16-wide tiles; SPLIT = 2: two wavefronts per site (the
-// same workgroup), each taking every other 16-wide tile.  Every load of a pass is issued
-// before the first product (rows beyond nrhs load a valid row and are zeroed), so the
-// wavefront has all its memory requests in flight at once.  Each output tile is the same
-// sequence of products in both forms.
+// same workgroup), each taking every other 16-wide tile; SPLIT = 3: one site per
+// wavefront, one tile at a time, the blocks and vectors read and the result written by
+// whole 128-byte lines staged through LDS (11.5 KB per wavefront).  Every load of a pass
+// is issued before the first product (rows beyond nrhs load a valid row and are zeroed),
+// so the wavefront has all its memory requests in flight at once.  Each output tile is the
+// same sequence of products in every form.
 template <bool G5, int SPLIT>
 __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restrict__ A, const c64* __restrict__ in,
                                                             c64* __restrict__ out, int Lx, int Lt, int nrhs,
@@ -514,12 +544,48 @@ __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restric
   const int64_t V = (int64_t)Lx * Lt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t wv = xcd_block() * 4 + w;
-  const int64_t s = wv / SPLIT;
+  const int64_t s = wv / (SPLIT == 2 ? 2 : 1);  // SPLIT = 2: two wavefronts per site
   if (s >= V) return;  // wave-uniform: the MFMAs below always run with a full wavefront
   const int row = lane & 15, kq = lane >> 4;
   const Nbr nb = neighbours(s, Lx, Lt);
   const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
   const float sg = (G5 && kq >= 2) ? -1.f : 1.f;
+  if constexpr (SPLIT == 3) {
+    __shared__ float4 stage[4][5][16 * 9];
+    float4(*rows)[16 * 9] = stage[w];
+    // a block is 16 rows of 16 complex entries, like 16 RHS rows of a site
+    Quad a[5];
+#pragma unroll
+    for (int dir = 0; dir < 5; ++dir) stage_rows(A + (s * 5 + dir) * 256, 16, 0, 16, 0, lane, rows[dir]);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int dir = 0; dir < 5; ++dir) a[dir] = staged_quad(rows[dir], lane);
+    __builtin_amdgcn_wave_barrier();
+    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+      const int ra = r0 + row;
+      const bool va = ra < nrhs;
+#pragma unroll
+      for (int dir = 0; dir < 5; ++dir) stage_rows(in, ldx, r0, nrhs, sites[dir] * 16, lane, rows[dir]);
+      __builtin_amdgcn_wave_barrier();
+      Quad xa[5];
+#pragma unroll
+      for (int dir = 0; dir < 5; ++dir) xa[dir] = staged_quad(rows[dir], lane);
+      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
+#pragma unroll
+      for (int dir = 0; dir < 5; ++dir) block_mfma(are, aim, a[dir], select_quad(va, xa[dir]));
+      __builtin_amdgcn_wave_barrier();
+      float4* o = rows[0];
+      o[row * 9 + 2 * kq] = make_float4(sg * are[0], sg * aim[0], sg * are[1], sg * aim[1]);
+      o[row * 9 + 2 * kq + 1] = make_float4(sg * are[2], sg * aim[2], sg * are[3], sg * aim[3]);
+      __builtin_amdgcn_wave_barrier();
+      const int rr = lane >> 3, pc = lane & 7;
+      if (r0 + rr < nrhs) *reinterpret_cast<float4*>(out + (int64_t)(r0 + rr) * ldy + s * 16 + 2 * pc) = o[rr * 9 + pc];
+      if (r0 + 8 + rr < nrhs)
+        *reinterpret_cast<float4*>(out + (int64_t)(r0 + 8 + rr) * ldy + s * 16 + 2 * pc) = o[(8 + rr) * 9 + pc];
+      __builtin_amdgcn_wave_barrier();
+    }
+    return;
+  }
   if constexpr (SPLIT == 2) {
     for (int r0 = 16 * (int)(wv % 2); r0 < nrhs; r0 += 32) {
       const int ra = r0 + row;
@@ -653,7 +719,7 @@ __device__ __forceinline__ c64 half2_to_c64(uint32_t w) {
 }
 
 // One 16-RHS tile of the FP16-block sweep at one site: xa = the four neighbour quads and
-// qa = the b quad of RHS row `row` (lane quarter kq); writes x of the site when va.
+// qa = the b quad of RHS row `row` (lane quarter kq); returns the lane's quad of the new x.
 // Hop products on the FP16 matrix cores: the neighbour quads of the RHS are scaled by a
 // power of two that brings their largest component to [2^14, 2^15) (the same scale for
 // the four lanes of the RHS), rounded to complex FP16 and multiplied by the stored
@@ -663,7 +729,7 @@ __device__ __forceinline__ c64 half2_to_c64(uint32_t w) {
 // of the product.  The inverse self block is widened to FP32 and applied to the FP32
 // residual.
 __device__ __forceinline__ void gs16_tile(const uint4 (&a)[4], const uint4& ai, const Quad (&xa)[4], Quad qa, bool va,
-                                          c64* __restrict__ xo) {
+                                          f32x4& ere, f32x4& eim) {
   float mx = 0.f;
 #pragma unroll
   for (int dir = 0; dir < 4; ++dir)
@@ -688,22 +754,24 @@ __device__ __forceinline__ void gs16_tile(const uint4 (&a)[4], const uint4& ai, 
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) qa.v[v] = cmk(qa.v[v].x - unsc * are[v], qa.v[v].y - unsc * aim[v]);
-  f32x4 ere = {0.f, 0.f, 0.f, 0.f}, eim = ere;
+  ere = f32x4{0.f, 0.f, 0.f, 0.f};
+  eim = ere;
   const uint32_t wi[4] = {ai.x, ai.y, ai.z, ai.w};
 #pragma unroll
   for (int q = 0; q < 4; ++q) cmfma(ere, eim, half2_to_c64(wi[q]), va ? qa.v[q] : cmk(0.f, 0.f));
-  if (va) store_quad(xo, ere, eim, 1.f);
 }
 
 // SPLIT (FP16 blocks only): 1 = one wavefront per site, its 16-RHS tiles in sequence;
 // 2 = two wavefronts per site (same workgroup), each taking every other tile and reading
-// the site's blocks; 3 = one wavefront per site, the loads of two tiles in flight together.
+// the site's blocks; 3 = one wavefront per site, the loads of two tiles in flight together;
+// 4 = as 1 with the vectors read by whole-line loads staged through LDS (11.5 KB per
+// wavefront).
 template <bool H16, int SPLIT>
 __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __restrict__ Av,
                                                                const void* __restrict__ Ainvv, c64* __restrict__ x,
                                                                const c64* __restrict__ b, int Lx, int Lt, int nrhs,
                                                                int color, int64_t ld) {
-  static_assert(SPLIT == 1 || (H16 && (SPLIT == 2 || SPLIT == 3)), "split forms only with the FP16 blocks");
+  static_assert(SPLIT == 1 || (H16 && SPLIT >= 2 && SPLIT <= 4), "split forms only with the FP16 blocks");
   constexpr int WPS = SPLIT == 2 ? 2 : 1;  // wavefronts per site
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t wv = xcd_block() * 4 + w;
@@ -742,8 +810,43 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
         const Quad qa = load_quad(b + oa - 4 * kq + own);
         const Quad qb = load_quad(b + ob - 4 * kq + own);
         __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
-        gs16_tile(a, ai, xa, qa, va, x + (int64_t)ra * ld + own);
-        gs16_tile(a, ai, xb, qb, vb, x + (int64_t)rb * ld + own);
+        f32x4 ere, eim;
+        gs16_tile(a, ai, xa, qa, va, ere, eim);
+        if (va) store_quad(x + (int64_t)ra * ld + own, ere, eim, 1.f);
+        gs16_tile(a, ai, xb, qb, vb, ere, eim);
+        if (vb) store_quad(x + (int64_t)rb * ld + own, ere, eim, 1.f);
+      }
+    } else if constexpr (SPLIT == 4) {
+      __shared__ float4 stage[4][5][16 * 9];
+      float4(*rows)[16 * 9] = stage[w];
+      for (int r0 = 0; r0 < nrhs; r0 += 16) {
+        const int ra = r0 + row;
+        const bool va = ra < nrhs;
+#pragma unroll
+        for (int dir = 0; dir < 4; ++dir) stage_rows(x, ld, r0, nrhs, sites[dir] * 16, lane, rows[dir]);
+        stage_rows(b, ld, r0, nrhs, s * 16, lane, rows[4]);
+        __builtin_amdgcn_wave_barrier();
+        Quad xa[4];
+#pragma unroll
+        for (int dir = 0; dir < 4; ++dir) xa[dir] = staged_quad(rows[dir], lane);
+        const Quad qa = staged_quad(rows[4], lane);
+        f32x4 ere, eim;
+        gs16_tile(a, ai, xa, qa, va, ere, eim);
+        // the new x goes out the same way: the lane's quad into LDS row `row`, then whole-line
+        // 16-byte stores (rows staged by the b vector above are free again)
+        __builtin_amdgcn_wave_barrier();
+        float4* out = rows[4];
+        out[row * 9 + 2 * kq] = make_float4(ere[0], eim[0], ere[1], eim[1]);
+        out[row * 9 + 2 * kq + 1] = make_float4(ere[2], eim[2], ere[3], eim[3]);
+        __builtin_amdgcn_wave_barrier();
+        {
+          const int rr = lane >> 3, pc = lane & 7;
+          if (r0 + rr < nrhs)
+            *reinterpret_cast<float4*>(x + (int64_t)(r0 + rr) * ld + s * 16 + 2 * pc) = out[rr * 9 + pc];
+          if (r0 + 8 + rr < nrhs)
+            *reinterpret_cast<float4*>(x + (int64_t)(r0 + 8 + rr) * ld + s * 16 + 2 * pc) = out[(8 + rr) * 9 + pc];
+        }
+        __builtin_amdgcn_wave_barrier();  // the next tile's staging writes come after these reads
       }
     } else {
       for (int r0 = 16 * (int)(wv % WPS); r0 < nrhs; r0 += 16 * WPS) {
@@ -755,7 +858,9 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
         for (int dir = 0; dir < 4; ++dir) xa[dir] = load_quad(x + oa + sites[dir] * 16);
         const Quad qa = load_quad(b + oa - 4 * kq + own);
         __builtin_amdgcn_sched_barrier(0);  // keep every load above the first product
-        gs16_tile(a, ai, xa, qa, va, x + (int64_t)ra * ld + own);
+        f32x4 ere, eim;
+        gs16_tile(a, ai, xa, qa, va, ere, eim);
+        if (va) store_quad(x + (int64_t)ra * ld + own, ere, eim, 1.f);
       }
     }
   } else {
@@ -1016,8 +1121,15 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
             "matrix-core coarse stencil needs 16-byte aligned RHS rows");
     // built-in rule: two wavefronts per site on small lattices (1024 sites: 8.9 -> 7.8 us)
     const int split = L.kv[KV_COARSE_SPLIT] > 0 ? L.kv[KV_COARSE_SPLIT] : (V < 4096 ? 2 : 1);
-    dim3 grid((unsigned)ceil_div(V * split, 4));
-    if (split == 2) {
+    dim3 grid((unsigned)ceil_div(V * (split == 2 ? 2 : 1), 4));
+    if (split == 3) {
+      if (gamma5_left)
+        hipLaunchKernelGGL((coarse16_mfma_kernel<true, 3>), grid, dim3(256), 0, ctx->stream, (const c64*)A,
+                           (const c64*)x, (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+      else
+        hipLaunchKernelGGL((coarse16_mfma_kernel<false, 3>), grid, dim3(256), 0, ctx->stream, (const c64*)A,
+                           (const c64*)x, (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
+    } else if (split == 2) {
       if (gamma5_left)
         hipLaunchKernelGGL((coarse16_mfma_kernel<true, 2>), grid, dim3(256), 0, ctx->stream, (const c64*)A,
                            (const c64*)x, (c64*)y, L.Lx, L.Lt, nrhs, ldx, ldy);
@@ -1167,11 +1279,11 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
     REQUIRE(((uintptr_t)x | (uintptr_t)b) % 16 == 0 && ld % 2 == 0,
             "matrix-core Gauss-Seidel needs 16-byte aligned vectors");
     const bool h16 = half && L.Ahop16.p && L.Ainv16.p;
-    // built-in rule: two tiles' loads in flight per wavefront where the launch has enough
-    // wavefronts to fill the chip without them (measured at 1024^2: level 2, 32768 sites
-    // per colour, 134 -> 127 us; level 3, 2048 sites, no gain)
-    // (and two wavefronts per site on the smallest launches: 512 sites, 5.8 -> 4.4 us)
-    const int gs_form = L.kv[KV_GS_SPLIT] > 0 ? L.kv[KV_GS_SPLIT] : (nsites >= 16384 ? 3 : (nsites < 1024 ? 2 : 1));
+    // built-in rule: vectors through whole-line loads and stores staged in LDS (measured at
+    // 1024^2: level 2, 32768 sites per colour, 127 -> 118 us; level 3, 2048 sites, 11.4 ->
+    // 10.3 us), and two wavefronts per site on the smallest launches (512 sites: 5.8 ->
+    // 4.4 us)
+    const int gs_form = L.kv[KV_GS_SPLIT] > 0 ? L.kv[KV_GS_SPLIT] : (nsites < 1024 ? 2 : 4);
     KTimer kt(ctx, "coarse_gs",
               (double)nrhs * (V / 2) * d * 3 * sizeof(Cx<R>) + (double)(V / 2) * 5 * d * d * (h16 ? 4 : sizeof(Cx<R>)));
     if (h16 && gs_form == 2)
@@ -1179,6 +1291,9 @@ void launch_coarse_gs(dmlmc_ctx* ctx, const Level& L, Cx<R>* x, const Cx<R>* b, 
                          ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, ld);
     else if (h16 && gs_form == 3)
       hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true, 3>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
+                         ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, ld);
+    else if (h16 && gs_form == 4)
+      hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true, 4>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,
                          ctx->stream, L.Ahop16.p, L.Ainv16.p, (c64*)x, (const c64*)b, L.Lx, L.Lt, nrhs, color, ld);
     else if (h16)
       hipLaunchKernelGGL((coarse16_gs_mfma_kernel<true, 1>), dim3((unsigned)ceil_div(nsites, 4)), dim3(256), 0,

@@ -76,8 +76,8 @@ std::vector<int> candidates(const dmlmc_hier* H, const Level& L, int k) {
   switch (k) {
     case KV_WILSON_RB: return L.fine ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{};
     case KV_SAP_RB: return L.fine ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{};
-    case KV_COARSE_SPLIT: return coarse16 ? std::vector<int>{1, 2} : std::vector<int>{};
-    case KV_GS_SPLIT: return (coarse16 && L.Ahop16.p && L.Ainv16.p) ? std::vector<int>{1, 2, 3} : std::vector<int>{};
+    case KV_COARSE_SPLIT: return coarse16 ? std::vector<int>{1, 2, 3} : std::vector<int>{};
+    case KV_GS_SPLIT: return (coarse16 && L.Ahop16.p && L.Ainv16.p) ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{};
     case KV_RESTRICT_UT: return transfer ? std::vector<int>{1, 2, 4} : std::vector<int>{};
     case KV_PROLONG_MT: {
       if (!transfer) return {};
@@ -212,8 +212,8 @@ void tune_kernels(dmlmc_hier* H, int nrhs, int reps, const char* cache_path, int
 void set_kernel_variant(dmlmc_hier* H, int level, int kernel, int value) {
   REQUIRE(level >= 1 && level <= (int)H->lv.size(), "level out of range");
   REQUIRE(kernel >= 0 && kernel < KV_COUNT, "unknown kernel id");
-  static const std::vector<int> allowed[KV_COUNT] = {{0, 1, 2, 4, 8}, {0, 1, 2}, {0, 1, 2, 4, 8},
-                                                     {0, 1, 2, 3},    {0, 1, 2, 4}, {0, 1, 2, 4}};
+  static const std::vector<int> allowed[KV_COUNT] = {{0, 1, 2, 4, 8}, {0, 1, 2, 3}, {0, 1, 2, 4, 8},
+                                                     {0, 1, 2, 3, 4}, {0, 1, 2, 4}, {0, 1, 2, 4}};
   REQUIRE(std::find(allowed[kernel].begin(), allowed[kernel].end(), value) != allowed[kernel].end(),
           "value not allowed for this kernel");
   H->lv[level - 1].kv[kernel] = value;

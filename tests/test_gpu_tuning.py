@@ -121,7 +121,8 @@ def test_kernel_variants_leave_samples_bitwise_identical(gpu, tmp_path):
          dm.KV_PROLONG_MT: 1},
         {dm.KV_WILSON_RB: 8, dm.KV_COARSE_SPLIT: 1, dm.KV_SAP_RB: 8, dm.KV_GS_SPLIT: 1, dm.KV_RESTRICT_UT: 4,
          dm.KV_PROLONG_MT: 2},
-        {dm.KV_WILSON_RB: 2, dm.KV_SAP_RB: 2, dm.KV_RESTRICT_UT: 2, dm.KV_PROLONG_MT: 4},
+        {dm.KV_WILSON_RB: 2, dm.KV_SAP_RB: 2, dm.KV_RESTRICT_UT: 2, dm.KV_PROLONG_MT: 4, dm.KV_GS_SPLIT: 3},
+        {dm.KV_GS_SPLIT: 4},
     ]
     for case in forced:
         for l in range(1, L + 1):
