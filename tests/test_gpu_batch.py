@@ -6,9 +6,12 @@ replayed from recorded graphs).  Every hierarchy is built on the device.
 
 Parity: the first samples of every level of each 64^2 field and of the first 128^2 field
 against the checker, which builds its own hierarchy and deflation from the same inputs
-(the device setup agrees with it to ~1e-7), error |s_gpu - s_ref| / (|t1| + |t2|)
-(coarsest: / |s|) below 1e-5.  All fields: 512 samples per level drawn, finite estimate,
-relative error estimate consistent with the sample variances.
+(the device setup agrees with it to ~1e-7, which a difference sample amplifies), error
+|s_gpu - s_ref| / (|t1| + |t2|) (coarsest: / |s|) below 1e-5.  And on the first field of
+every size (256^2 included), the same samples from a device hierarchy built on the
+checker's test vectors and deflation, at the mixed-precision bar of 1e-6.  All fields:
+512 samples per level drawn, finite estimate, relative error estimate consistent with the
+sample variances.
 """
 import functools
 
@@ -66,5 +69,24 @@ def test_batched_fields(gpu, size):
                         s = omlmc.coarsest_sample(lv, solver, dref, W.noise_seed, i)
                         scale = abs(s)
                     assert abs(got[i] - s) / scale < 1e-5, (W.name, l, i, got[i], s)
+        if j == 0:
+            # the checker's test vectors and deflation imported: the solves alone are compared
+            lv, dref, solver = _checker(W.name)
+            Hi = dm.Hierarchy(ctx, W.theta(), load_m0(W.name), W.aggs, W.ntv, n_inv=W.n_inv, seed=W.mg_seed,
+                              import_tv=[lvl.V for lvl in lv[:-1]])
+            di = dm.Deflation(Hi, L, W.k_defl, import_X=dref.X, import_lambda=dref.lam)
+            ri = dm.mlmc_trace(Hi, di, W.eps, W.noise_seed, [NCHECK] * L, NCHECK, prec=dm.MIXED, rtol=W.rtol,
+                               fixed_counts=True, max_samples=[NCHECK] * L, keep_samples=True)
+            for l in range(1, L + 1):
+                for i in range(NCHECK):
+                    if l < L:
+                        s, t1, t2 = omlmc.difference_sample(lv, solver, W.noise_seed, l, i)
+                        scale = abs(t1) + abs(t2)
+                    else:
+                        s = omlmc.coarsest_sample(lv, solver, dref, W.noise_seed, i)
+                        scale = abs(s)
+                    assert abs(ri.samples[l - 1][i] - s) / scale < 1e-6, (W.name, l, i, ri.samples[l - 1][i], s)
+            di.close()
+            Hi.close()
         d.close()
         H.close()
