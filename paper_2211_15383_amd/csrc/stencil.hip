@@ -986,6 +986,67 @@ __global__ __launch_bounds__(256) void prolong16_mfma_kernel(const c64* __restri
   }
 }
 
+// Prolongation for d_f = 16, where each 16-entry tile of an aggregate is one fine site
+// (its 16 entries of one RHS are one 128-byte line): as prolong16_mfma_kernel, one 16-RHS
+// tile at a time, with the coarse vector read, the old fine values read (when adding) and
+// the results written by whole lines staged through LDS.  The same products and sums.
+template <int MT>
+__global__ __launch_bounds__(256) void prolong16_staged_kernel(const c64* __restrict__ P, const c64* __restrict__ ec,
+                                                               c64* __restrict__ xf, AggMap g, int64_t Vc, int nrhs,
+                                                               int add, int64_t ldf, int64_t ldc) {
+  __shared__ float4 stage[4][2][16 * 9];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int groups = g.E / 16 / MT;
+  const int64_t wave = xcd_block() * 4 + w;
+  const int64_t cs = wave / groups;
+  if (cs >= Vc) return;  // wave-uniform; no workgroup barrier below
+  const int grp = (int)(wave % groups);
+  const int row = lane & 15, kq = lane >> 4;
+  const int cj = kq >> 1, k0 = 4 * (kq & 1);
+  float4(*rows)[16 * 9] = stage[w];
+  Quad a[MT];
+  int64_t fs[MT];
+#pragma unroll
+  for (int u = 0; u < MT; ++u) {
+    const int mt = grp * MT + u;
+    int ce;
+    const int64_t pr = g.prow(cs, 16 * mt + row, ce);
+    a[u] = select_quad(ce == cj, load_quad_nt(P + pr + k0));
+    fs[u] = g.fine_offset(cs, 16 * mt);  // the tile's site: entries fs .. fs + 15
+  }
+  const int rr = lane >> 3, pc = lane & 7;
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const bool va = r0 + row < nrhs;
+    stage_rows(ec, ldc, r0, nrhs, cs * 16, lane, rows[0]);
+    __builtin_amdgcn_wave_barrier();
+    const Quad ea = select_quad(va, staged_quad(rows[0], lane));
+#pragma unroll
+    for (int u = 0; u < MT; ++u) {
+      f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = are;
+      block_mfma(are, aim, a[u], ea);
+      if (add) {
+        stage_rows(xf, ldf, r0, nrhs, fs[u], lane, rows[1]);
+        __builtin_amdgcn_wave_barrier();
+        const Quad xo = staged_quad(rows[1], lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          are[v] += xo.v[v].x;
+          aim[v] += xo.v[v].y;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      rows[1][row * 9 + 2 * kq] = make_float4(are[0], aim[0], are[1], aim[1]);
+      rows[1][row * 9 + 2 * kq + 1] = make_float4(are[2], aim[2], are[3], aim[3]);
+      __builtin_amdgcn_wave_barrier();
+      if (r0 + rr < nrhs) *reinterpret_cast<float4*>(xf + (int64_t)(r0 + rr) * ldf + fs[u] + 2 * pc) = rows[1][rr * 9 + pc];
+      if (r0 + 8 + rr < nrhs)
+        *reinterpret_cast<float4*>(xf + (int64_t)(r0 + 8 + rr) * ldf + fs[u] + 2 * pc) = rows[1][(8 + rr) * 9 + pc];
+      __builtin_amdgcn_wave_barrier();
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // WPA wavefronts per aggregate (WPA = min(4, E / 16)), 4 / WPA aggregates per workgroup:
 // the aggregate's 16-entry tiles are dealt round-robin to its wavefronts, each of which
 // requests the loads of up to UT tiles before multiplying; the partial 16 x 32 results
@@ -1375,6 +1436,23 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
                                                       : (tiles % 4 == 0 ? std::min(4, tiles) : (tiles % 2 == 0 ? 2 : 1));
     const int64_t Vc = nc / 16;
     const dim3 grid((unsigned)ceil_div(Vc * (tiles / mtw), 4));
+    // 16 dofs per fine site: whole-line traffic staged through LDS; built-in rule from 16384
+    // fine sites on (measured at 1024^2: 256^2 sites, 95 -> 72 us; 64^2 sites, no gain)
+    const bool staged = L.dofs == 16 && (L.kv[KV_PROLONG_STAGED] == 2 ||
+                                         (L.kv[KV_PROLONG_STAGED] == 0 && L.sites() >= 16384));
+    if (staged) {
+      if (mtw == 4)
+        hipLaunchKernelGGL(prolong16_staged_kernel<4>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                           (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
+      else if (mtw == 2)
+        hipLaunchKernelGGL(prolong16_staged_kernel<2>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                           (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
+      else
+        hipLaunchKernelGGL(prolong16_staged_kernel<1>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                           (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
+      LAUNCH_CHECK();
+      return;
+    }
     if (mtw == 4)
       hipLaunchKernelGGL(prolong16_mfma_kernel<4>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
                          (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
