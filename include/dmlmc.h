@@ -333,9 +333,14 @@ dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_def
  *   DMLMC_KV_RESTRICT_UT   matrix-core restriction: tiles per batch of loads, 1, 2, 4
  *   DMLMC_KV_PROLONG_MT    matrix-core prolongation: tiles per wavefront, 1, 2, 4 (a value
  *                          that does not divide the level's tile count falls back to the rule)
- *   DMLMC_KV_PROLONG_STAGED  prolongation onto a level with 16 dofs per site: 1 = direct
- *                          loads and stores, 2 = whole 128-byte lines staged through LDS
- *                          (the rule from 16384 fine sites on)
+ *   DMLMC_KV_PROLONG_STAGED  prolongation onto a level with 16 dofs per site, or whose
+ *                          aggregate rows are half a 128-byte line (a_x x dofs = 8, an even
+ *                          number of aggregates in x): 1 = direct loads and stores, 2 = whole
+ *                          128-byte lines staged through LDS (the rule from 16384 fine sites on)
+ *   DMLMC_KV_RESTRICT_STAGED  restriction from a level whose aggregate rows are half a line
+ *                          (as above, a_t <= 4): 1 = direct, 2 = whole lines staged through
+ *                          LDS, one wavefront per pair of aggregates adjacent in x (the rule
+ *                          from 16384 fine sites on)
  * dmlmc_tune_kernels times, on every level of h, each variant of each kernel that runs
  * there at that level's real shape (nrhs right-hand sides at the solver's work stride,
  * reps launches per variant after one warm-up, HIP events on the context stream) and
@@ -349,7 +354,8 @@ dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_def
  * allocated and freed inside the call.  Errors: EINVAL (nrhs not in 1..512, reps not in
  * 1..1000, cache file not writable), EHIP. */
 enum { DMLMC_KV_WILSON_RB = 0, DMLMC_KV_COARSE_SPLIT = 1, DMLMC_KV_SAP_RB = 2, DMLMC_KV_GS_SPLIT = 3,
-       DMLMC_KV_RESTRICT_UT = 4, DMLMC_KV_PROLONG_MT = 5, DMLMC_KV_PROLONG_STAGED = 6, DMLMC_KV_COUNT = 7 };
+       DMLMC_KV_RESTRICT_UT = 4, DMLMC_KV_PROLONG_MT = 5, DMLMC_KV_PROLONG_STAGED = 6,
+       DMLMC_KV_RESTRICT_STAGED = 7, DMLMC_KV_COUNT = 8 };
 dmlmc_status dmlmc_tune_kernels(dmlmc_ctx *ctx, dmlmc_hier *h, int nrhs, int reps, const char *cache_path,
                                 int *picks, double *best_us, double *default_us);
 /* Sets (or reads) one kernel's variant on one level (1-based) by hand; EINVAL for an

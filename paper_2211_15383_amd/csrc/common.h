@@ -188,8 +188,9 @@ enum KernelVariant {
                      // flight; 4: whole-line vector loads and stores staged in LDS
   KV_RESTRICT_UT,    // matrix-core restriction: 16-entry tiles whose loads a wavefront issues at once (1, 2, 4)
   KV_PROLONG_MT,     // matrix-core prolongation: 16-entry tiles per wavefront (1, 2, 4; dividing the tile count)
-  KV_PROLONG_STAGED,  // prolongation with 16 dofs on the fine side: 1 = direct loads and stores, 2 = whole-line
-                      // vector traffic staged through LDS
+  KV_PROLONG_STAGED,  // prolongation with 16 dofs on the fine side, or fine rows of half a line: 1 = direct
+                      // loads and stores, 2 = whole-line vector traffic staged through LDS
+  KV_RESTRICT_STAGED,  // restriction with fine rows of half a line: 1 = direct, 2 = staged through LDS
   KV_COUNT
 };
 

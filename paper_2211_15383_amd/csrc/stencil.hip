@@ -1047,6 +1047,83 @@ __global__ __launch_bounds__(256) void prolong16_staged_kernel(const c64* __rest
   }
 }
 
+// Prolongation for aggregates whose rows are half a 128-byte line (a_x d_f = 8 entries,
+// the fine level of 2 dofs on 4-site-wide aggregates): one wavefront per pair of
+// aggregates adjacent in x (X even), whose rows share lines, all TT = a_t / 2 tiles of
+// both, one 16-RHS tile at a time.  The two coarse vectors are read, and the 16 x a_t fine
+// lines written (and, when adding, read), by whole lines staged through LDS.  Each entry
+// is the product of prolong16_mfma_kernel, plus the old value when adding, in the same
+// order.
+template <int TT>
+__global__ __launch_bounds__(256) void prolong16_pair_kernel(const c64* __restrict__ P, const c64* __restrict__ ec,
+                                                             c64* __restrict__ xf, AggMap g, int64_t Vc, int nrhs,
+                                                             int add, int64_t ldf, int64_t ldc) {
+  constexpr int NL = 16 * 2 * TT;  // lines of one RHS tile: 16 RHS x a_t fine rows
+  __shared__ float4 stage[4][NL * 9];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t cs0 = 2 * (xcd_block() * 4 + w);
+  if (cs0 >= Vc) return;  // wave-uniform; no workgroup barrier below
+  const int row = lane & 15, kq = lane >> 4;
+  const int cj = kq >> 1, k0 = 4 * (kq & 1);
+  float4* lines = stage[w];
+  Quad a[2][TT];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int u = 0; u < TT; ++u) {
+      int ce;
+      const int64_t pr = g.prow(cs0 + p, 16 * u + row, ce);
+      a[p][u] = select_quad(ce == cj, load_quad_nt(P + pr + k0));
+    }
+  const int rr = lane >> 3, pc = lane & 7;
+  // fine row lt of the pair starts at aggregate cs0's row lt (16 entries: cs0's 8, then cs0 + 1's)
+  int64_t fl[2 * TT];
+#pragma unroll
+  for (int lt = 0; lt < 2 * TT; ++lt) fl[lt] = g.fine_offset(cs0, 8 * lt) + 2 * pc;
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const bool va = r0 + row < nrhs;
+    stage_rows(ec, ldc, r0, nrhs, cs0 * 16, lane, lines);
+    stage_rows(ec, ldc, r0, nrhs, (cs0 + 1) * 16, lane, lines + 16 * 9);
+    __builtin_amdgcn_wave_barrier();
+    const Quad e0 = select_quad(va, staged_quad(lines, lane));
+    const Quad e1 = select_quad(va, staged_quad(lines + 16 * 9, lane));
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int u = 0; u < TT; ++u) {
+        f32x4 re = {0.f, 0.f, 0.f, 0.f}, im = re;
+        block_mfma(re, im, a[p][u], p ? e1 : e0);
+        // entries 16 u + 4 kq .. + 3: fine row 2 u + kq / 2, entries 4 (kq % 2) .. of its 8
+        float4* d = lines + ((2 * u + (kq >> 1)) * 16 + row) * 9 + 4 * p + 2 * (kq & 1);
+        d[0] = make_float4(re[0], im[0], re[1], im[1]);
+        d[1] = make_float4(re[2], im[2], re[3], im[3]);
+      }
+    __builtin_amdgcn_wave_barrier();
+    float4 old[NL / 8];
+    if (add) {
+#pragma unroll
+      for (int i = 0; i < NL / 8; ++i) {
+        const int li = 8 * i + rr, r = min(r0 + (li & 15), nrhs - 1);
+        old[i] = *reinterpret_cast<const float4*>(xf + (int64_t)r * ldf + fl[li >> 4]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NL / 8; ++i) {
+      const int li = 8 * i + rr, r = r0 + (li & 15);
+      float4 v = lines[li * 9 + pc];
+      if (add) {
+        v.x = v.x + old[i].x;
+        v.y = v.y + old[i].y;
+        v.z = v.z + old[i].z;
+        v.w = v.w + old[i].w;
+      }
+      if (r < nrhs) *reinterpret_cast<float4*>(xf + (int64_t)r * ldf + fl[li >> 4]) = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // WPA wavefronts per aggregate (WPA = min(4, E / 16)), 4 / WPA aggregates per workgroup:
 // the aggregate's 16-entry tiles are dealt round-robin to its wavefronts, each of which
 // requests the loads of up to UT tiles before multiplying; the partial 16 x 32 results
@@ -1116,6 +1193,94 @@ __global__ __launch_bounds__(256) void restrict16_mfma_kernel(const c64* __restr
   }
 }
 
+// Restriction for the pair shape of prolong16_pair_kernel with at most three tiles per
+// aggregate (where restrict16_mfma_kernel takes one wavefront per aggregate): one
+// wavefront per pair of aggregates adjacent in x, one 16-RHS tile at a time; the 16 x a_t
+// fine lines are read, and the two aggregates' coarse results written, by whole lines
+// staged through LDS.  Each result is the sum of restrict16_mfma_kernel's products in its
+// order (tile 0, 1, ...).
+template <int TT>
+__global__ __launch_bounds__(256) void restrict16_pair_kernel(const c64* __restrict__ P, const c64* __restrict__ xf,
+                                                              c64* __restrict__ yc, AggMap g, int64_t Vc, int nrhs,
+                                                              int64_t ldf, int64_t ldc) {
+  constexpr int NL = 16 * 2 * TT;
+  __shared__ float4 stage[4][NL * 9];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t cs0 = 2 * (xcd_block() * 4 + w);
+  if (cs0 >= Vc) return;  // wave-uniform; no workgroup barrier below
+  const int row = lane & 15, kq = lane >> 4;
+  const int cj = row >> 3, kj = row & 7;
+  float4* lines = stage[w];
+  Quad a[2][TT];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int u = 0; u < TT; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        int ce;
+        const int64_t pr = g.prow(cs0 + p, 16 * u + 4 * kq + t, ce);
+        const float* pf = reinterpret_cast<const float*>(P + pr + kj);
+        const c64 pv = cmk(__builtin_nontemporal_load(pf), __builtin_nontemporal_load(pf + 1));
+        a[p][u].v[t] = ce == cj ? cmk(pv.x, -pv.y) : cmk(0.f, 0.f);
+      }
+  const int rr = lane >> 3, pc = lane & 7;
+  int64_t fl[2 * TT];
+#pragma unroll
+  for (int lt = 0; lt < 2 * TT; ++lt) fl[lt] = g.fine_offset(cs0, 8 * lt) + 2 * pc;
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const bool va = r0 + row < nrhs;
+    float4 in[NL / 8];
+#pragma unroll
+    for (int i = 0; i < NL / 8; ++i) {
+      const int li = 8 * i + rr, r = min(r0 + (li & 15), nrhs - 1);
+      in[i] = *reinterpret_cast<const float4*>(xf + (int64_t)r * ldf + fl[li >> 4]);
+    }
+#pragma unroll
+    for (int i = 0; i < NL / 8; ++i) lines[(8 * i + rr) * 9 + pc] = in[i];
+    __builtin_amdgcn_wave_barrier();
+    f32x4 re[2], im[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      re[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+      im[p] = re[p];
+#pragma unroll
+      for (int u = 0; u < TT; ++u) {
+        const float4* q = lines + ((2 * u + (kq >> 1)) * 16 + row) * 9 + 4 * p + 2 * (kq & 1);
+        const float4 x0 = q[0], x1 = q[1];
+        Quad xq;
+        xq.v[0] = cmk(x0.x, x0.y);
+        xq.v[1] = cmk(x0.z, x0.w);
+        xq.v[2] = cmk(x1.x, x1.y);
+        xq.v[3] = cmk(x1.z, x1.w);
+        block_mfma(re[p], im[p], a[p][u], select_quad(va, xq));
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // coarse rows: RHS row r of the pair is 32 entries (two lines), entries 16 p + 4 kq ..
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      float4* d = lines + (2 * row + p) * 9 + 2 * kq;
+      d[0] = make_float4(re[p][0], im[p][0], re[p][1], im[p][1]);
+      d[1] = make_float4(re[p][2], im[p][2], re[p][3], im[p][3]);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int li = 8 * i + rr, r = r0 + (li >> 1);
+      if (r < nrhs)
+        *reinterpret_cast<float4*>(yc + (int64_t)r * ldc + (cs0 + (li & 1)) * 16 + 2 * pc) = lines[li * 9 + pc];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// the fine rows of an aggregate are half a 128-byte line and pairs of aggregates adjacent in
+// x share them (tiles per aggregate: a_t / 2)
+bool transfer16_pair_ok(const Level& L) {
+  return L.ax * L.dofs == 8 && (L.Lx / L.ax) % 2 == 0 && (L.at == 2 || L.at == 4 || L.at == 8);
+}
+
 bool transfer16_ok(const Level& L) {
   const int E = L.ax * L.at * L.dofs;
   return L.N == 8 && L.dofs % 2 == 0 && (L.ax * L.dofs) % 4 == 0 && E % 16 == 0;
@@ -1146,6 +1311,7 @@ inline int rhs_block_for(int64_t threads, int nrhs) {
 }  // namespace
 
 bool transfer16_available(const Level& L) { return transfer16_ok(L); }
+bool transfer16_pair_available(const Level& L) { return transfer16_ok(L) && transfer16_pair_ok(L); }
 
 template <typename R>
 void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx, int64_t ldy,
@@ -1391,6 +1557,20 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
   if (std::is_same<R, float>::value && transfer16_ok(L)) {
     REQUIRE(((uintptr_t)xf | (uintptr_t)yc) % 16 == 0, "matrix-core restriction needs 16-byte aligned vectors");
     const AggMap g = agg_map(L);
+    // rows of half a line: pairs of aggregates staged through LDS (built-in rule from 16384
+    // fine sites on)
+    const int rst = L.kv[KV_RESTRICT_STAGED];
+    if (transfer16_pair_ok(L) && L.at <= 4 && (rst == 2 || (rst == 0 && L.sites() >= 16384))) {
+      const dim3 grid((unsigned)ceil_div(Vc / 2, 4));
+      if (L.at == 4)
+        hipLaunchKernelGGL(restrict16_pair_kernel<2>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)xf,
+                           (c64*)yc, g, Vc, nrhs, ldf, ldc);
+      else
+        hipLaunchKernelGGL(restrict16_pair_kernel<1>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)xf,
+                           (c64*)yc, g, Vc, nrhs, ldf, ldc);
+      LAUNCH_CHECK();
+      return;
+    }
     const int wpa = g.E / 16 >= 4 ? 4 : 1;  // wavefronts per aggregate
     const dim3 grid((unsigned)ceil_div(Vc, 4 / wpa));
     // built-in rule (measured at 1024^2): one tile per batch of loads when an aggregate's
@@ -1436,10 +1616,26 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
                                                       : (tiles % 4 == 0 ? std::min(4, tiles) : (tiles % 2 == 0 ? 2 : 1));
     const int64_t Vc = nc / 16;
     const dim3 grid((unsigned)ceil_div(Vc * (tiles / mtw), 4));
-    // 16 dofs per fine site: whole-line traffic staged through LDS; built-in rule from 16384
-    // fine sites on (measured at 1024^2: 256^2 sites, 95 -> 72 us; 64^2 sites, no gain)
-    const bool staged = L.dofs == 16 && (L.kv[KV_PROLONG_STAGED] == 2 ||
-                                         (L.kv[KV_PROLONG_STAGED] == 0 && L.sites() >= 16384));
+    // 16 dofs per fine site, or rows of half a line (pairs of aggregates): whole-line traffic
+    // staged through LDS; built-in rule from 16384 fine sites on (measured at 1024^2: 256^2
+    // sites, 95 -> 72 us; 64^2 sites, no gain)
+    const bool pair = transfer16_pair_ok(L);
+    const bool staged = (L.dofs == 16 || pair) && (L.kv[KV_PROLONG_STAGED] == 2 ||
+                                                   (L.kv[KV_PROLONG_STAGED] == 0 && L.sites() >= 16384));
+    if (staged && pair) {
+      const dim3 pgrid((unsigned)ceil_div(Vc / 2, 4));
+      if (L.at == 8)
+        hipLaunchKernelGGL(prolong16_pair_kernel<4>, pgrid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                           (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
+      else if (L.at == 4)
+        hipLaunchKernelGGL(prolong16_pair_kernel<2>, pgrid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                           (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
+      else
+        hipLaunchKernelGGL(prolong16_pair_kernel<1>, pgrid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,
+                           (c64*)xf, g, Vc, nrhs, add ? 1 : 0, ldf, ldc);
+      LAUNCH_CHECK();
+      return;
+    }
     if (staged) {
       if (mtw == 4)
         hipLaunchKernelGGL(prolong16_staged_kernel<4>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,

@@ -12,3 +12,4 @@ void tune_kernels(dmlmc_hier* H, int nrhs, int reps, const char* cache_path, int
 void set_kernel_variant(dmlmc_hier* H, int level, int kernel, int value);
 // the matrix-core transfer kernels handle this level's interpolation (stencil.hip)
 bool transfer16_available(const Level& L);
+bool transfer16_pair_available(const Level& L);

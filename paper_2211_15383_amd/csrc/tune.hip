@@ -32,7 +32,7 @@ std::map<std::string, int> g_cache;
 
 const char* kv_name(int k) {
   static const char* names[KV_COUNT] = {"wilson_rb", "coarse_split",   "sap_rb",         "gs_split",
-                                        "restrict_ut", "prolong_mt", "prolong_staged"};
+                                        "restrict_ut", "prolong_mt", "prolong_staged", "restrict_staged"};
   return names[k];
 }
 
@@ -80,7 +80,10 @@ std::vector<int> candidates(const dmlmc_hier* H, const Level& L, int k) {
     case KV_COARSE_SPLIT: return coarse16 ? std::vector<int>{1, 2, 3} : std::vector<int>{};
     case KV_GS_SPLIT: return (coarse16 && L.Ahop16.p && L.Ainv16.p) ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{};
     case KV_RESTRICT_UT: return transfer ? std::vector<int>{1, 2, 4} : std::vector<int>{};
-    case KV_PROLONG_STAGED: return (transfer && L.dofs == 16) ? std::vector<int>{1, 2} : std::vector<int>{};
+    case KV_PROLONG_STAGED:
+      return (transfer && (L.dofs == 16 || transfer16_pair_available(L))) ? std::vector<int>{1, 2} : std::vector<int>{};
+    case KV_RESTRICT_STAGED:
+      return (transfer && transfer16_pair_available(L) && L.at <= 4) ? std::vector<int>{1, 2} : std::vector<int>{};
     case KV_PROLONG_MT: {
       if (!transfer) return {};
       const int tiles = L.ax * L.at * L.dofs / 16;
@@ -150,6 +153,7 @@ void tune_kernels(dmlmc_hier* H, int nrhs, int reps, const char* cache_path, int
             case KV_RESTRICT_UT: launch_restrict<float>(ctx, L, x, yc, nrhs, ld, ldc); break;
             case KV_PROLONG_MT: launch_prolong<float>(ctx, L, xc, y, nrhs, false, ldc, ld); break;
             case KV_PROLONG_STAGED: launch_prolong<float>(ctx, L, xc, y, nrhs, false, ldc, ld); break;
+            case KV_RESTRICT_STAGED: launch_restrict<float>(ctx, L, x, yc, nrhs, ld, ldc); break;
           }
         };
         auto time_value = [&](int v) {
@@ -216,7 +220,7 @@ void set_kernel_variant(dmlmc_hier* H, int level, int kernel, int value) {
   REQUIRE(level >= 1 && level <= (int)H->lv.size(), "level out of range");
   REQUIRE(kernel >= 0 && kernel < KV_COUNT, "unknown kernel id");
   static const std::vector<int> allowed[KV_COUNT] = {{0, 1, 2, 4, 8}, {0, 1, 2, 3}, {0, 1, 2, 4, 8}, {0, 1, 2, 3, 4},
-                                                     {0, 1, 2, 4},    {0, 1, 2, 4}, {0, 1, 2}};
+                                                     {0, 1, 2, 4},    {0, 1, 2, 4}, {0, 1, 2},    {0, 1, 2}};
   REQUIRE(std::find(allowed[kernel].begin(), allowed[kernel].end(), value) != allowed[kernel].end(),
           "value not allowed for this kernel");
   H->lv[level - 1].kv[kernel] = value;

@@ -23,9 +23,11 @@ FP64, MIXED = 0, 1
 DIRECT_OFF, DIRECT_FP32, DIRECT_FP16, DIRECT_FP8 = 0, 1, 2, 3
 OP_D, OP_RESTRICT, OP_PROLONG, OP_SMOOTH, OP_VCYCLE, OP_DEFL_C, OP_DEFL_P, OP_GAMMA5_D = 0, 1, 2, 3, 4, 6, 7, 8
 # launch-variant autotuner kernel ids (dmlmc_tune_kernels)
-KV_WILSON_RB, KV_COARSE_SPLIT, KV_SAP_RB, KV_GS_SPLIT, KV_RESTRICT_UT, KV_PROLONG_MT, KV_PROLONG_STAGED = range(7)
-KV_COUNT = 7
-KV_NAMES = ("wilson_rb", "coarse_split", "sap_rb", "gs_split", "restrict_ut", "prolong_mt", "prolong_staged")
+(KV_WILSON_RB, KV_COARSE_SPLIT, KV_SAP_RB, KV_GS_SPLIT, KV_RESTRICT_UT, KV_PROLONG_MT, KV_PROLONG_STAGED,
+ KV_RESTRICT_STAGED) = range(8)
+KV_COUNT = 8
+KV_NAMES = ("wilson_rb", "coarse_split", "sap_rb", "gs_split", "restrict_ut", "prolong_mt", "prolong_staged",
+            "restrict_staged")
 
 EXPORTED = [
     "dmlmc_create", "dmlmc_destroy", "dmlmc_last_error", "dmlmc_version", "dmlmc_build_hierarchy",

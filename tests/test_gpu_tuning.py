@@ -122,8 +122,8 @@ def test_kernel_variants_leave_samples_bitwise_identical(gpu, tmp_path):
         {dm.KV_WILSON_RB: 8, dm.KV_COARSE_SPLIT: 1, dm.KV_SAP_RB: 8, dm.KV_GS_SPLIT: 1, dm.KV_RESTRICT_UT: 4,
          dm.KV_PROLONG_MT: 2},
         {dm.KV_WILSON_RB: 2, dm.KV_SAP_RB: 2, dm.KV_RESTRICT_UT: 2, dm.KV_PROLONG_MT: 4, dm.KV_GS_SPLIT: 3},
-        {dm.KV_GS_SPLIT: 4, dm.KV_PROLONG_STAGED: 1},
-        {dm.KV_PROLONG_STAGED: 2, dm.KV_COARSE_SPLIT: 3},
+        {dm.KV_GS_SPLIT: 4, dm.KV_PROLONG_STAGED: 1, dm.KV_RESTRICT_STAGED: 1},
+        {dm.KV_PROLONG_STAGED: 2, dm.KV_COARSE_SPLIT: 3, dm.KV_RESTRICT_STAGED: 2},
     ]
     for case in forced:
         for l in range(1, L + 1):
@@ -142,7 +142,8 @@ def test_kernel_variants_leave_samples_bitwise_identical(gpu, tmp_path):
     picks = H.tune_kernels(32, reps=3, cache_path=cache)
     print(f"[variants] tuned {picks}", flush=True)
     kinds = {k for (_, k) in picks}
-    assert {"wilson_rb", "sap_rb", "coarse_split", "gs_split", "restrict_ut", "prolong_mt", "prolong_staged"} <= kinds
+    assert {"wilson_rb", "sap_rb", "coarse_split", "gs_split", "restrict_ut", "prolong_mt", "prolong_staged",
+            "restrict_staged"} <= kinds
     for (l, k), (v, best, rule) in picks.items():
         assert H.kernel_variant(l, dm.KV_NAMES.index(k)) == v
         assert best > 0 and rule > 0 and best <= rule
