@@ -324,7 +324,9 @@ dmlmc_status dmlmc_tune_rhs_block(dmlmc_ctx *ctx, dmlmc_hier *h, const dmlmc_def
  * entry is the same in all of them, so a choice changes timing only, never a result bit.
  * Kernel ids and their values (0 always selects the built-in rule):
  *   DMLMC_KV_WILSON_RB     fine stencil, RHS per thread: 1, 2, 4, 8
- *   DMLMC_KV_COARSE_SPLIT  coarse block stencil (16 dofs/site): wavefronts per site, 1 or 2
+ *   DMLMC_KV_COARSE_SPLIT  coarse block stencil (16 dofs/site): wavefronts per site, 1 or 2;
+ *                          3: one wavefront per site, blocks and vectors read and results
+ *                          written by whole 128-byte lines staged through LDS (the rule)
  *   DMLMC_KV_SAP_RB        SAP colour sweep, RHS per thread: 1, 2, 4, 8
  *   DMLMC_KV_GS_SPLIT      coarse Gauss-Seidel (FP16 blocks): wavefronts per site, 1 or 2;
  *                          3: one wavefront per site with two 16-RHS tiles' loads in flight;

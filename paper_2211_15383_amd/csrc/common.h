@@ -182,7 +182,8 @@ void timing_collect(dmlmc_ctx* ctx);
 // variant gives bitwise the same results.  Value 0 takes the built-in rule.
 enum KernelVariant {
   KV_WILSON_RB = 0,  // fine stencil: RHS per thread (1, 2, 4, 8)
-  KV_COARSE_SPLIT,   // complex-FP32 coarse stencil, d = 16: wavefronts per site (1: both 16-RHS tiles, 2: one each)
+  KV_COARSE_SPLIT,   // complex-FP32 coarse stencil, d = 16: wavefronts per site (1: both 16-RHS tiles, 2: one each);
+                     // 3: whole-line traffic staged through LDS
   KV_SAP_RB,         // SAP colour sweep: RHS per thread (1, 2, 4, 8)
   KV_GS_SPLIT,       // complex-FP16-block Gauss-Seidel, d = 16: 1, 2 wavefronts per site; 3: tile pairs in
                      // flight; 4: whole-line vector loads and stores staged in LDS

@@ -501,26 +501,32 @@ __device__ __forceinline__ Quad select_quad(bool keep, const Quad& q) {
   return r;
 }
 
+// LDS position of 16-byte chunk c (0..7) of staged line L: lines of 8 chunks, unpadded, with
+// the chunk index XOR-swizzled by the line, so that the column reads and writes of the
+// matrix-core layout (one chunk of each of 8 or 16 consecutive lines) and the row accesses
+// of the whole-line loads and stores (the 8 chunks of a line) both fall on distinct banks
+__device__ __forceinline__ int sw(int L, int c) { return L * 8 + (c ^ ((L ^ (L >> 3)) & 7)); }
+
 // The 16 RHS rows r0 .. r0+15 (clamped to nrhs - 1) of the 16 complex entries at entry
 // offset `off` of v, read with whole-line loads: each of a lane's two 16-byte loads belongs
 // to a group of 8 lanes covering one 128-byte line (RHS l / 8 and 8 + l / 8, piece l % 8),
 // so each load instruction touches 8 lines instead of 16 half lines.  The two pieces go to
-// the wavefront's LDS rows (144 bytes apart, so that the read-back below is free of bank
-// conflicts); LDS operations of one wavefront complete in order.
+// the wavefront's LDS rows at their swizzled positions (sw); LDS operations of one
+// wavefront complete in order.
 __device__ __forceinline__ void stage_rows(const c64* __restrict__ v, int64_t ld, int r0, int nrhs, int64_t off,
                                            int lane, float4* __restrict__ rows) {
   const int rr = lane >> 3, pc = lane & 7;
   const int ra = min(r0 + rr, nrhs - 1), rb = min(r0 + 8 + rr, nrhs - 1);
   const float4 A = *reinterpret_cast<const float4*>(v + (int64_t)ra * ld + off + 2 * pc);
   const float4 B = *reinterpret_cast<const float4*>(v + (int64_t)rb * ld + off + 2 * pc);
-  rows[rr * 9 + pc] = A;
-  rows[(8 + rr) * 9 + pc] = B;
+  rows[sw(rr, pc)] = A;
+  rows[sw(8 + rr, pc)] = B;
 }
 
 // the quad of lane (row, kq) from staged rows: entries 4 kq .. 4 kq + 3 of RHS row
 __device__ __forceinline__ Quad staged_quad(const float4* __restrict__ rows, int lane) {
   const int row = lane & 15, kq = lane >> 4;
-  const float4 u = rows[row * 9 + 2 * kq], w = rows[row * 9 + 2 * kq + 1];
+  const float4 u = rows[sw(row, 2 * kq)], w = rows[sw(row, 2 * kq + 1)];
   Quad q;
   q.v[0] = cmk(u.x, u.y);
   q.v[1] = cmk(u.z, u.w);
@@ -533,7 +539,7 @@ __device__ __forceinline__ Quad staged_quad(const float4* __restrict__ rows, int
 // wavefront, all RHS in pairs of 16-wide tiles; SPLIT = 2: two wavefronts per site (the
 // same workgroup), each taking every other 16-wide tile; SPLIT = 3: one site per
 // wavefront, one tile at a time, the blocks and vectors read and the result written by
-// whole 128-byte lines staged through LDS (11.5 KB per wavefront).  Every load of a pass
+// whole 128-byte lines staged through LDS (10 KB per wavefront).  Every load of a pass
 // is issued before the first product (rows beyond nrhs load a valid row and are zeroed),
 // so the wavefront has all its memory requests in flight at once.  Each output tile is the
 // same sequence of products in every form.
@@ -551,8 +557,8 @@ __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restric
   const int64_t sites[5] = {s, nb.xp, nb.xm, nb.tp, nb.tm};
   const float sg = (G5 && kq >= 2) ? -1.f : 1.f;
   if constexpr (SPLIT == 3) {
-    __shared__ float4 stage[4][5][16 * 9];
-    float4(*rows)[16 * 9] = stage[w];
+    __shared__ float4 stage[4][5][16 * 8];
+    float4(*rows)[16 * 8] = stage[w];
     // a block is 16 rows of 16 complex entries, like 16 RHS rows of a site
     Quad a[5];
 #pragma unroll
@@ -575,13 +581,13 @@ __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restric
       for (int dir = 0; dir < 5; ++dir) block_mfma(are, aim, a[dir], select_quad(va, xa[dir]));
       __builtin_amdgcn_wave_barrier();
       float4* o = rows[0];
-      o[row * 9 + 2 * kq] = make_float4(sg * are[0], sg * aim[0], sg * are[1], sg * aim[1]);
-      o[row * 9 + 2 * kq + 1] = make_float4(sg * are[2], sg * aim[2], sg * are[3], sg * aim[3]);
+      o[sw(row, 2 * kq)] = make_float4(sg * are[0], sg * aim[0], sg * are[1], sg * aim[1]);
+      o[sw(row, 2 * kq + 1)] = make_float4(sg * are[2], sg * aim[2], sg * are[3], sg * aim[3]);
       __builtin_amdgcn_wave_barrier();
       const int rr = lane >> 3, pc = lane & 7;
-      if (r0 + rr < nrhs) *reinterpret_cast<float4*>(out + (int64_t)(r0 + rr) * ldy + s * 16 + 2 * pc) = o[rr * 9 + pc];
+      if (r0 + rr < nrhs) *reinterpret_cast<float4*>(out + (int64_t)(r0 + rr) * ldy + s * 16 + 2 * pc) = o[sw(rr, pc)];
       if (r0 + 8 + rr < nrhs)
-        *reinterpret_cast<float4*>(out + (int64_t)(r0 + 8 + rr) * ldy + s * 16 + 2 * pc) = o[(8 + rr) * 9 + pc];
+        *reinterpret_cast<float4*>(out + (int64_t)(r0 + 8 + rr) * ldy + s * 16 + 2 * pc) = o[sw(8 + rr, pc)];
       __builtin_amdgcn_wave_barrier();
     }
     return;
@@ -764,7 +770,7 @@ __device__ __forceinline__ void gs16_tile(const uint4 (&a)[4], const uint4& ai, 
 // SPLIT (FP16 blocks only): 1 = one wavefront per site, its 16-RHS tiles in sequence;
 // 2 = two wavefronts per site (same workgroup), each taking every other tile and reading
 // the site's blocks; 3 = one wavefront per site, the loads of two tiles in flight together;
-// 4 = as 1 with the vectors read by whole-line loads staged through LDS (11.5 KB per
+// 4 = as 1 with the vectors read by whole-line loads staged through LDS (10 KB per
 // wavefront).
 template <bool H16, int SPLIT>
 __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __restrict__ Av,
@@ -817,8 +823,8 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
         if (vb) store_quad(x + (int64_t)rb * ld + own, ere, eim, 1.f);
       }
     } else if constexpr (SPLIT == 4) {
-      __shared__ float4 stage[4][5][16 * 9];
-      float4(*rows)[16 * 9] = stage[w];
+      __shared__ float4 stage[4][5][16 * 8];
+      float4(*rows)[16 * 8] = stage[w];
       for (int r0 = 0; r0 < nrhs; r0 += 16) {
         const int ra = r0 + row;
         const bool va = ra < nrhs;
@@ -836,15 +842,15 @@ __global__ __launch_bounds__(256) void coarse16_gs_mfma_kernel(const void* __res
         // 16-byte stores (rows staged by the b vector above are free again)
         __builtin_amdgcn_wave_barrier();
         float4* out = rows[4];
-        out[row * 9 + 2 * kq] = make_float4(ere[0], eim[0], ere[1], eim[1]);
-        out[row * 9 + 2 * kq + 1] = make_float4(ere[2], eim[2], ere[3], eim[3]);
+        out[sw(row, 2 * kq)] = make_float4(ere[0], eim[0], ere[1], eim[1]);
+        out[sw(row, 2 * kq + 1)] = make_float4(ere[2], eim[2], ere[3], eim[3]);
         __builtin_amdgcn_wave_barrier();
         {
           const int rr = lane >> 3, pc = lane & 7;
           if (r0 + rr < nrhs)
-            *reinterpret_cast<float4*>(x + (int64_t)(r0 + rr) * ld + s * 16 + 2 * pc) = out[rr * 9 + pc];
+            *reinterpret_cast<float4*>(x + (int64_t)(r0 + rr) * ld + s * 16 + 2 * pc) = out[sw(rr, pc)];
           if (r0 + 8 + rr < nrhs)
-            *reinterpret_cast<float4*>(x + (int64_t)(r0 + 8 + rr) * ld + s * 16 + 2 * pc) = out[(8 + rr) * 9 + pc];
+            *reinterpret_cast<float4*>(x + (int64_t)(r0 + 8 + rr) * ld + s * 16 + 2 * pc) = out[sw(8 + rr, pc)];
         }
         __builtin_amdgcn_wave_barrier();  // the next tile's staging writes come after these reads
       }
@@ -994,7 +1000,7 @@ template <int MT>
 __global__ __launch_bounds__(256) void prolong16_staged_kernel(const c64* __restrict__ P, const c64* __restrict__ ec,
                                                                c64* __restrict__ xf, AggMap g, int64_t Vc, int nrhs,
                                                                int add, int64_t ldf, int64_t ldc) {
-  __shared__ float4 stage[4][2][16 * 9];
+  __shared__ float4 stage[4][2][16 * 8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int groups = g.E / 16 / MT;
   const int64_t wave = xcd_block() * 4 + w;
@@ -1003,7 +1009,7 @@ __global__ __launch_bounds__(256) void prolong16_staged_kernel(const c64* __rest
   const int grp = (int)(wave % groups);
   const int row = lane & 15, kq = lane >> 4;
   const int cj = kq >> 1, k0 = 4 * (kq & 1);
-  float4(*rows)[16 * 9] = stage[w];
+  float4(*rows)[16 * 8] = stage[w];
   Quad a[MT];
   int64_t fs[MT];
 #pragma unroll
@@ -1035,12 +1041,12 @@ __global__ __launch_bounds__(256) void prolong16_staged_kernel(const c64* __rest
         }
       }
       __builtin_amdgcn_wave_barrier();
-      rows[1][row * 9 + 2 * kq] = make_float4(are[0], aim[0], are[1], aim[1]);
-      rows[1][row * 9 + 2 * kq + 1] = make_float4(are[2], aim[2], are[3], aim[3]);
+      rows[1][sw(row, 2 * kq)] = make_float4(are[0], aim[0], are[1], aim[1]);
+      rows[1][sw(row, 2 * kq + 1)] = make_float4(are[2], aim[2], are[3], aim[3]);
       __builtin_amdgcn_wave_barrier();
-      if (r0 + rr < nrhs) *reinterpret_cast<float4*>(xf + (int64_t)(r0 + rr) * ldf + fs[u] + 2 * pc) = rows[1][rr * 9 + pc];
+      if (r0 + rr < nrhs) *reinterpret_cast<float4*>(xf + (int64_t)(r0 + rr) * ldf + fs[u] + 2 * pc) = rows[1][sw(rr, pc)];
       if (r0 + 8 + rr < nrhs)
-        *reinterpret_cast<float4*>(xf + (int64_t)(r0 + 8 + rr) * ldf + fs[u] + 2 * pc) = rows[1][(8 + rr) * 9 + pc];
+        *reinterpret_cast<float4*>(xf + (int64_t)(r0 + 8 + rr) * ldf + fs[u] + 2 * pc) = rows[1][sw(8 + rr, pc)];
       __builtin_amdgcn_wave_barrier();
     }
     __builtin_amdgcn_wave_barrier();
@@ -1059,7 +1065,7 @@ __global__ __launch_bounds__(256) void prolong16_pair_kernel(const c64* __restri
                                                              c64* __restrict__ xf, AggMap g, int64_t Vc, int nrhs,
                                                              int add, int64_t ldf, int64_t ldc) {
   constexpr int NL = 16 * 2 * TT;  // lines of one RHS tile: 16 RHS x a_t fine rows
-  __shared__ float4 stage[4][NL * 9];
+  __shared__ float4 stage[4][NL * 8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t cs0 = 2 * (xcd_block() * 4 + w);
   if (cs0 >= Vc) return;  // wave-uniform; no workgroup barrier below
@@ -1083,10 +1089,10 @@ __global__ __launch_bounds__(256) void prolong16_pair_kernel(const c64* __restri
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const bool va = r0 + row < nrhs;
     stage_rows(ec, ldc, r0, nrhs, cs0 * 16, lane, lines);
-    stage_rows(ec, ldc, r0, nrhs, (cs0 + 1) * 16, lane, lines + 16 * 9);
+    stage_rows(ec, ldc, r0, nrhs, (cs0 + 1) * 16, lane, lines + 16 * 8);
     __builtin_amdgcn_wave_barrier();
     const Quad e0 = select_quad(va, staged_quad(lines, lane));
-    const Quad e1 = select_quad(va, staged_quad(lines + 16 * 9, lane));
+    const Quad e1 = select_quad(va, staged_quad(lines + 16 * 8, lane));
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int p = 0; p < 2; ++p)
@@ -1095,9 +1101,9 @@ __global__ __launch_bounds__(256) void prolong16_pair_kernel(const c64* __restri
         f32x4 re = {0.f, 0.f, 0.f, 0.f}, im = re;
         block_mfma(re, im, a[p][u], p ? e1 : e0);
         // entries 16 u + 4 kq .. + 3: fine row 2 u + kq / 2, entries 4 (kq % 2) .. of its 8
-        float4* d = lines + ((2 * u + (kq >> 1)) * 16 + row) * 9 + 4 * p + 2 * (kq & 1);
-        d[0] = make_float4(re[0], im[0], re[1], im[1]);
-        d[1] = make_float4(re[2], im[2], re[3], im[3]);
+        const int L = (2 * u + (kq >> 1)) * 16 + row, c = 4 * p + 2 * (kq & 1);
+        lines[sw(L, c)] = make_float4(re[0], im[0], re[1], im[1]);
+        lines[sw(L, c + 1)] = make_float4(re[2], im[2], re[3], im[3]);
       }
     __builtin_amdgcn_wave_barrier();
     float4 old[NL / 8];
@@ -1111,7 +1117,7 @@ __global__ __launch_bounds__(256) void prolong16_pair_kernel(const c64* __restri
 #pragma unroll
     for (int i = 0; i < NL / 8; ++i) {
       const int li = 8 * i + rr, r = r0 + (li & 15);
-      float4 v = lines[li * 9 + pc];
+      float4 v = lines[sw(li, pc)];
       if (add) {
         v.x = v.x + old[i].x;
         v.y = v.y + old[i].y;
@@ -1204,7 +1210,7 @@ __global__ __launch_bounds__(256) void restrict16_pair_kernel(const c64* __restr
                                                               c64* __restrict__ yc, AggMap g, int64_t Vc, int nrhs,
                                                               int64_t ldf, int64_t ldc) {
   constexpr int NL = 16 * 2 * TT;
-  __shared__ float4 stage[4][NL * 9];
+  __shared__ float4 stage[4][NL * 8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t cs0 = 2 * (xcd_block() * 4 + w);
   if (cs0 >= Vc) return;  // wave-uniform; no workgroup barrier below
@@ -1237,7 +1243,7 @@ __global__ __launch_bounds__(256) void restrict16_pair_kernel(const c64* __restr
       in[i] = *reinterpret_cast<const float4*>(xf + (int64_t)r * ldf + fl[li >> 4]);
     }
 #pragma unroll
-    for (int i = 0; i < NL / 8; ++i) lines[(8 * i + rr) * 9 + pc] = in[i];
+    for (int i = 0; i < NL / 8; ++i) lines[sw(8 * i + rr, pc)] = in[i];
     __builtin_amdgcn_wave_barrier();
     f32x4 re[2], im[2];
 #pragma unroll
@@ -1246,8 +1252,8 @@ __global__ __launch_bounds__(256) void restrict16_pair_kernel(const c64* __restr
       im[p] = re[p];
 #pragma unroll
       for (int u = 0; u < TT; ++u) {
-        const float4* q = lines + ((2 * u + (kq >> 1)) * 16 + row) * 9 + 4 * p + 2 * (kq & 1);
-        const float4 x0 = q[0], x1 = q[1];
+        const int L = (2 * u + (kq >> 1)) * 16 + row, c = 4 * p + 2 * (kq & 1);
+        const float4 x0 = lines[sw(L, c)], x1 = lines[sw(L, c + 1)];
         Quad xq;
         xq.v[0] = cmk(x0.x, x0.y);
         xq.v[1] = cmk(x0.z, x0.w);
@@ -1260,16 +1266,15 @@ __global__ __launch_bounds__(256) void restrict16_pair_kernel(const c64* __restr
     // coarse rows: RHS row r of the pair is 32 entries (two lines), entries 16 p + 4 kq ..
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      float4* d = lines + (2 * row + p) * 9 + 2 * kq;
-      d[0] = make_float4(re[p][0], im[p][0], re[p][1], im[p][1]);
-      d[1] = make_float4(re[p][2], im[p][2], re[p][3], im[p][3]);
+      lines[sw(2 * row + p, 2 * kq)] = make_float4(re[p][0], im[p][0], re[p][1], im[p][1]);
+      lines[sw(2 * row + p, 2 * kq + 1)] = make_float4(re[p][2], im[p][2], re[p][3], im[p][3]);
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int li = 8 * i + rr, r = r0 + (li >> 1);
       if (r < nrhs)
-        *reinterpret_cast<float4*>(yc + (int64_t)r * ldc + (cs0 + (li & 1)) * 16 + 2 * pc) = lines[li * 9 + pc];
+        *reinterpret_cast<float4*>(yc + (int64_t)r * ldc + (cs0 + (li & 1)) * 16 + 2 * pc) = lines[sw(li, pc)];
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -1313,6 +1318,17 @@ inline int rhs_block_for(int64_t threads, int nrhs) {
 bool transfer16_available(const Level& L) { return transfer16_ok(L); }
 bool transfer16_pair_available(const Level& L) { return transfer16_ok(L) && transfer16_pair_ok(L); }
 
+// whether the staged transfers run (built-in rule from 16384 fine sites on: measured at
+// 1024^2, where the level-1 and level-2 transfers gain and the 64^2-site ones do not)
+static bool prolong_staged_rule(const Level& L) {
+  return L.kv[KV_PROLONG_STAGED] == 2 || (L.kv[KV_PROLONG_STAGED] == 0 && L.sites() >= 16384);
+}
+bool restrict16_pair_selected(const Level& L) {
+  const int v = L.kv[KV_RESTRICT_STAGED];
+  return transfer16_pair_available(L) && L.at <= 4 && (v == 2 || (v == 0 && L.sites() >= 16384));
+}
+bool prolong16_pair_selected(const Level& L) { return transfer16_pair_available(L) && prolong_staged_rule(L); }
+
 template <typename R>
 void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, int64_t ldx, int64_t ldy,
                    bool gamma5_left, const Cx<R>* sub) {
@@ -1346,8 +1362,10 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
     REQUIRE(sub == nullptr, "the complex-FP32 matrix-core stencil has no residual form");
     REQUIRE(ldx % 2 == 0 && ldy % 2 == 0 && ((uintptr_t)x | (uintptr_t)y) % 16 == 0,
             "matrix-core coarse stencil needs 16-byte aligned RHS rows");
-    // built-in rule: two wavefronts per site on small lattices (1024 sites: 8.9 -> 7.8 us)
-    const int split = L.kv[KV_COARSE_SPLIT] > 0 ? L.kv[KV_COARSE_SPLIT] : (V < 4096 ? 2 : 1);
+    // built-in rule: whole-line traffic staged through LDS (measured at 1024^2 with the
+    // swizzled LDS rows: 65536 sites 290 -> 267 us, 4096 sites 21.9 -> 20.1 us, 1024 sites
+    // 8.0 -> 7.0 us against the best of the other forms)
+    const int split = L.kv[KV_COARSE_SPLIT] > 0 ? L.kv[KV_COARSE_SPLIT] : 3;
     dim3 grid((unsigned)ceil_div(V * (split == 2 ? 2 : 1), 4));
     if (split == 3) {
       if (gamma5_left)
@@ -1557,10 +1575,8 @@ void launch_restrict(dmlmc_ctx* ctx, const Level& L, const Cx<R>* xf, Cx<R>* yc,
   if (std::is_same<R, float>::value && transfer16_ok(L)) {
     REQUIRE(((uintptr_t)xf | (uintptr_t)yc) % 16 == 0, "matrix-core restriction needs 16-byte aligned vectors");
     const AggMap g = agg_map(L);
-    // rows of half a line: pairs of aggregates staged through LDS (built-in rule from 16384
-    // fine sites on)
-    const int rst = L.kv[KV_RESTRICT_STAGED];
-    if (transfer16_pair_ok(L) && L.at <= 4 && (rst == 2 || (rst == 0 && L.sites() >= 16384))) {
+    // rows of half a line: pairs of aggregates staged through LDS
+    if (restrict16_pair_selected(L)) {
       const dim3 grid((unsigned)ceil_div(Vc / 2, 4));
       if (L.at == 4)
         hipLaunchKernelGGL(restrict16_pair_kernel<2>, grid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)xf,
@@ -1619,10 +1635,8 @@ void launch_prolong(dmlmc_ctx* ctx, const Level& L, const Cx<R>* ec, Cx<R>* xf, 
     // 16 dofs per fine site, or rows of half a line (pairs of aggregates): whole-line traffic
     // staged through LDS; built-in rule from 16384 fine sites on (measured at 1024^2: 256^2
     // sites, 95 -> 72 us; 64^2 sites, no gain)
-    const bool pair = transfer16_pair_ok(L);
-    const bool staged = (L.dofs == 16 || pair) && (L.kv[KV_PROLONG_STAGED] == 2 ||
-                                                   (L.kv[KV_PROLONG_STAGED] == 0 && L.sites() >= 16384));
-    if (staged && pair) {
+    const bool staged = (L.dofs == 16 || transfer16_pair_ok(L)) && prolong_staged_rule(L);
+    if (prolong16_pair_selected(L)) {
       const dim3 pgrid((unsigned)ceil_div(Vc / 2, 4));
       if (L.at == 8)
         hipLaunchKernelGGL(prolong16_pair_kernel<4>, pgrid, dim3(256), 0, ctx->stream, (const c64*)P, (const c64*)ec,

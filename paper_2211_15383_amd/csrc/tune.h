@@ -13,3 +13,7 @@ void set_kernel_variant(dmlmc_hier* H, int level, int kernel, int value);
 // the matrix-core transfer kernels handle this level's interpolation (stencil.hip)
 bool transfer16_available(const Level& L);
 bool transfer16_pair_available(const Level& L);
+// whether the launch rules of a level currently select the pair-staged transfer kernels
+// (which have no tile-count variants)
+bool restrict16_pair_selected(const Level& L);
+bool prolong16_pair_selected(const Level& L);

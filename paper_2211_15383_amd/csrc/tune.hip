@@ -79,13 +79,13 @@ std::vector<int> candidates(const dmlmc_hier* H, const Level& L, int k) {
     case KV_SAP_RB: return L.fine ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{};
     case KV_COARSE_SPLIT: return coarse16 ? std::vector<int>{1, 2, 3} : std::vector<int>{};
     case KV_GS_SPLIT: return (coarse16 && L.Ahop16.p && L.Ainv16.p) ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{};
-    case KV_RESTRICT_UT: return transfer ? std::vector<int>{1, 2, 4} : std::vector<int>{};
+    case KV_RESTRICT_UT: return (transfer && !restrict16_pair_selected(L)) ? std::vector<int>{1, 2, 4} : std::vector<int>{};
     case KV_PROLONG_STAGED:
       return (transfer && (L.dofs == 16 || transfer16_pair_available(L))) ? std::vector<int>{1, 2} : std::vector<int>{};
     case KV_RESTRICT_STAGED:
       return (transfer && transfer16_pair_available(L) && L.at <= 4) ? std::vector<int>{1, 2} : std::vector<int>{};
     case KV_PROLONG_MT: {
-      if (!transfer) return {};
+      if (!transfer || prolong16_pair_selected(L)) return {};
       const int tiles = L.ax * L.at * L.dofs / 16;
       std::vector<int> v;
       for (int m : {1, 2, 4})
@@ -142,7 +142,11 @@ void tune_kernels(dmlmc_hier* H, int nrhs, int reps, const char* cache_path, int
       }
       launch_z2<float>(ctx, x, L.n(), 0x7475ull, l, 0, nrhs, ld);
       launch_z2<float>(ctx, y, L.n(), 0x7476ull, l, 0, nrhs, ld);
-      for (int k = 0; k < KV_COUNT; ++k) {
+      // the staged-transfer choices come before the tile counts of the kernels they replace
+      static const int order[KV_COUNT] = {KV_WILSON_RB,      KV_SAP_RB,          KV_COARSE_SPLIT, KV_GS_SPLIT,
+                                          KV_PROLONG_STAGED, KV_RESTRICT_STAGED, KV_RESTRICT_UT,  KV_PROLONG_MT};
+      for (int k : order) {
+        cand[k] = candidates(H, L, k);
         if (cand[k].empty()) continue;
         auto run = [&]() {
           switch (k) {
