@@ -245,7 +245,8 @@ struct dmlmc_hier {
   int tuned_block = 0;  // RHS block chosen by the autotuner (0: not tuned)
   // explicit coarsest inverse for the complex-FP32 coarsest solves: complex FP32 [n][n],
   // and its complex-FP16 copy (scaled by 2^-e so that every component is below 1;
-  // coarse_dinv16_unscale = 2^e), and its 8-bit copy (two bytes per complex entry, each
+  // coarse_dinv16_unscale = 2^e; stored in 2 KB blocks of 16 rows x 32 columns in the
+  // order of the matrix-core product's loads), and its 8-bit copy (two bytes per complex entry, each
   // row scaled by its own power of two, coarse_dinv8_rows[i] = 2^(e_i - 8)); mode 0 off, 1 FP32
   // inverse, 2 FP16 inverse, 3 8-bit inverse
   DevBuf coarse_dinv;

@@ -133,10 +133,22 @@ __device__ __forceinline__ uint32_t pack_half2(float re, float im) {
   return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
 
+// The complex-FP16 inverse is stored in the order the product reads it: for each 16-row
+// tile T and 32-column step Q, a 2 KB block holding, for u = 0, 1 and lane = (row, g) =
+// row + 16 g, the four words Dinv[16 T + row][32 Q + 8 g + 4 u .. + 3] (block (T, Q) at
+// word (T n / 32 + Q) 512).  Each 16-byte load of a wavefront then reads one contiguous
+// 1 KB (eight whole 128-byte lines) instead of half of each of 16 lines.
+__device__ __forceinline__ int64_t packed16_index(int64_t i, int64_t j, int64_t n) {
+  const int64_t T = i / 16, Q = j / 32;
+  const int row = (int)(i % 16), c = (int)(j % 32);
+  const int g = c / 8, u = (c % 8) / 4, e = c % 4;
+  return (T * (n / 32) + Q) * 512 + u * 256 + (row + 16 * g) * 4 + e;
+}
+
 // grid: (n / (16 TI) / 4 workgroups) x KS; wave (group, ks) accumulates the TI row tiles
 // Dinv[i0 + 16 t .. + 16) times B over columns [ks n / KS, (ks + 1) n / KS), 32 columns
-// per step: lane (row, g) holds words j0 + 32 q + 8 g .. + 7 of its Dinv rows and of its
-// RHS rows, as two K = 32 operands (words 0..3 and 4..7).
+// per step: lane (row, g) holds words j0 + 32 q + 8 g .. + 7 of its Dinv rows (from the
+// packed order above) and of its RHS rows, as two K = 32 operands (words 0..3 and 4..7).
 template <int TI>
 __global__ __launch_bounds__(256) void dense16_apply_kernel(const uint32_t* __restrict__ Dinv,
                                                             const uint32_t* __restrict__ B, c64* __restrict__ part,
@@ -157,7 +169,8 @@ __global__ __launch_bounds__(256) void dense16_apply_kernel(const uint32_t* __re
     const u32x4* Bb = reinterpret_cast<const u32x4*>(B + (int64_t)min(rb, nrhs - 1) * n + j0 + 8 * g);
     const u32x4* Ar[TI];
 #pragma unroll
-    for (int t = 0; t < TI; ++t) Ar[t] = reinterpret_cast<const u32x4*>(Dinv + (i0 + 16 * t + row) * n + j0 + 8 * g);
+    for (int t = 0; t < TI; ++t)
+      Ar[t] = reinterpret_cast<const u32x4*>(Dinv + ((i0 / 16 + t) * (n / 32) + j0 / 32) * 512) + lane;
     f32x4 are[TI], aim[TI], bre[TI], bim[TI];
 #pragma unroll
     for (int t = 0; t < TI; ++t) are[t] = aim[t] = bre[t] = bim[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -169,7 +182,7 @@ __global__ __launch_bounds__(256) void dense16_apply_kernel(const uint32_t* __re
         xa[u] = Ba[8 * q + u];
         xb[u] = Bb[8 * q + u];
 #pragma unroll
-        for (int t = 0; t < TI; ++t) a[t][u] = Ar[t][8 * q + u];
+        for (int t = 0; t < TI; ++t) a[t][u] = Ar[t][128 * q + 64 * u];
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -338,9 +351,13 @@ __global__ __launch_bounds__(1024) void absmax_partial_kernel(const c64* __restr
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-__global__ void to_half_kernel(const c64* __restrict__ A, int64_t m, float s, uint32_t* __restrict__ A16) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-    A16[i] = pack_half2(s * A[i].x, s * A[i].y);
+// A16 = FP16(s A) in the packed order of dense16_apply_kernel (n x n, n % 32 == 0)
+__global__ void to_half_kernel(const c64* __restrict__ A, int64_t n, float s, uint32_t* __restrict__ A16) {
+  const int64_t m = n * n;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = k / n, j = k % n;
+    A16[packed16_index(i, j, n)] = pack_half2(s * A[k].x, s * A[k].y);
+  }
 }
 
 // Nearest 8-bit float (sign, 4 exponent bits with bias 7, 3 mantissa bits, ties to even)
@@ -490,7 +507,7 @@ void build_coarse_direct16(dmlmc_hier* H) {
   if (amax > 0.f) std::frexp(amax, &e);  // amax < 2^e
   e = std::min(std::max(e, -100), 100);
   H->coarse_dinv16.alloc(sizeof(uint32_t) * (size_t)m);
-  hipLaunchKernelGGL(to_half_kernel, dim3(8192), dim3(256), 0, ctx->stream, H->coarse_dinv.as<c64>(), m,
+  hipLaunchKernelGGL(to_half_kernel, dim3(8192), dim3(256), 0, ctx->stream, H->coarse_dinv.as<c64>(), n,
                      std::ldexp(1.f, -e), H->coarse_dinv16.as<uint32_t>());
   LAUNCH_CHECK();
   HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -161,14 +161,17 @@ __device__ void reduce_or_partial(const double (&acc)[NV], int nv, double* lds, 
   }
 }
 
+// One wavefront per RHS: lane l adds the partials of blocks l, l + 64, ... (one load per
+// lane instead of G dependent ones in a row), then the wavefront sums across lanes.
 __global__ __launch_bounds__(64) void partial_finish_kernel(const double* __restrict__ part, int G, int nv, Fin f) {
   __shared__ double red[NVMAX];
-  const int r = blockIdx.x;
-  for (int q = threadIdx.x; q < nv; q += blockDim.x) {
+  const int r = blockIdx.x, l = threadIdx.x;
+  const double* base = part + (int64_t)r * G * nv;
+  for (int q = 0; q < nv; ++q) {
     double s = 0.0;
-    const double* base = part + (int64_t)r * G * nv + q;
-    for (int g = 0; g < G; ++g) s += base[(int64_t)g * nv];
-    red[q] = s;
+    for (int g = l; g < G; g += 64) s += base[(int64_t)g * nv + q];
+    s = wave_sum(s);
+    if (l == 0) red[q] = s;
   }
   __syncthreads();
   finish_pass(f, r, nv, red);
