@@ -523,6 +523,16 @@ __device__ __forceinline__ void stage_rows(const c64* __restrict__ v, int64_t ld
   rows[sw(8 + rr, pc)] = B;
 }
 
+// the 16 rows of a 16 x 16 block (streamed once per launch: non-temporal loads), staged
+// as stage_rows does
+__device__ __forceinline__ void stage_rows_nt(const c64* __restrict__ A, int lane, float4* __restrict__ rows) {
+  const int rr = lane >> 3, pc = lane & 7;
+  const f32x4 u = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(A + rr * 16 + 2 * pc));
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(A + (8 + rr) * 16 + 2 * pc));
+  rows[sw(rr, pc)] = make_float4(u[0], u[1], u[2], u[3]);
+  rows[sw(8 + rr, pc)] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
 // the quad of lane (row, kq) from staged rows: entries 4 kq .. 4 kq + 3 of RHS row
 __device__ __forceinline__ Quad staged_quad(const float4* __restrict__ rows, int lane) {
   const int row = lane & 15, kq = lane >> 4;
@@ -562,7 +572,7 @@ __global__ __launch_bounds__(256) void coarse16_mfma_kernel(const c64* __restric
     // a block is 16 rows of 16 complex entries, like 16 RHS rows of a site
     Quad a[5];
 #pragma unroll
-    for (int dir = 0; dir < 5; ++dir) stage_rows(A + (s * 5 + dir) * 256, 16, 0, 16, 0, lane, rows[dir]);
+    for (int dir = 0; dir < 5; ++dir) stage_rows_nt(A + (s * 5 + dir) * 256, lane, rows[dir]);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int dir = 0; dir < 5; ++dir) a[dir] = staged_quad(rows[dir], lane);
