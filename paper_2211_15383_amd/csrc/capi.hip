@@ -177,9 +177,12 @@ void dmlmc_destroy(dmlmc_ctx* ctx) {
   }
   ctx->scratch_dots.release();
   ctx->scratch_small.release();
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->readback_event) (void)hipEventDestroy(ctx->readback_event);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
+
 
 const char* dmlmc_last_error(const dmlmc_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 

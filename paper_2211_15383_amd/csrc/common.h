@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <set>
 #include <memory>
@@ -152,7 +153,22 @@ struct dmlmc_ctx {
   const char* group_cls = nullptr;
   double group_bytes = 0.0;
   int64_t group_launches = 0;
+  // pinned host staging of small device results read back during a solve (readback)
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t readback_event = nullptr;
 };
+
+// Copies small device arrays to host memory and waits for them: the copies go to the
+// context's pinned buffer (direct transfers, no pageable staging), one event on the
+// context stream is waited for, then the values are copied out.  Each part is
+// {device source, host destination, bytes}.
+struct ReadbackPart {
+  const void* dev;
+  void* host;
+  size_t bytes;
+};
+void readback(dmlmc_ctx* ctx, std::initializer_list<ReadbackPart> parts);
 
 // RAII bracket around one launch of a timed kernel class.
 struct KTimer {

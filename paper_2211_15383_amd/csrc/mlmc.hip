@@ -43,8 +43,7 @@ static int deflated_block(dmlmc_hier* H, const dmlmc_defl* defl, int l, const c1
   if (!r.converged) throw DmlmcError(DMLMC_ENOCONV, "sample solve did not converge at level " + std::to_string(l));
   launch_dots<double, double>(ctx, X, Z, n, b, n, n, s1);
   std::vector<c128> h1(b);
-  HIPCHK(hipMemcpyAsync(h1.data(), s1, sizeof(c128) * b, hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  readback(ctx, {{s1, h1.data(), sizeof(c128) * b}});
   for (int q = 0; q < b; ++q) out.emplace_back(h1[q].x, h1[q].y);
   return r.iters;
 }
@@ -100,9 +99,7 @@ static int sample_block(dmlmc_hier* H, const dmlmc_defl* defl, int l, int64_t i0
     launch_dots<double, double>(ctx, X, Z, n, b, n, n, s1);
     launch_dots<double, double>(ctx, Y, Zc, nc, b, nc, nc, s2);
     std::vector<c128> h1(b), h2(b);
-    HIPCHK(hipMemcpyAsync(h1.data(), s1, sizeof(c128) * b, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(h2.data(), s2, sizeof(c128) * b, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    readback(ctx, {{s1, h1.data(), sizeof(c128) * b}, {s2, h2.data(), sizeof(c128) * b}});
     for (int q = 0; q < b; ++q) out.emplace_back(h1[q].x - h2[q].x, h1[q].y - h2[q].y);
   } else {
     iters = deflated_block(H, defl, l, X, b, p, out);

@@ -15,6 +15,33 @@
 #include "dense.h"
 #include "solver.h"
 
+void readback(dmlmc_ctx* ctx, std::initializer_list<ReadbackPart> parts) {
+  size_t total = 0;
+  for (const ReadbackPart& p : parts) total += (p.bytes + 15) / 16 * 16;
+  if (total > ctx->pinned_bytes) {
+    if (ctx->pinned) HIPCHK(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    const size_t want = std::max<size_t>(total, 64 * 1024);
+    HIPCHK(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    ctx->pinned_bytes = want;
+  }
+  if (!ctx->readback_event) HIPCHK(hipEventCreateWithFlags(&ctx->readback_event, hipEventDisableTiming));
+  char* stage = static_cast<char*>(ctx->pinned);
+  size_t off = 0;
+  for (const ReadbackPart& p : parts) {
+    HIPCHK(hipMemcpyAsync(stage + off, p.dev, p.bytes, hipMemcpyDeviceToHost, ctx->stream));
+    off += (p.bytes + 15) / 16 * 16;
+  }
+  HIPCHK(hipEventRecord(ctx->readback_event, ctx->stream));
+  HIPCHK(hipEventSynchronize(ctx->readback_event));
+  off = 0;
+  for (const ReadbackPart& p : parts) {
+    std::memcpy(p.host, stage + off, p.bytes);
+    off += (p.bytes + 15) / 16 * 16;
+  }
+}
+
 namespace {
 
 // ---------------------------------------------------------------- Krylov bookkeeping kernels
@@ -425,8 +452,7 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128
       arnoldi_step<double>(ctx, V, w, j, n, nrhs, k);
     }
     it = j + 1;
-    HIPCHK(hipMemcpyAsync(res_host.data(), k.res, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    readback(ctx, {{k.res, res_host.data(), sizeof(double) * nrhs}});
     bool done = true;
     for (int q = 0; q < nrhs; ++q) {
       if (!std::isfinite(res_host[q])) throw DmlmcError(DMLMC_ENUMERIC, "NaN/Inf in the Krylov residual estimate");
@@ -457,8 +483,7 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
   double* nrm = (double*)hier_buf(H, "sv_nrm", l, sizeof(double) * nrhs);
   std::vector<double> bn(nrhs), rn(nrhs), target(nrhs), est;
   launch_norms2<double>(ctx, B, n, nrhs, n, nrm);
-  HIPCHK(hipMemcpyAsync(bn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  readback(ctx, {{nrm, bn.data(), sizeof(double) * nrhs}});
   // A right-hand side whose entries are far from unit size (root mean square beyond
   // 2^+-8) is solved as 2^-e b with 2^e its root mean square, and the solution scaled
   // back: a power of two is exact in every precision, and the complex-FP32 bulk (whose
@@ -491,7 +516,7 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
     launch_cast<float, double>(ctx, B, U0, n, nrhs, n, ldw);  // r = b at x = 0
   else
     launch_cast<double, double>(ctx, B, Rr, n, nrhs, n, n);
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (any_rescale) HIPCHK(hipStreamSynchronize(ctx->stream));  // the scaled norms' copy into bn
   for (int q = 0; q < nrhs; ++q) {
     bn[q] = std::sqrt(bn[q]);
     rn[q] = bn[q];
@@ -578,8 +603,7 @@ SolveResult solve_level(dmlmc_hier* H, int l, const c128* B, c128* X, int nrhs, 
       apply_residual<double>(ctx, L, X, B, Rr, na);
       launch_norms2<double>(ctx, Rr, n, na, n, nrm);
     }
-    HIPCHK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * na, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    readback(ctx, {{nrm, rn.data(), sizeof(double) * na}});
     for (int q = 0; q < na; ++q) {
       if (!std::isfinite(rn[q])) throw DmlmcError(DMLMC_ENUMERIC, "NaN/Inf in the FP64 residual");
       rn[q] = std::sqrt(rn[q]);
