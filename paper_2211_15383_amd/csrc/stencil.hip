@@ -192,6 +192,11 @@ __global__ __launch_bounds__(256) void sap_kernel(const Cx<R>* __restrict__ U, C
   const bool hxp = lx + 1 < BSX, hxm = lx > 0, htp = lt + 1 < BST, htm = lt > 0;
   const int wl = (threadIdx.x & 63);  // lane within wavefront
   const int wbase = wl - lane;        // first lane of my block within the wavefront
+  const int src_xp = wbase + (hxp ? lane + 1 : lane), src_xm = wbase + (hxm ? lane - 1 : lane);
+  const int src_tp = wbase + (htp ? lane + BSX : lane), src_tm = wbase + (htm ? lane - BSX : lane);
+  // links of the block-restricted operator: zero on the hops that leave the block
+  const Cx<R> zc = cmk((R)0, (R)0);
+  const Cx<R> uxb = hxp ? ux : zc, uxmb = hxm ? uxm : zc, utb = htp ? ut : zc, utmb = htm ? utm : zc;
   const R half = (R)0.5;
   const int r0 = blockIdx.y * rb;
   const int r1 = min(r0 + rb, nrhs);
@@ -229,28 +234,31 @@ __global__ __launch_bounds__(256) void sap_kernel(const Cx<R>* __restrict__ U, C
     Spinor<R> e;
     e.s0 = e.s1 = cmk((R)0, (R)0);
     for (int it = 0; it < mr; ++it) {
-      // q = D_BB rho, neighbours from lanes of the same block
-      Spinor<R> gfx, gbx, gft, gbt;
-      const R v[4] = {rho.s0.x, rho.s0.y, rho.s1.x, rho.s1.y};
-      R fxv[4], bxv[4], ftv[4], btv[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        fxv[c] = __shfl(v[c], wbase + (hxp ? lane + 1 : lane), 64);
-        bxv[c] = __shfl(v[c], wbase + (hxm ? lane - 1 : lane), 64);
-        ftv[c] = __shfl(v[c], wbase + (htp ? lane + BSX : lane), 64);
-        btv[c] = __shfl(v[c], wbase + (htm ? lane - BSX : lane), 64);
-      }
-      const R zx = (R)0;
-      gfx.s0 = hxp ? cmk(fxv[0], fxv[1]) : cmk(zx, zx);
-      gfx.s1 = hxp ? cmk(fxv[2], fxv[3]) : cmk(zx, zx);
-      gbx.s0 = hxm ? cmk(bxv[0], bxv[1]) : cmk(zx, zx);
-      gbx.s1 = hxm ? cmk(bxv[2], bxv[3]) : cmk(zx, zx);
-      gft.s0 = htp ? cmk(ftv[0], ftv[1]) : cmk(zx, zx);
-      gft.s1 = htp ? cmk(ftv[2], ftv[3]) : cmk(zx, zx);
-      gbt.s0 = htm ? cmk(btv[0], btv[1]) : cmk(zx, zx);
-      gbt.s1 = htm ? cmk(btv[2], btv[3]) : cmk(zx, zx);
+      // q = D_BB rho, neighbours from lanes of the same block: each lane forms the spin
+      // projections the four hops onto its site need and the neighbours take them (two
+      // values per hop instead of the whole spinor); the hops that leave the block use the
+      // zeroed links
+      const Cx<R> pxf = rho.s0 - rho.s1, pxb = rho.s0 + rho.s1;
+      const Cx<R> ptf = rho.s0 + mul_i(rho.s1), ptb = rho.s0 + mul_mi(rho.s1);
+      const Cx<R> fxp = cmk(__shfl(pxf.x, src_xp, 64), __shfl(pxf.y, src_xp, 64));
+      const Cx<R> bxp = cmk(__shfl(pxb.x, src_xm, 64), __shfl(pxb.y, src_xm, 64));
+      const Cx<R> ftp = cmk(__shfl(ptf.x, src_tp, 64), __shfl(ptf.y, src_tp, 64));
+      const Cx<R> btp = cmk(__shfl(ptb.x, src_tm, 64), __shfl(ptb.y, src_tm, 64));
       Cx<R> a0, a1;
-      hops(ux, uxm, ut, utm, gfx, gbx, gft, gbt, a0, a1);
+      {
+        Cx<R> h = uxb * fxp;
+        a0 = h;
+        a1 = cmk(-h.x, -h.y);
+        Cx<R> g = conj(uxmb) * bxp;
+        a0 = a0 + g;
+        a1 = a1 + g;
+        h = utb * ftp;
+        a0 = a0 + h;
+        a1 = a1 + mul_mi(h);
+        g = conj(utmb) * btp;
+        a0 = a0 + g;
+        a1 = a1 + mul_i(g);
+      }
       Spinor<R> q;
       q.s0 = diag * rho.s0 - half * a0;
       q.s1 = diag * rho.s1 - half * a1;
