@@ -104,6 +104,41 @@ def test_transfer_and_coarse_operators(gpu, name):
                 assert rel_err(to_host(yd), Dc @ xc) < tol, ("Dc", l + 1, prec)
 
 
+@pytest.mark.parametrize("Lx,Lt,agg", [(32, 16, (4, 2)), (32, 32, (4, 8)), (20, 16, (4, 4))])
+def test_transfer_shapes_and_staged_forms(gpu, Lx, Lt, agg):
+    """Matrix-core transfers on level-1 aggregate shapes the workloads do not use: rows of half
+    a 128-byte line with one or four 16-entry tiles per aggregate, and an odd number of
+    aggregates in x (no pairs: the direct kernels run).  Restriction and prolongation
+    against P^H x and P x from the checker's interpolator, and bitwise the same in the
+    direct and the staged forms."""
+    torch, dm, ctx = gpu
+    theta = link_angles(Lx, Lt, 0.3, 7 * Lx + Lt)
+    m0 = -0.05
+    # Gaussian test vectors: with 4 x 2 aggregates a block is 8 x 8, and the Z4 start
+    # vectors make some of those blocks singular (their Q is then rounding noise)
+    V = random_vectors(Lx * Lt * 2, 8, Lx + Lt)
+    lv = omg.build_hierarchy(theta, m0, (agg,), (8,), 0, 3, import_tv=[V])
+    H = dm.Hierarchy(ctx, theta, m0, (agg,), (8,), n_inv=0, seed=3, import_tv=[V])
+    P = lv[0].P
+    nf, nc = P.shape
+    c64 = torch.complex64
+    for nrhs in (1, 17, 32):
+        xf = random_vectors(nf, nrhs, nrhs)
+        xc = random_vectors(nc, nrhs, 100 + nrhs)
+        outs = []
+        for v in (1, 2):
+            H.set_kernel_variant(1, dm.KV_PROLONG_STAGED, v)
+            H.set_kernel_variant(1, dm.KV_RESTRICT_STAGED, v)
+            yc = torch.empty((nrhs, nc), dtype=c64, device="cuda:0")
+            H.apply(dm.OP_RESTRICT, 1, to_dev(torch, xf, c64), yc, dm.MIXED)
+            yf = torch.empty((nrhs, nf), dtype=c64, device="cuda:0")
+            H.apply(dm.OP_PROLONG, 1, to_dev(torch, xc, c64), yf, dm.MIXED)
+            assert rel_err(to_host(yc), P.conj().T @ xf) < 1e-6, ("R", v, nrhs)
+            assert rel_err(to_host(yf), P @ xc) < 1e-6, ("P", v, nrhs)
+            outs.append((yc.cpu(), yf.cpu()))
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), nrhs
+
+
 @pytest.mark.parametrize("name", ["schwinger16", "schwinger128"])
 def test_smoother_properties(gpu, name):
     """Smoothers keep the exact solution fixed and reduce the residual of a Z2 RHS
