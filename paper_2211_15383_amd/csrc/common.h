@@ -328,6 +328,13 @@ void launch_coarse(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
 template <typename R>
 void apply_op(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int nrhs, bool gamma5_left = false,
               int64_t ld = 0);
+// y = D z on the fine level in complex FP32 fused with the dots <u_i, wscale[r] y> of a
+// single-pass Gram-Schmidt step (basis u_i, i < nb <= 8, at Ub + i * vs, RHS r at r * ld):
+// writes G = wilson_dots_blocks(L) block partials per RHS, 2 nb doubles each, to part
+// (layout of the Gram-Schmidt partial sums) and returns G
+int wilson_dots_blocks(const Level& L);
+int launch_wilson_dots(dmlmc_ctx* ctx, const Level& L, const c64* z, c64* y, int nrhs, int64_t ld, const c64* Ub,
+                       int nb, int64_t vs, const double* wscale, double* part);
 // r = b - D x in one pass (the refinement residual)
 template <typename R>
 void apply_residual(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, const Cx<R>* b, Cx<R>* r, int nrhs);

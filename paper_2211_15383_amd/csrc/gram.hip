@@ -588,9 +588,17 @@ void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs
 }
 
 // One Arnoldi step, single-pass form on an unnormalised complex-FP32 basis.
+int64_t gs_fused_max_n() { return 2 * (int64_t)FUSED_THREADS * FUSED_PPT; }
+
+double* gs_partials(dmlmc_ctx* ctx, int64_t n, int nrhs, int extra_G) {
+  const int G = std::max(gs_blocks(n, nrhs), extra_G);
+  ctx->scratch_dots.ensure(sizeof(double) * (size_t)nrhs * G * NVMAX);
+  return ctx->scratch_dots.as<double>();
+}
+
 template <typename RW>
 void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, int j, int64_t n, int nrhs,
-                       const KrylovArrays& k, const double* wscale, int64_t ld) {
+                       const KrylovArrays& k, const double* wscale, int64_t ld, int dots_G) {
   const int nb = j + 1;
   if (nb > NBMAX) throw DmlmcError(DMLMC_EINVAL, "Krylov basis larger than the Gram-Schmidt limit");
   if (ld <= 0) ld = n;
@@ -608,14 +616,17 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
     return;
   }
   const int G = gs_blocks(n, nrhs);
-  ctx->scratch_dots.ensure(sizeof(double) * (size_t)nrhs * G * NVMAX);
-  double* part = ctx->scratch_dots.as<double>();
+  double* part = gs_partials(ctx, n, nrhs, dots_G);
   dim3 grid(G, nrhs);
   Fin fa = base_fin(k, j, nrhs);
   fa.mode = FIN_SCALED;
   fa.h = k.h1;
   fa.scale = scale;
-  {
+  if (dots_G > 0) {
+    // the dots were formed with w (launch_wilson_dots): only their partial sums remain
+    KTimer kt(ctx, "gs_dots", 0.0);
+    launch_partial_finish(ctx, part, dots_G, 2 * nb, fa, nrhs);
+  } else {
     KTimer kt(ctx, "gs_dots", (double)nrhs * n * (nb * sizeof(c64) + sizeof(Cx<RW>)));
     // the basis count rounded up to 4, 8, 16 or 32 sizes the registers (and occupancy)
     if (nb <= 4)
@@ -659,6 +670,6 @@ void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, i
 template void arnoldi_step<double>(dmlmc_ctx*, c128*, c128*, int, int64_t, int, const KrylovArrays&);
 template void arnoldi_step<float>(dmlmc_ctx*, c64*, c128*, int, int64_t, int, const KrylovArrays&);
 template void arnoldi_step_cgs1<float>(dmlmc_ctx*, c64*, double*, const c64*, int, int64_t, int, const KrylovArrays&,
-                                       const double*, int64_t);
+                                       const double*, int64_t, int);
 template void arnoldi_step_cgs1<double>(dmlmc_ctx*, c64*, double*, const c128*, int, int64_t, int,
-                                        const KrylovArrays&, const double*, int64_t);
+                                        const KrylovArrays&, const double*, int64_t, int);

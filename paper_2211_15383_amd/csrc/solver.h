@@ -36,9 +36,16 @@ void arnoldi_step(dmlmc_ctx* ctx, Cx<RV>* V, c128* w, int j, int64_t n, int nrhs
 // (scale[i][nrhs]); the new vector is wscale[r] * w (wscale NULL: factor 1), w complex
 // FP32 or FP64; FP64 arithmetic.  U and w hold RHS r at r * ld (ld = 0: n), basis vector
 // i at i * nrhs * ld.
+// dots_G > 0: the dots were already formed as dots_G block partials per RHS in the buffer
+// gs_partials returns (launch_wilson_dots); only their sums and the update remain.
 template <typename RW>
 void arnoldi_step_cgs1(dmlmc_ctx* ctx, c64* U, double* scale, const Cx<RW>* w, int j, int64_t n, int nrhs,
-                       const KrylovArrays& k, const double* wscale = nullptr, int64_t ld = 0);
+                       const KrylovArrays& k, const double* wscale = nullptr, int64_t ld = 0, int dots_G = 0);
+// The context's Gram-Schmidt partial-sum buffer, large enough for the passes on vectors of
+// length n and for extra_G block partials per RHS (its address stays valid for both).
+double* gs_partials(dmlmc_ctx* ctx, int64_t n, int nrhs, int extra_G);
+// Vectors longer than this take the multi-workgroup Gram-Schmidt passes.
+int64_t gs_fused_max_n();
 void krylov_solution(dmlmc_ctx* ctx, const KrylovArrays& k, int iters, int nrhs);
 // y[r][i] *= scale[i][r] for i < iters
 void krylov_scale_y(dmlmc_ctx* ctx, const KrylovArrays& k, const double* scale, int iters, int nrhs);

@@ -441,10 +441,20 @@ int fgmres_cycle(dmlmc_hier* H, int l, const c128* r, const double* rnorm2, c128
       // and the scaled FP16 coarsest solve included), so it runs on the unnormalised U_j:
       // z'_j = M U_j, the Arnoldi step scales A z'_j by s_j in FP64, and the solution
       // update takes y_j s_j
+      // on the fine level the operator pass also forms the Gram-Schmidt dots (one read of
+      // the new vector less)
+      const bool fused = L.fine && n > gs_fused_max_n() && j + 1 <= 8;
       run_graphed(H, key, [&]() {
         vcycle<RP>(H, l, (const Cx<RP>*)(U + j * vstride), zj, nrhs, ldw);
-        apply_op<RP>(ctx, L, zj, wr, nrhs, false, ldw);
-        arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k, scale + (int64_t)j * nrhs, ldw);
+        if (fused) {
+          double* part = gs_partials(ctx, n, nrhs, wilson_dots_blocks(L));
+          const int G = launch_wilson_dots(ctx, L, (const c64*)zj, (c64*)wr, nrhs, ldw, U, j + 1, vstride,
+                                           scale + (int64_t)j * nrhs, part);
+          arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k, scale + (int64_t)j * nrhs, ldw, G);
+        } else {
+          apply_op<RP>(ctx, L, zj, wr, nrhs, false, ldw);
+          arnoldi_step_cgs1<float>(ctx, U, scale, (const c64*)wr, j, n, nrhs, k, scale + (int64_t)j * nrhs, ldw);
+        }
       });
     } else {
       vcycle<RP>(H, l, (const Cx<RP>*)(V + j * vstride), zj, nrhs);

@@ -453,6 +453,105 @@ struct __align__(16) C64Pair {
   c64 a, b;
 };
 
+// The fine stencil of a complex-FP32 Arnoldi step fused with the dots of its single-pass
+// Gram-Schmidt: y = D z as wilson_kernel computes it (complex FP32, stored rounded to
+// complex FP32), and for every RHS r the FP64 dots <u_i, s_r y> (i < nb, s_r = wscale[r],
+// the same terms as gs1_dots_kernel) summed over the block's sites, written as block
+// partials part[(r G + block) 2 nb + 2 i + (0: re, 1: im)] with G = gridDim.x, so that the
+// dots pass need not read y again.  SPT sites per thread (blocks of 256 SPT sites, the
+// thread's sites 256 apart); threads beyond the lattice add zeros (no early return: the
+// block sums have barriers).
+template <int NBT, int SPT>
+__global__ __launch_bounds__(256) void wilson_dots_kernel(const c64* __restrict__ U, const c64* __restrict__ in,
+                                                          c64* __restrict__ out, int Lx, int Lt, float diag, int nrhs,
+                                                          int rb, int64_t ld, const c64* __restrict__ Ub, int nb,
+                                                          int64_t vs, const double* __restrict__ wscale,
+                                                          double* __restrict__ part) {
+  __shared__ double red[4][2 * NBT];
+  const int64_t V = (int64_t)Lx * Lt;
+  const int64_t blk = xcd_block();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t st[SPT];
+  bool act[SPT];
+  Nbr nbr[SPT];
+  c64 ux[SPT], ut[SPT], uxm[SPT], utm[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int64_t sr = (blk * SPT + q) * 256 + threadIdx.x;
+    act[q] = sr < V;
+    st[q] = act[q] ? sr : 0;
+    nbr[q] = neighbours(st[q], Lx, Lt);
+    ux[q] = U[st[q]];
+    ut[q] = U[V + st[q]];
+    uxm[q] = U[nbr[q].xm];
+    utm[q] = U[V + nbr[q].tm];
+  }
+  const int r0 = blockIdx.y * rb;
+  const int r1 = min(r0 + rb, nrhs);
+  const float half = 0.5f;
+  for (int r = r0; r < r1; ++r) {
+    const Spinor<float>* p = reinterpret_cast<const Spinor<float>*>(in + r * ld);
+    const C64Pair* ur = reinterpret_cast<const C64Pair*>(Ub + r * ld);
+    Spinor<float> c[SPT], fx[SPT], bx[SPT], ft[SPT], bt[SPT];
+    C64Pair u[SPT][NBT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      c[q] = p[st[q]];
+      fx[q] = p[nbr[q].xp];
+      bx[q] = p[nbr[q].xm];
+      ft[q] = p[nbr[q].tp];
+      bt[q] = p[nbr[q].tm];
+#pragma unroll
+      for (int i = 0; i < NBT; ++i)
+        if (i < nb) u[q][i] = ur[(int64_t)i * (vs / 2) + st[q]];
+    }
+    const double ws = wscale[r];
+    double acc[2 * NBT];
+#pragma unroll
+    for (int i = 0; i < 2 * NBT; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      Cx<float> a0, a1;
+      hops(ux[q], uxm[q], ut[q], utm[q], fx[q], bx[q], ft[q], bt[q], a0, a1);
+      Spinor<float> o;
+      o.s0 = diag * c[q].s0 - half * a0;
+      o.s1 = diag * c[q].s1 - half * a1;
+      if (act[q]) {
+        float* of = reinterpret_cast<float*>(out + r * ld + 2 * st[q]);
+        __builtin_nontemporal_store(o.s0.x, of);
+        __builtin_nontemporal_store(o.s0.y, of + 1);
+        __builtin_nontemporal_store(o.s1.x, of + 2);
+        __builtin_nontemporal_store(o.s1.y, of + 3);
+        const double b0x = ws * o.s0.x, b0y = ws * o.s0.y, b1x = ws * o.s1.x, b1y = ws * o.s1.y;
+#pragma unroll
+        for (int i = 0; i < NBT; ++i) {
+          if (i < nb) {
+            const C64Pair v = u[q][i];
+            acc[2 * i] += (double)v.a.x * b0x + (double)v.a.y * b0y + (double)v.b.x * b1x + (double)v.b.y * b1y;
+            acc[2 * i + 1] += (double)v.a.x * b0y - (double)v.a.y * b0x + (double)v.b.x * b1y - (double)v.b.y * b1x;
+          }
+        }
+      }
+    }
+    const int nv = 2 * nb;
+#pragma unroll
+    for (int i = 0; i < 2 * NBT; ++i) {
+      if (i < nv) {
+        double v = acc[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[w][i] = v;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv)
+      part[((int64_t)r * gridDim.x + blk) * nv + threadIdx.x] =
+          red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+
 struct Quad {
   c64 v[4];
 };
@@ -1379,6 +1478,32 @@ void launch_wilson(dmlmc_ctx* ctx, const Level& L, const Cx<R>* x, Cx<R>* y, int
     hipLaunchKernelGGL((wilson_kernel<R, false>), grid, dim3(256), 0, ctx->stream, U, x, y, L.Lx, L.Lt,
                        (R)(L.m0 + 2.0), nrhs, rb, ldx, ldy, sub);
   LAUNCH_CHECK();
+}
+
+constexpr int WD_SPT = 2;  // sites per thread of the fused stencil-and-dots kernel
+
+int wilson_dots_blocks(const Level& L) { return (int)ceil_div(L.sites(), 256 * WD_SPT); }
+
+int launch_wilson_dots(dmlmc_ctx* ctx, const Level& L, const c64* z, c64* y, int nrhs, int64_t ld, const c64* Ub,
+                       int nb, int64_t vs, const double* wscale, double* part) {
+  REQUIRE(L.fine && nb >= 1 && nb <= 8, "the fused stencil-and-dots pass runs on the fine level with at most 8 basis vectors");
+  REQUIRE(ld >= L.n() && ld % 2 == 0 && vs % 2 == 0 && ((uintptr_t)Ub % 16) == 0,
+          "the fused stencil-and-dots pass needs even strides and a 16-byte aligned basis");
+  const int64_t V = L.sites();
+  const int G = wilson_dots_blocks(L);
+  const int rb = L.kv[KV_WILSON_RB] > 0 ? std::min(L.kv[KV_WILSON_RB], nrhs)
+                                        : std::min(8, rhs_block_for(ceil_div(V, WD_SPT), nrhs));
+  dim3 grid((unsigned)G, (unsigned)ceil_div(nrhs, rb));
+  KTimer kt(ctx, "wilson",
+            (double)nrhs * V * 4 * sizeof(c64) + (double)V * 2 * sizeof(c64) + (double)nrhs * L.n() * nb * sizeof(c64));
+  if (nb <= 4)
+    hipLaunchKernelGGL((wilson_dots_kernel<4, WD_SPT>), grid, dim3(256), 0, ctx->stream, L.U32.as<c64>(), z, y, L.Lx,
+                       L.Lt, (float)(L.m0 + 2.0), nrhs, rb, ld, Ub, nb, vs, wscale, part);
+  else
+    hipLaunchKernelGGL((wilson_dots_kernel<8, WD_SPT>), grid, dim3(256), 0, ctx->stream, L.U32.as<c64>(), z, y, L.Lx,
+                       L.Lt, (float)(L.m0 + 2.0), nrhs, rb, ld, Ub, nb, vs, wscale, part);
+  LAUNCH_CHECK();
+  return G;
 }
 
 template <typename R>
