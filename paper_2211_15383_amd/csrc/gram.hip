@@ -161,15 +161,24 @@ __device__ void reduce_or_partial(const double (&acc)[NV], int nv, double* lds, 
   }
 }
 
-// One wavefront per RHS: lane l adds the partials of blocks l, l + 64, ... (one load per
-// lane instead of G dependent ones in a row), then the wavefront sums across lanes.
+// One wavefront per RHS: lane l adds the partials of blocks l, l + 64, ... into four
+// running sums (blocks l + 256 i + 64 u go to sum u, so that four loads are in flight and
+// no add waits on the previous one), then the wavefront sums across lanes.
 __global__ __launch_bounds__(64) void partial_finish_kernel(const double* __restrict__ part, int G, int nv, Fin f) {
   __shared__ double red[NVMAX];
   const int r = blockIdx.x, l = threadIdx.x;
   const double* base = part + (int64_t)r * G * nv;
   for (int q = 0; q < nv; ++q) {
-    double s = 0.0;
-    for (int g = l; g < G; g += 64) s += base[(int64_t)g * nv + q];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int g = l;
+    for (; g + 192 < G; g += 256) {
+      s0 += base[(int64_t)g * nv + q];
+      s1 += base[(int64_t)(g + 64) * nv + q];
+      s2 += base[(int64_t)(g + 128) * nv + q];
+      s3 += base[(int64_t)(g + 192) * nv + q];
+    }
+    for (; g < G; g += 64) s0 += base[(int64_t)g * nv + q];
+    double s = (s0 + s1) + (s2 + s3);
     s = wave_sum(s);
     if (l == 0) red[q] = s;
   }
