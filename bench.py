@@ -32,13 +32,13 @@ METRIC = "time to 1e-2 rel. trace error, mixed+batched vs FP64 (s); stencil HBM 
 HBM_PEAK_GBPS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_CLASSES = ("wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong", "gs_dots", "gs_update",
-               "coarse_direct16", "coarse_direct8")
+               "coarse_direct16", "coarse_direct8", "combine")
 STENCIL_CLASSES = ("wilson", "coarse", "sap", "coarse_gs", "restrict", "prolong")
 # source file of each timed kernel class (a recorded HBM traffic figure is only valid for the
 # source it was measured on)
 CLASS_SOURCE = {"wilson": "stencil.hip", "coarse": "stencil.hip", "sap": "stencil.hip", "coarse_gs": "stencil.hip",
                 "restrict": "stencil.hip", "prolong": "stencil.hip", "gs_dots": "gram.hip", "gs_update": "gram.hip",
-                "coarse_direct16": "dense.hip", "coarse_direct8": "dense.hip"}
+                "coarse_direct16": "dense.hip", "coarse_direct8": "dense.hip", "combine": "solver.hip"}
 
 
 def log(msg):

@@ -251,6 +251,8 @@ void launch_combine(dmlmc_ctx* ctx, const Cx<RZ>* Z, int iters, const KrylovArra
   if (ldz <= 0) ldz = n;
   if (ldx <= 0) ldx = n;
   REQUIRE(ldz >= n && ldx >= n, "vector strides below the vector length");
+  KTimer kt(ctx, "combine",
+            (double)nrhs * n * (iters * sizeof(Cx<RZ>) + (accumulate ? 2 : 1) * sizeof(Cx<RX>)));
   hipLaunchKernelGGL((combine_kernel<RZ, RX>), dim3(gridn(n), nrhs), dim3(256), 0, ctx->stream, Z, iters, k.y, k.m, x,
                      n, (int64_t)nrhs * ldz, accumulate ? 1 : 0, ldz, ldx);
   LAUNCH_CHECK();
