@@ -173,10 +173,10 @@ def test_adaptive_loop_hand_computed():
     closed form.  Level 1 draws 10 + (-1)^i, level 2 draws 100 + 3 (-1)^i, so after an
     even number n of samples the means are exactly 10 and 100 and the sample variances
     n/(n-1) and 9 n/(n-1); costs (4, 1); eps |T| = 0.1 with T = 110.
-    Round 1 (n0 = 8): err^2 T^2 = (8/7)/8 + (72/7)/8 = 10/7 > 0.01, so
+    First pass (n0 = 8): err^2 T^2 = (8/7)/8 + (72/7)/8 = 10/7 > 0.01, so
     N_l = ceil(0.01^-1 sqrt(V_l/C_l) (sqrt(V_1 C_1) + sqrt(V_2 C_2))) with V = (8/7, 72/7):
     sqrt(2/7) (sqrt(32/7) + sqrt(72/7)) / 0.01 = 285.7.. -> 286 -> 288 (blocks of 4) and
-    sqrt(72/7) (...) / 0.01 = 1714.2.. -> 1715 -> 1716.  Round 2: 1/287 + 9/1715 <= 0.01,
+    sqrt(72/7) (...) / 0.01 = 1714.2.. -> 1715 -> 1716.  Second pass: 1/287 + 9/1715 <= 0.01,
     stop."""
     calls = []
 
