@@ -99,6 +99,10 @@ def test_recorded_traffic_lookup():
     got, src = b.recorded_traffic("coarse_gs", alg)
     assert got == float(m.group(2)) and src.startswith("hbm_traffic_")
     assert b.recorded_traffic("coarse_gs", alg * 1.02) == (None, None)
+    # every class the benchmark can rank as dominant names the source its digest is taken of
+    for cls in b.HBM_CLASSES:
+        assert os.path.isfile(os.path.join(root, "paper_2211_15383_amd", "csrc", b.CLASS_SOURCE[cls])), cls
+        assert b.recorded_traffic(cls, 1.0) == (None, None)
 
 
 def test_kernel_variant_calls_reject_bad_arguments():
